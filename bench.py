@@ -1,0 +1,173 @@
+"""Throughput of the rank-m spin-charge Krylov kernel update on one MI355X.
+
+One step = one krylov_kernel_apply: m sequential density-matrix responses
+(potentials, forward eigenbasis transform with the Fermi Hadamard product and
+chemical-potential shift, back-transform with the Mulliken projection) plus
+the Krylov orthogonalization and the m x m Gram solve, on a prepared
+1024-atom bcc-Fe system (Nb = 9216, m = 12, FP64). Inputs are resident in
+HBM before the timed region.
+
+Prints one JSON line. The roofline object reports the dominant transform
+kernel: algorithmic flops per launch (2 spins x 2 Nb^3) over its average
+launch time from HIP events recorded by the library on the launch stream.
+The cpu_baseline leg times the plain FP64 oracle on the host for a bounded
+sample of the same workload (one of the m responses of an update).
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FP64_MFMA_PEAK_TFLOPS = 78.6
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--cells", type=int, default=8, help="bcc supercell edge in cells (2 n^3 atoms)")
+    ap.add_argument("--rank", type=int, default=12)
+    ap.add_argument("--seed", type=int, default=1024)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "traffic_fp64_1024.json"))
+    return ap.parse_args()
+
+
+def cpu_baseline(sysd, m):
+    """Oracle timed on the host: one response (one of m directions) at full size."""
+    import numpy as np
+
+    from oracle.expansion import congruence_cholesky, expansion_point
+    from oracle.response import response
+
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count()
+    ep = expansion_point(sysd, Z=congruence_cholesky(sysd["S"]))
+    v = np.random.default_rng(7).standard_normal(2 * sysd["n_atoms"])
+    v /= np.linalg.norm(v)
+    t0 = time.perf_counter()
+    response(sysd, ep, v)
+    dt = time.perf_counter() - t0
+    return {
+        "value": 1.0 / (m * dt),
+        "unit": "updates/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": f"one oracle response (1 of the m={m} Krylov directions of one update, both spins, "
+                  f"{sysd['n_atoms']} atoms) timed once: {dt:.2f} s; value = 1/(m x that time)",
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding of this path is a design note, not built)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2303_03529_amd import krylov
+    from paper_2303_03529_amd.caller_setup import expansion_point_device
+    from synth import make_system
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    t_setup = time.perf_counter()
+    sysd = make_system(args.cells, seed=args.seed)
+    N, nb, m = sysd["n_atoms"], sysd["n_basis"], args.rank
+    e = expansion_point_device(sysd, dev)
+    h = krylov.Handle()
+    h.prepare(sysd["offsets"], e["S"], e["Z"], e["Q_up"], e["Q_dn"], e["eps_up"], e["eps_dn"],
+              e["gamma"], sysd["W"], sysd["kT"], sysd["n_electrons"])
+    del e
+    torch.cuda.empty_cache()
+    delta = torch.as_tensor(sysd["delta"], dtype=torch.float64, device=dev)
+    out = torch.empty_like(delta)
+    setup_s = time.perf_counter() - t_setup
+    print(f"# setup {setup_s:.1f} s (N={N}, Nb={nb}, m={m})", file=sys.stderr, flush=True)
+
+    for _ in range(args.warmup):
+        h.krylov_kernel_apply(delta, m, out=out, info=False)
+    torch.cuda.synchronize()
+    h.profile_enable(True)
+    h.profile_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        h.krylov_kernel_apply(delta, m, out=out, info=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_fwd, n_fwd = h.profile_read(0)
+    ms_back, n_back = h.profile_read(1)
+    h.profile_enable(False)
+    _, info = h.krylov_kernel_apply(delta, m, out=out, info=True)
+    assert info.rank_used == m, info
+
+    elapsed = t1 - t0
+    value = args.steps / elapsed
+    flops_launch = 2 * 2.0 * nb ** 3  # one transform, both spins
+    kernels = {
+        "forward_fermi": (ms_fwd / max(n_fwd, 1), n_fwd),
+        "back_mulliken": (ms_back / max(n_back, 1), n_back),
+    }
+    dom = max(kernels, key=lambda k: kernels[k][0] * kernels[k][1])
+    avg_ms = kernels[dom][0]
+    achieved = flops_launch / (avg_ms * 1e-3) / 1e12
+    traffic = None
+    if os.path.exists(args.traffic_file):
+        tr = json.load(open(args.traffic_file))
+        if tr.get("kernel") == dom and tr.get("n_basis") == nb:
+            traffic = tr.get("bytes_per_launch")
+    roofline = {
+        "bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_MFMA_PEAK_TFLOPS,
+        "unit": "TFLOP/s", "frac": round(achieved / FP64_MFMA_PEAK_TFLOPS, 4), "traffic": traffic,
+        "kernel": dom, "avg_launch_ms": round(avg_ms, 4),
+        "flops_per_launch": flops_launch,
+        "other_kernel_avg_ms": {k: round(v[0], 4) for k, v in kernels.items() if k != dom},
+    }
+    update_flops = 8.0 * m * nb ** 3
+    res = {
+        "metric": "Krylov rank-m kernel updates/sec at 1024-atom Fe",
+        "value": value,
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"bcc Fe {N} atoms ({args.cells}^3 cells), Nb={nb}, rank m={m}, "
+                               "FP64 path, K0=-I",
+                   "n_atoms": N, "n_basis": nb, "rank": m, "seed": args.seed},
+        "update_tflops": update_flops / (elapsed / args.steps) / 1e12,
+        "mfma_util_update": update_flops / (elapsed / args.steps) / 1e12 / FP64_MFMA_PEAK_TFLOPS,
+        "roofline": roofline,
+        "cpu_baseline": None,
+    }
+    h.close()
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(sysd, m)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

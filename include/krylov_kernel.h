@@ -1,0 +1,152 @@
+/*
+ * krylov_kernel.h -- C ABI of the MI355X (gfx950) spin-charge Krylov kernel library.
+ *
+ * Method: Zhang, Cawkwell, Negre, Perriot, Niklasson, "Spin-Polarized Extended
+ * Lagrangian Born-Oppenheimer Molecular Dynamics" (arXiv:2303.03529).
+ *   - Sec. II.G: rank-m preconditioned Krylov approximation of the kernel
+ *     K = J^-1 of the residual f(n) = q[n] - n in the spin-doubled 2N space,
+ *     using directional derivatives f_v = dq[n + lambda v]/dlambda - v.
+ *   - Sec. II.C: Fermi-Dirac density matrix in the orthogonalized basis
+ *     (H-perp = Z^T H Z, Z^T S Z = I) with one chemical potential for N_e.
+ *   - Sec. III.A: spin-polarized SCC-DFTB shadow energy; its derivative gives
+ *     the first-order Hamiltonians H1^sigma = 1/2 (U~ S + S U~) with per-atom
+ *     potentials u^sigma = gamma v_q +/- W v_m, and Mulliken charges/moments.
+ *
+ * Conventions for every entry point:
+ *   - Matrices and vectors are FP64, row-major, contiguous, in DEVICE memory
+ *     owned by the caller (e.g. allocated through PyTorch). The library never
+ *     frees or retains caller pointers past the call; kk_prepare copies or
+ *     derives everything it needs into handle-owned device memory.
+ *   - Vectors of length 2N are ordered (q_1..q_N, m_1..m_N): charge, then
+ *     magnetization (q = n_up + n_dn, m = n_up - n_dn).
+ *   - Work is enqueued asynchronously on the handle's HIP stream; outputs are
+ *     valid once that stream has reached the call. Only calls that return
+ *     host values (kk_get_mu, a non-NULL info, kk_profile_read) synchronize.
+ *   - Errors never cross the ABI as exceptions: each call returns a kk_status
+ *     and kk_last_error() gives a message (thread-local). On error nothing is
+ *     enqueued unless stated otherwise.
+ *   - A handle is not thread-safe; use one handle per stream.
+ */
+#ifndef KRYLOV_KERNEL_H
+#define KRYLOV_KERNEL_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct kk_handle_s *kk_handle;
+
+typedef enum {
+  KK_OK = 0,
+  KK_BREAKDOWN = 1,      /* warning: the Krylov space closed early, rank_used < m */
+  KK_EINVAL = -1,        /* bad argument (NULL pointer, size, offsets, m)          */
+  KK_ENOMEM = -2,        /* device allocation failed                               */
+  KK_EHIP = -3,          /* a HIP runtime call failed                              */
+  KK_ENOTPREPARED = -4,  /* kk_prepare has not succeeded on this handle            */
+  KK_ESINGULAR = -5      /* the m x m Gram matrix O is not positive definite       */
+} kk_status;
+
+typedef enum { KK_FP64 = 0 } kk_precision;
+
+typedef struct {
+  int rank_used;     /* number of Krylov directions actually used (<= m)          */
+  int status;        /* KK_OK, KK_BREAKDOWN or KK_ESINGULAR                        */
+  double min_pivot;  /* smallest Cholesky pivot of O (squared diagonal of L)       */
+  double max_pivot;  /* largest Cholesky pivot of O                                */
+} kk_info;
+
+/* Create a handle bound to hip_stream (a hipStream_t; NULL = the null stream).
+ * Allocates only host state. */
+kk_status kk_create(kk_handle *h, void *hip_stream);
+
+/* Release the handle and every device buffer it owns (synchronizes its stream). */
+kk_status kk_destroy(kk_handle h);
+
+/*
+ * kk_prepare -- expansion-point setup, once per MD step (Sec. II.C).
+ *   n_atoms        N >= 1
+ *   atom_offsets   HOST array of N+1 ints: orbitals of atom I are
+ *                  [atom_offsets[I], atom_offsets[I+1]); offsets[0] = 0,
+ *                  strictly increasing, offsets[N] = n_basis.
+ *   n_basis        Nb >= 1
+ *   S              Nb x Nb overlap matrix (symmetric positive definite)
+ *   Z              Nb x Nb congruence factor with Z^T S Z = I
+ *   Q_up, Q_dn     Nb x Nb orthonormal eigenvectors (columns) of Z^T H^sigma Z
+ *   eps_up, eps_dn Nb eigenvalues matching the columns of Q
+ *   gamma          N x N screened Coulomb matrix (symmetric)
+ *   W              Stoner constant (same energy unit as eps)
+ *   kT             electronic temperature (> 0, energy unit of eps)
+ *   n_electrons    total electron count over both spins, 0 < N_e < 2 Nb
+ *   precision      KK_FP64
+ * The library forms C^sigma = Z Q^sigma, G^sigma = S C^sigma, the occupations
+ * f^sigma and solves the common chemical potential mu on the device. The
+ * call allocates device memory and synchronizes the stream before returning,
+ * so the inputs may be freed afterwards. Re-preparing replaces the old state.
+ */
+kk_status kk_prepare(kk_handle h, int n_atoms, const int *atom_offsets, int n_basis,
+                     const double *S, const double *Z, const double *Q_up, const double *Q_dn,
+                     const double *eps_up, const double *eps_dn, const double *gamma,
+                     double W, double kT, double n_electrons, int precision);
+
+/* Chemical potential found by kk_prepare (synchronizes the stream). */
+kk_status kk_get_mu(kk_handle h, double *mu);
+
+/*
+ * density_response_batch -- first-order spin-charge response (Sec. II.G,
+ * directional derivative; Sec. II.C; Sec. III.A).
+ *   batch >= 1 directions v (batch x 2N, row per direction).
+ *   Writes q1 (batch x 2N): q1(v) = d q[n + lambda v]/d lambda at lambda = 0,
+ *   as (dq, dm). It does not subtract v; J v = q1(v) - v.
+ * q1 must not overlap v.
+ */
+kk_status density_response_batch(kk_handle h, int batch, const double *v, double *q1);
+
+/*
+ * mulliken_project -- Mulliken projection of spin density-matrix changes
+ * (Sec. III.A): dn^sigma_I = sum_{i in I} sum_j dD^sigma_ij S_ji.
+ *   dD_up, dD_dn  batch x Nb x Nb each (symmetric or not)
+ *   dqm           batch x 2N output (dn_up + dn_dn, dn_up - dn_dn)
+ * Uses the S and atom offsets given to kk_prepare.
+ */
+kk_status mulliken_project(kk_handle h, int batch, const double *dD_up, const double *dD_dn,
+                           double *dqm);
+
+/*
+ * krylov_kernel_apply -- rank-m preconditioned Krylov kernel (Sec. II.G):
+ *   Kdelta ~ (K0 J)^-1 K0 delta = sum_{k,l<=m} v_k M_kl f~_{v_l}^T K0 delta,
+ *   M = O^-1, O_kl = f~_{v_k}^T f~_{v_l}, v_k an orthonormal (modified
+ *   Gram-Schmidt, two passes) basis of span{f~, (K0 J) f~, ...}, f~ = K0 delta.
+ *   delta   2N residual f = q[n] - n
+ *   m       1 <= m <= min(2N, 64)
+ *   K0      2N x 2N preconditioner, or NULL for K0 = -I
+ *   Kdelta  2N output (the caller applies -omega^2); must not overlap delta
+ *   info    HOST pointer or NULL; if non-NULL the call synchronizes and fills it.
+ * A direction whose orthogonalized norm drops to <= 1e-13 of its starting norm
+ * ends the expansion; the result then uses rank_used < m directions and the
+ * call returns KK_BREAKDOWN when info is given. delta = 0 gives Kdelta = 0.
+ * If O is not positive definite, Kdelta is set to zero and info->status (and
+ * the return value when info is given) is KK_ESINGULAR.
+ */
+kk_status krylov_kernel_apply(kk_handle h, const double *delta, int m, const double *K0,
+                              double *Kdelta, kk_info *info);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *kk_last_error(void);
+
+/*
+ * Kernel timing for measurement. When enabled, the library records HIP events
+ * on its stream around each launch of its two dense transform kernels
+ * (kernel_id 0: forward eigenbasis transform with the Fermi Hadamard product;
+ * 1: back-transform with the Mulliken projection). kk_profile_read
+ * synchronizes and returns the summed milliseconds and launch count since the
+ * last reset. At most 8192 launches are recorded between resets.
+ */
+kk_status kk_profile_enable(kk_handle h, int enable);
+kk_status kk_profile_reset(kk_handle h);
+kk_status kk_profile_read(kk_handle h, int kernel_id, double *total_ms, int *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KRYLOV_KERNEL_H */

@@ -1,0 +1,519 @@
+// C ABI of the spin-charge Krylov kernel library (declared in include/krylov_kernel.h).
+//
+// Data layout in device memory (np = Nb rounded up to the 128 tile, zero padded):
+//   per spin s: C_s = Z Q_s, CT_s = C_s^T, G_s = S C_s    (np x np each, row-major)
+//               eps_s, f_s, fc_s = 1 - f_s, w_s = beta f fc   (np each)
+//               t_s[I] = sum_{i in I} sum_k C_ik w_k G_ik     (response to a unit mu shift)
+//   S (np x np) for mulliken_project, gamma (N x N), atom offsets (N+1).
+// Per response item (direction b, spin s): u~ (np), Y (np x np), diag X (np),
+// Mulliken partial row sums (2 np/128 x np).
+//
+// One response (Sec. II.G directional derivative) is four launches per batch:
+//   potentials -> gemm<FERMI> (X = 1/2(C^T U~ G + G^T U~ C), Y = F o X) ->
+//   gemm<MULLIKEN> (P = C Y, rows dotted with G) -> combine (mu shift, per-atom
+//   sums, charge/spin mix). The mu shift enters only through t_s, because
+//   C diag(w) C^T S has fixed Mulliken populations.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "krylov_kernel.h"
+#include "kk_gemm.hpp"
+#include "kk_kernels.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+kk_status fail(kk_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIP_OR_FAIL(expr)                                                                  \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) return fail(KK_EHIP, "%s: %s", #expr, hipGetErrorString(e_));   \
+  } while (0)
+
+#define LAUNCH_CHECK(what)                                                                 \
+  do {                                                                                     \
+    hipError_t e_ = hipGetLastError();                                                     \
+    if (e_ != hipSuccess) return fail(KK_EHIP, "launch %s: %s", what, hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr int MAX_CHUNK = kk::MAX_GEMM_BATCH / 2;  // directions per GEMM launch
+constexpr size_t WORKSPACE_BUDGET = size_t(12) << 30;  // bytes of Y workspace per handle
+constexpr int MAX_EVENTS = 8192;
+
+}  // namespace
+
+struct kk_handle_s {
+  hipStream_t stream = nullptr;
+  bool prepared = false;
+  int natoms = 0, nb = 0, np = 0, nparts = 0;
+  double W = 0, kT = 0, beta = 0, n_e = 0;
+  std::vector<void*> owned;  // every device allocation of the prepared state
+
+  double *S = nullptr, *gamma = nullptr;
+  double *C[2] = {nullptr, nullptr}, *CT[2] = {nullptr, nullptr}, *G[2] = {nullptr, nullptr};
+  double *eps[2] = {nullptr, nullptr}, *f[2] = {nullptr, nullptr}, *fc[2] = {nullptr, nullptr},
+         *w[2] = {nullptr, nullptr};
+  double *t = nullptr, *mu = nullptr, *wsum = nullptr;
+  int* offsets = nullptr;
+  int2 *tiles_upper = nullptr, *tiles_full = nullptr;
+  int n_upper = 0, n_full = 0;
+
+  // response workspace (grown on demand)
+  int chunk_cap = 0;
+  double *u = nullptr, *Y = nullptr, *xdiag = nullptr, *part = nullptr;
+  // Krylov workspace
+  double *V = nullptr, *Ft = nullptr, *ftilde = nullptr, *q1 = nullptr;
+  kk::KrylovState* kst = nullptr;
+
+  // kernel timing
+  bool profiling = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, std::pair<int, int>>> ev_used;  // (kernel id, (start ev, end ev))
+  int ev_next = 0;
+
+  std::vector<void*> ws_owned;  // response workspace, replaced when it grows
+
+  void free_workspace() {
+    for (void* p : ws_owned) (void)hipFree(p);
+    ws_owned.clear();
+    chunk_cap = 0;
+    u = Y = xdiag = part = nullptr;
+  }
+
+  void release() {
+    if (owned.empty() && ws_owned.empty()) {
+      prepared = false;
+      return;
+    }
+    (void)hipStreamSynchronize(stream);
+    free_workspace();
+    for (void* p : owned) (void)hipFree(p);
+    owned.clear();
+    prepared = false;
+    V = Ft = ftilde = q1 = nullptr;
+    kst = nullptr;
+  }
+};
+
+namespace {
+
+kk_status dalloc(std::vector<void*>& owner, void** p, size_t bytes) {
+  hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 256));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(KK_ENOMEM, "hipMalloc(%zu bytes): %s", bytes, hipGetErrorString(e));
+  }
+  owner.push_back(*p);
+  return KK_OK;
+}
+
+template <typename T>
+kk_status dalloc_t(kk_handle h, T** p, size_t count, bool workspace = false) {
+  void* q = nullptr;
+  kk_status st = dalloc(workspace ? h->ws_owned : h->owned, &q, count * sizeof(T));
+  *p = static_cast<T*>(q);
+  return st;
+}
+
+// Zero device memory with a plain kernel (no memset nodes if a caller captures).
+__global__ void zero_fill(double* p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+kk_status zero(kk_handle h, double* p, size_t n) {
+  const int blocks = (int)std::min<size_t>((n + 255) / 256, 65536);
+  zero_fill<<<std::max(blocks, 1), 256, 0, h->stream>>>(p, n);
+  LAUNCH_CHECK("zero_fill");
+  return KK_OK;
+}
+
+// Tile orders. Full grid: groups of 8 tile rows, sweep columns inside a group,
+// so the tiles resident on one XCD share A and B panels. Upper triangle: the
+// same grouping restricted to tm <= tn.
+std::vector<int2> tile_order(int T, bool upper) {
+  std::vector<int2> v;
+  const int GROUP = 8;
+  for (int g0 = 0; g0 < T; g0 += GROUP)
+    for (int tn = 0; tn < T; ++tn)
+      for (int tm = g0; tm < std::min(T, g0 + GROUP); ++tm)
+        if (!upper || tm <= tn) v.push_back(make_int2(tm, tn));
+  return v;
+}
+
+struct ProfileScope {
+  kk_handle h;
+  int id;
+  int ev0 = -1;
+  ProfileScope(kk_handle hh, int kid) : h(hh), id(kid) {
+    if (h->profiling && h->ev_next + 2 <= (int)h->ev_pool.size()) {
+      ev0 = h->ev_next;
+      h->ev_next += 2;
+      (void)hipEventRecord(h->ev_pool[ev0], h->stream);
+    }
+  }
+  ~ProfileScope() {
+    if (ev0 >= 0) {
+      (void)hipEventRecord(h->ev_pool[ev0 + 1], h->stream);
+      h->ev_used.push_back({id, {ev0, ev0 + 1}});
+    }
+  }
+};
+
+kk_status launch_gemm(kk_handle h, int epi, kk::GemmArgs& a) {
+  const int grid = a.ntiles * a.nitems;
+  if (grid <= 0) return KK_OK;
+  if (epi == kk::EPI_STORE) {
+    kk::gemm_f64<kk::EPI_STORE><<<grid, kk::NTHREADS, 0, h->stream>>>(a);
+  } else if (epi == kk::EPI_FERMI) {
+    ProfileScope ps(h, 0);
+    kk::gemm_f64<kk::EPI_FERMI><<<grid, kk::NTHREADS, 0, h->stream>>>(a);
+  } else {
+    ProfileScope ps(h, 1);
+    kk::gemm_f64<kk::EPI_MULLIKEN><<<grid, kk::NTHREADS, 0, h->stream>>>(a);
+  }
+  LAUNCH_CHECK("gemm_f64");
+  return KK_OK;
+}
+
+kk_status ensure_workspace(kk_handle h, int chunk) {
+  if (chunk <= h->chunk_cap) return KK_OK;
+  const size_t np = h->np, items = (size_t)2 * chunk;
+  HIP_OR_FAIL(hipStreamSynchronize(h->stream));
+  h->free_workspace();
+  kk_status st;
+  if ((st = dalloc_t(h, &h->u, items * np, true))) return st;
+  if ((st = dalloc_t(h, &h->Y, items * np * np, true))) return st;
+  if ((st = dalloc_t(h, &h->xdiag, items * np, true))) return st;
+  if ((st = dalloc_t(h, &h->part, items * h->nparts * np, true))) return st;
+  if ((st = zero(h, h->u, items * np))) return st;
+  h->chunk_cap = chunk;
+  return KK_OK;
+}
+
+int max_chunk(kk_handle h) {
+  const size_t per_dir = (size_t)2 * h->np * h->np * sizeof(double);
+  size_t c = WORKSPACE_BUDGET / std::max<size_t>(per_dir, 1);
+  return (int)std::max<size_t>(1, std::min<size_t>(c, MAX_CHUNK));
+}
+
+// Responses of `batch` directions v (batch x 2N) into q1 (batch x 2N); batch <= chunk_cap.
+kk_status response_chunk(kk_handle h, int batch, const double* v, double* q1, const int* stop) {
+  const int N = h->natoms, np = h->np;
+  {
+    const int waves = N * batch, threads = 256;
+    const int blocks = (waves * kk::WAVE + threads - 1) / threads;
+    kk::potentials<<<blocks, threads, 0, h->stream>>>(h->gamma, N, h->W, v, batch, h->offsets, np,
+                                                       h->u, stop);
+    LAUNCH_CHECK("potentials");
+  }
+  kk::GemmArgs fa{};
+  fa.n = np; fa.k_half = np; fa.two_halves = 1; fa.ntiles = h->n_upper; fa.nitems = 2 * batch;
+  fa.tiles = h->tiles_upper; fa.stop = stop; fa.beta = h->beta;
+  kk::GemmArgs ba{};
+  ba.n = np; ba.k_half = np; ba.two_halves = 0; ba.ntiles = h->n_full; ba.nitems = 2 * batch;
+  ba.tiles = h->tiles_full; ba.stop = stop; ba.beta = h->beta;
+  for (int b = 0; b < batch; ++b)
+    for (int s = 0; s < 2; ++s) {
+      const int z = 2 * b + s;
+      double* Yz = h->Y + (size_t)z * np * np;
+      kk::GemmItem& fi = fa.item[z];
+      fi.a0 = h->C[s]; fi.b0 = h->G[s]; fi.a1 = h->G[s]; fi.b1 = h->C[s];
+      fi.scale = h->u + (size_t)z * np; fi.out = Yz;
+      fi.eps = h->eps[s]; fi.f = h->f[s]; fi.fc = h->fc[s]; fi.w = h->w[s];
+      fi.xdiag = h->xdiag + (size_t)z * np;
+      kk::GemmItem& bi = ba.item[z];
+      bi.a0 = h->CT[s]; bi.b0 = Yz; bi.g = h->G[s];
+      bi.part = h->part + (size_t)z * h->nparts * np;
+    }
+  kk_status st;
+  if ((st = launch_gemm(h, kk::EPI_FERMI, fa))) return st;
+  if ((st = launch_gemm(h, kk::EPI_MULLIKEN, ba))) return st;
+  {
+    const int threads = 256;
+    dim3 grid((N + threads - 1) / threads, batch);
+    kk::combine<<<grid, threads, 0, h->stream>>>(h->xdiag, h->part, h->nparts, h->w[0], h->w[1],
+                                                  h->wsum, h->t, h->nb, np, h->offsets, N, q1, stop);
+    LAUNCH_CHECK("combine");
+  }
+  return KK_OK;
+}
+
+kk_status check_handle(kk_handle h) {
+  if (!h) return fail(KK_EINVAL, "handle is NULL");
+  if (!h->prepared) return fail(KK_ENOTPREPARED, "kk_prepare has not succeeded on this handle");
+  return KK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* kk_last_error(void) { return g_err.c_str(); }
+
+kk_status kk_create(kk_handle* h, void* hip_stream) {
+  if (!h) return fail(KK_EINVAL, "kk_create: output pointer is NULL");
+  *h = new (std::nothrow) kk_handle_s();
+  if (!*h) return fail(KK_ENOMEM, "kk_create: out of host memory");
+  (*h)->stream = static_cast<hipStream_t>(hip_stream);
+  g_err.clear();
+  return KK_OK;
+}
+
+kk_status kk_destroy(kk_handle h) {
+  if (!h) return fail(KK_EINVAL, "kk_destroy: handle is NULL");
+  h->release();
+  for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+  delete h;
+  return KK_OK;
+}
+
+kk_status kk_prepare(kk_handle h, int n_atoms, const int* atom_offsets, int n_basis, const double* S,
+                     const double* Z, const double* Q_up, const double* Q_dn, const double* eps_up,
+                     const double* eps_dn, const double* gamma, double W, double kT,
+                     double n_electrons, int precision) {
+  if (!h) return fail(KK_EINVAL, "kk_prepare: handle is NULL");
+  if (n_atoms < 1 || n_basis < 1) return fail(KK_EINVAL, "kk_prepare: n_atoms and n_basis must be >= 1");
+  if (2 * n_atoms > 8 * 1024) return fail(KK_EINVAL, "kk_prepare: at most 4096 atoms are supported");
+  if (!atom_offsets || !S || !Z || !Q_up || !Q_dn || !eps_up || !eps_dn || !gamma)
+    return fail(KK_EINVAL, "kk_prepare: NULL array argument");
+  if (!(kT > 0.0)) return fail(KK_EINVAL, "kk_prepare: kT must be > 0");
+  if (!(n_electrons > 0.0 && n_electrons < 2.0 * n_basis))
+    return fail(KK_EINVAL, "kk_prepare: need 0 < n_electrons < 2 n_basis");
+  if (precision != KK_FP64) return fail(KK_EINVAL, "kk_prepare: unsupported precision %d", precision);
+  if (atom_offsets[0] != 0 || atom_offsets[n_atoms] != n_basis)
+    return fail(KK_EINVAL, "kk_prepare: atom_offsets must start at 0 and end at n_basis");
+  for (int a = 0; a < n_atoms; ++a)
+    if (atom_offsets[a + 1] <= atom_offsets[a])
+      return fail(KK_EINVAL, "kk_prepare: atom_offsets must be strictly increasing (atom %d)", a);
+
+  h->release();
+  const int nb = n_basis, np = (nb + kk::TILE - 1) / kk::TILE * kk::TILE;
+  const size_t np2 = (size_t)np * np;
+  h->natoms = n_atoms; h->nb = nb; h->np = np; h->nparts = 2 * (np / kk::TILE);
+  h->W = W; h->kT = kT; h->beta = 1.0 / kT; h->n_e = n_electrons;
+
+  kk_status st;
+  if ((st = dalloc_t(h, &h->S, np2))) return st;
+  for (int s = 0; s < 2; ++s) {
+    if ((st = dalloc_t(h, &h->C[s], np2))) return st;
+    if ((st = dalloc_t(h, &h->CT[s], np2))) return st;
+    if ((st = dalloc_t(h, &h->G[s], np2))) return st;
+    if ((st = dalloc_t(h, &h->eps[s], np))) return st;
+    if ((st = dalloc_t(h, &h->f[s], np))) return st;
+    if ((st = dalloc_t(h, &h->fc[s], np))) return st;
+    if ((st = dalloc_t(h, &h->w[s], np))) return st;
+  }
+  if ((st = dalloc_t(h, &h->gamma, (size_t)n_atoms * n_atoms))) return st;
+  if ((st = dalloc_t(h, &h->t, (size_t)2 * n_atoms))) return st;
+  if ((st = dalloc_t(h, &h->mu, 1))) return st;
+  if ((st = dalloc_t(h, &h->wsum, 1))) return st;
+  if ((st = dalloc_t(h, &h->offsets, (size_t)n_atoms + 1))) return st;
+  const int T = np / kk::TILE;
+  std::vector<int2> up = tile_order(T, true), full = tile_order(T, false);
+  h->n_upper = (int)up.size();
+  h->n_full = (int)full.size();
+  if ((st = dalloc_t(h, &h->tiles_upper, up.size()))) return st;
+  if ((st = dalloc_t(h, &h->tiles_full, full.size()))) return st;
+  const int n2 = 2 * n_atoms;
+  if ((st = dalloc_t(h, &h->V, (size_t)kk::MAX_RANK * n2))) return st;
+  if ((st = dalloc_t(h, &h->Ft, (size_t)kk::MAX_RANK * n2))) return st;
+  if ((st = dalloc_t(h, &h->ftilde, (size_t)n2))) return st;
+  if ((st = dalloc_t(h, &h->q1, (size_t)n2))) return st;
+  if ((st = dalloc_t(h, &h->kst, 1))) return st;
+
+  HIP_OR_FAIL(hipMemcpyAsync(h->offsets, atom_offsets, sizeof(int) * (n_atoms + 1), hipMemcpyHostToDevice,
+                             h->stream));
+  HIP_OR_FAIL(hipMemcpyAsync(h->tiles_upper, up.data(), sizeof(int2) * up.size(), hipMemcpyHostToDevice,
+                             h->stream));
+  HIP_OR_FAIL(hipMemcpyAsync(h->tiles_full, full.data(), sizeof(int2) * full.size(), hipMemcpyHostToDevice,
+                             h->stream));
+  HIP_OR_FAIL(hipMemcpyAsync(h->gamma, gamma, sizeof(double) * n_atoms * n_atoms, hipMemcpyDeviceToDevice,
+                             h->stream));
+
+  // Padded copies: S, Z^T (into CT[0]) and Q_s (into CT[1] as scratch), then
+  // C_s = Z Q_s, G_s = S C_s, CT_s = C_s^T.
+  dim3 pg(np / 32, np / 32), pb(256);
+  kk::pad_copy<<<pg, pb, 0, h->stream>>>(S, nb, h->S, np, 0);
+  LAUNCH_CHECK("pad_copy S");
+  kk::pad_copy<<<pg, pb, 0, h->stream>>>(Z, nb, h->G[0], np, 1);  // G[0] holds Z^T for now
+  LAUNCH_CHECK("pad_copy Z");
+  const double* Qs[2] = {Q_up, Q_dn};
+  for (int s = 0; s < 2; ++s) {
+    kk::pad_copy<<<pg, pb, 0, h->stream>>>(Qs[s], nb, h->CT[s], np, 0);
+    LAUNCH_CHECK("pad_copy Q");
+  }
+  kk::GemmArgs a{};
+  a.n = np; a.k_half = np; a.two_halves = 0; a.ntiles = h->n_full; a.tiles = h->tiles_full;
+  a.stop = nullptr; a.nitems = 2;
+  for (int s = 0; s < 2; ++s) {  // C_s[m][n] = sum_k Z^T[k][m] Q_s[k][n]
+    a.item[s] = kk::GemmItem{};
+    a.item[s].a0 = h->G[0]; a.item[s].b0 = h->CT[s]; a.item[s].out = h->C[s];
+  }
+  if ((st = launch_gemm(h, kk::EPI_STORE, a))) return st;
+  for (int s = 0; s < 2; ++s) {  // G_s[m][n] = sum_k S[k][m] C_s[k][n] (S symmetric)
+    a.item[s] = kk::GemmItem{};
+    a.item[s].a0 = h->S; a.item[s].b0 = h->C[s]; a.item[s].out = h->G[s];
+  }
+  if ((st = launch_gemm(h, kk::EPI_STORE, a))) return st;
+  for (int s = 0; s < 2; ++s) {
+    kk::transpose_sq<<<pg, pb, 0, h->stream>>>(h->C[s], h->CT[s], np);
+    LAUNCH_CHECK("transpose C");
+  }
+  // chemical potential and occupations (eps copied into padded arrays)
+  kk::solve_mu<<<1, 1024, 0, h->stream>>>(eps_up, eps_dn, nb, n_electrons, h->beta, h->mu);
+  LAUNCH_CHECK("solve_mu");
+  const double* es[2] = {eps_up, eps_dn};
+  for (int s = 0; s < 2; ++s) {
+    kk::occupations<<<(np + 255) / 256, 256, 0, h->stream>>>(es[s], nb, np, h->mu, h->beta, h->eps[s],
+                                                              h->f[s], h->fc[s], h->w[s]);
+    LAUNCH_CHECK("occupations");
+  }
+  kk::sum_two<<<1, 1024, 0, h->stream>>>(h->w[0], h->w[1], np, h->wsum);
+  LAUNCH_CHECK("sum_two");
+  kk::atom_row_dots<<<n_atoms, 256, 0, h->stream>>>(h->C[0], h->C[1], np, h->G[0], h->G[1], np, h->w[0],
+                                                     h->w[1], np, h->offsets, n_atoms, h->t);
+  LAUNCH_CHECK("atom_row_dots");
+  HIP_OR_FAIL(hipStreamSynchronize(h->stream));
+  h->prepared = true;
+  g_err.clear();
+  return KK_OK;
+}
+
+kk_status kk_get_mu(kk_handle h, double* mu) {
+  kk_status st = check_handle(h);
+  if (st) return st;
+  if (!mu) return fail(KK_EINVAL, "kk_get_mu: output is NULL");
+  HIP_OR_FAIL(hipMemcpyAsync(mu, h->mu, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIP_OR_FAIL(hipStreamSynchronize(h->stream));
+  return KK_OK;
+}
+
+kk_status density_response_batch(kk_handle h, int batch, const double* v, double* q1) {
+  kk_status st = check_handle(h);
+  if (st) return st;
+  if (batch < 1) return fail(KK_EINVAL, "density_response_batch: batch must be >= 1");
+  if (!v || !q1) return fail(KK_EINVAL, "density_response_batch: NULL array argument");
+  const int chunk = std::min(batch, max_chunk(h));
+  if ((st = ensure_workspace(h, chunk))) return st;
+  const size_t n2 = 2 * (size_t)h->natoms;
+  for (int b0 = 0; b0 < batch; b0 += chunk) {
+    const int nbat = std::min(chunk, batch - b0);
+    if ((st = response_chunk(h, nbat, v + b0 * n2, q1 + b0 * n2, nullptr))) return st;
+  }
+  g_err.clear();
+  return KK_OK;
+}
+
+kk_status mulliken_project(kk_handle h, int batch, const double* dD_up, const double* dD_dn, double* dqm) {
+  kk_status st = check_handle(h);
+  if (st) return st;
+  if (batch < 1) return fail(KK_EINVAL, "mulliken_project: batch must be >= 1");
+  if (!dD_up || !dD_dn || !dqm) return fail(KK_EINVAL, "mulliken_project: NULL array argument");
+  dim3 grid(h->natoms, batch);
+  kk::mulliken_rows<<<grid, 256, 0, h->stream>>>(dD_up, dD_dn, h->nb, h->S, h->np, h->offsets, h->natoms,
+                                                  dqm);
+  LAUNCH_CHECK("mulliken_rows");
+  g_err.clear();
+  return KK_OK;
+}
+
+kk_status krylov_kernel_apply(kk_handle h, const double* delta, int m, const double* K0, double* Kdelta,
+                              kk_info* info) {
+  kk_status st = check_handle(h);
+  if (st) return st;
+  const int n2 = 2 * h->natoms;
+  if (!delta || !Kdelta) return fail(KK_EINVAL, "krylov_kernel_apply: NULL array argument");
+  if (m < 1 || m > std::min(n2, kk::MAX_RANK))
+    return fail(KK_EINVAL, "krylov_kernel_apply: need 1 <= m <= min(2N, %d), got %d", kk::MAX_RANK, m);
+  if ((st = ensure_workspace(h, 1))) return st;
+  const int* stop = &h->kst->stop;
+  const int gv_threads = 256, gv_blocks = (n2 * kk::WAVE + gv_threads - 1) / gv_threads;
+
+  kk::krylov_reset<<<1, 64, 0, h->stream>>>(h->kst);
+  LAUNCH_CHECK("krylov_reset");
+  kk::precondition<<<gv_blocks, gv_threads, 0, h->stream>>>(K0, delta, nullptr, h->ftilde, n2, nullptr);
+  LAUNCH_CHECK("precondition");
+  for (int k = 0; k < m; ++k) {
+    const double* src = (k == 0) ? h->ftilde : h->Ft + (size_t)(k - 1) * n2;
+    kk::krylov_orthonormalize<<<1, 1024, 0, h->stream>>>(src, h->V, n2, h->kst);
+    LAUNCH_CHECK("krylov_orthonormalize");
+    const double* vk = h->V + (size_t)k * n2;
+    if ((st = response_chunk(h, 1, vk, h->q1, stop))) return st;
+    kk::precondition<<<gv_blocks, gv_threads, 0, h->stream>>>(K0, h->q1, vk, h->Ft + (size_t)k * n2, n2,
+                                                               stop);
+    LAUNCH_CHECK("precondition");
+  }
+  kk::krylov_solve<<<1, 1024, 0, h->stream>>>(h->V, h->Ft, h->ftilde, n2, h->kst, Kdelta);
+  LAUNCH_CHECK("krylov_solve");
+  if (info) {
+    kk::KrylovState hs;
+    HIP_OR_FAIL(hipMemcpyAsync(&hs, h->kst, sizeof hs, hipMemcpyDeviceToHost, h->stream));
+    HIP_OR_FAIL(hipStreamSynchronize(h->stream));
+    info->rank_used = hs.rank;
+    info->status = hs.status;
+    info->min_pivot = hs.min_pivot;
+    info->max_pivot = hs.max_pivot;
+    g_err.clear();
+    if (hs.status == KK_ESINGULAR) return fail(KK_ESINGULAR, "krylov_kernel_apply: Gram matrix not positive definite");
+    return hs.status == 1 ? KK_BREAKDOWN : KK_OK;
+  }
+  g_err.clear();
+  return KK_OK;
+}
+
+kk_status kk_profile_enable(kk_handle h, int enable) {
+  if (!h) return fail(KK_EINVAL, "kk_profile_enable: handle is NULL");
+  if (enable && h->ev_pool.empty()) {
+    h->ev_pool.resize(2 * MAX_EVENTS);
+    for (auto& e : h->ev_pool) HIP_OR_FAIL(hipEventCreate(&e));
+  }
+  h->profiling = enable != 0;
+  return KK_OK;
+}
+
+kk_status kk_profile_reset(kk_handle h) {
+  if (!h) return fail(KK_EINVAL, "kk_profile_reset: handle is NULL");
+  HIP_OR_FAIL(hipStreamSynchronize(h->stream));
+  h->ev_used.clear();
+  h->ev_next = 0;
+  return KK_OK;
+}
+
+kk_status kk_profile_read(kk_handle h, int kernel_id, double* total_ms, int* launches) {
+  if (!h) return fail(KK_EINVAL, "kk_profile_read: handle is NULL");
+  if (!total_ms || !launches) return fail(KK_EINVAL, "kk_profile_read: NULL output");
+  HIP_OR_FAIL(hipStreamSynchronize(h->stream));
+  double tot = 0.0;
+  int cnt = 0;
+  for (auto& u : h->ev_used) {
+    if (u.first != kernel_id) continue;
+    float ms = 0.f;
+    HIP_OR_FAIL(hipEventElapsedTime(&ms, h->ev_pool[u.second.first], h->ev_pool[u.second.second]));
+    tot += ms;
+    ++cnt;
+  }
+  *total_ms = tot;
+  *launches = cnt;
+  return KK_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,428 @@
+// Vector, reduction and setup kernels of the spin-charge response and the
+// Krylov loop. All reductions use a fixed order, so results are bitwise
+// reproducible run to run.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace kk {
+
+constexpr int WAVE = 64;
+constexpr double BREAKDOWN_TOL = 1e-13;
+constexpr int MAX_RANK = 64;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// Sum over a block of up to 1024 threads (multiple of 64); every thread gets
+// thread 0's total. sh must hold at least 17 doubles.
+__device__ double block_sum(double v, double* sh) {
+  const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
+  const int nw = blockDim.x / WAVE;
+  v = wave_sum(v);
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  if (wave == 0) {
+    double t = (lane < nw) ? sh[lane] : 0.0;
+    t = wave_sum(t);
+    if (lane == 0) sh[16] = t;
+  }
+  __syncthreads();
+  const double r = sh[16];
+  __syncthreads();
+  return r;
+}
+
+// dst (np x np, zero padded) = src (nb x nb) or its transpose. 32 x 32 tiles.
+__global__ void pad_copy(const double* __restrict__ src, int nb, double* __restrict__ dst, int np,
+                         int transpose) {
+  __shared__ double t[32][33];
+  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8 threads
+  for (int k = ty; k < 32; k += 8) {
+    // read source rows coalesced: source tile origin is (by, bx) if plain, (bx, by) if transposed
+    const int sr = (transpose ? bx : by) + k, sc = (transpose ? by : bx) + tx;
+    t[k][tx] = (sr < nb && sc < nb) ? src[(size_t)sr * nb + sc] : 0.0;
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int dr = by + k, dc = bx + tx;
+    if (dr < np && dc < np) dst[(size_t)dr * np + dc] = transpose ? t[tx][k] : t[k][tx];
+  }
+}
+
+// dst (np x np) = src^T (both np x np).
+__global__ void transpose_sq(const double* __restrict__ src, double* __restrict__ dst, int np) {
+  __shared__ double t[32][33];
+  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int k = ty; k < 32; k += 8) t[k][tx] = src[(size_t)(bx + k) * np + by + tx];
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) dst[(size_t)(by + k) * np + bx + tx] = t[tx][k];
+}
+
+__device__ __forceinline__ double occ(double e, double mu, double beta) {
+  return 1.0 / (1.0 + exp(beta * (e - mu)));
+}
+
+// Sec. II.C: one chemical potential for both spins with sum_sigma sum_k
+// f(eps_k) = N_e. Bisection on [min eps - 40 kT, max eps + 40 kT], then Newton
+// steps with dN/dmu = sum beta f (1 - f). One block of 1024 threads.
+__global__ void __launch_bounds__(1024) solve_mu(const double* __restrict__ e_up,
+                                                 const double* __restrict__ e_dn, int nb,
+                                                 double n_e, double beta, double* mu_out) {
+  __shared__ double sh[17];
+  const double kT = 1.0 / beta;
+  double lo = 1e300, hi = -1e300;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+    lo = fmin(lo, fmin(e_up[i], e_dn[i]));
+    hi = fmax(hi, fmax(e_up[i], e_dn[i]));
+  }
+  // min/max via sums of one-hot is awkward; use LDS reductions directly.
+  __shared__ double smin[1024], smax[1024];
+  smin[threadIdx.x] = lo;
+  smax[threadIdx.x] = hi;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + s]);
+      smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  lo = smin[0] - 40.0 * kT;
+  hi = smax[0] + 40.0 * kT;
+  __syncthreads();
+  for (int iter = 0; iter < 400; ++iter) {
+    const double mid = 0.5 * (lo + hi);
+    double c = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) c += occ(e_up[i], mid, beta) + occ(e_dn[i], mid, beta);
+    c = block_sum(c, sh);
+    if (c < n_e) lo = mid; else hi = mid;
+    if (hi - lo <= 1e-15 * fmax(1.0, fabs(mid))) break;
+  }
+  double mu = 0.5 * (lo + hi);
+  for (int it = 0; it < 3; ++it) {
+    double c = 0.0, d = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+      const double fu = occ(e_up[i], mu, beta), fd = occ(e_dn[i], mu, beta);
+      c += fu + fd;
+      d += fu * occ(-e_up[i], -mu, beta) + fd * occ(-e_dn[i], -mu, beta);
+    }
+    c = block_sum(c, sh);
+    d = block_sum(d, sh) * beta;
+    const double resid = c - n_e;
+    if (d <= 0.0 || fabs(resid) <= 1e-13 * n_e) break;
+    mu -= resid / d;
+  }
+  if (threadIdx.x == 0) *mu_out = mu;
+}
+
+// Occupations of one spin: f = 1/(1+exp(beta(e-mu))), fc = 1 - f (computed as
+// f of the mirrored argument), w = beta f fc; padded entries (i >= nb) are 0.
+__global__ void occupations(const double* __restrict__ eps_in, int nb, int np,
+                            const double* __restrict__ mu_p, double beta, double* __restrict__ eps,
+                            double* __restrict__ f, double* __restrict__ fc, double* __restrict__ w) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  if (i < nb) {
+    const double mu = *mu_p, e = eps_in[i];
+    const double a = occ(e, mu, beta), b = occ(-e, -mu, beta);
+    eps[i] = e; f[i] = a; fc[i] = b; w[i] = beta * a * b;
+  } else {
+    eps[i] = 0.0; f[i] = 0.0; fc[i] = 0.0; w[i] = 0.0;
+  }
+}
+
+// out[s*natoms + I] = sum_{i in I} sum_k X_s[i][k] * Y_s[i][k] * (wk ? wk_s[k] : 1)
+// for s = 0, 1 (two spins). One block per atom.
+__global__ void atom_row_dots(const double* __restrict__ x0, const double* __restrict__ x1, int ldx,
+                              const double* __restrict__ y0, const double* __restrict__ y1, int ldy,
+                              const double* __restrict__ wk0, const double* __restrict__ wk1,
+                              int ncols, const int* __restrict__ offsets, int natoms,
+                              double* __restrict__ out) {
+  __shared__ double sh[17];
+  const int a = blockIdx.x;
+  const int r0 = offsets[a], r1 = offsets[a + 1];
+  for (int s = 0; s < 2; ++s) {
+    const double* x = s ? x1 : x0;
+    const double* y = s ? y1 : y0;
+    const double* wk = s ? wk1 : wk0;
+    double acc = 0.0;
+    for (int i = r0; i < r1; ++i) {
+      const double* xr = x + (size_t)i * ldx;
+      const double* yr = y + (size_t)i * ldy;
+      for (int k = threadIdx.x; k < ncols; k += blockDim.x) {
+        const double p = xr[k] * yr[k];
+        acc += wk ? p * wk[k] : p;
+      }
+    }
+    acc = block_sum(acc, sh);
+    if (threadIdx.x == 0) out[s * natoms + a] = acc;
+  }
+}
+
+// Mulliken projection of caller density-matrix changes (Sec. III.A):
+// dn^s_I = sum_{i in I} sum_j dD^s_ij S_ji, S symmetric so S_ji = S_ij.
+// Output (dq, dm) = (dn_up + dn_dn, dn_up - dn_dn). One block per atom and item.
+__global__ void mulliken_rows(const double* __restrict__ dup, const double* __restrict__ ddn, int nb,
+                              const double* __restrict__ S, int lds, const int* __restrict__ offsets,
+                              int natoms, double* __restrict__ dqm) {
+  __shared__ double sh[17];
+  const int a = blockIdx.x, b = blockIdx.y;
+  const size_t mat = (size_t)nb * nb * b;
+  const int r0 = offsets[a], r1 = offsets[a + 1];
+  double su = 0.0, sd = 0.0;
+  for (int i = r0; i < r1; ++i) {
+    const double* pu = dup + mat + (size_t)i * nb;
+    const double* pd = ddn + mat + (size_t)i * nb;
+    const double* ps = S + (size_t)i * lds;
+    for (int k = threadIdx.x; k < nb; k += blockDim.x) {
+      const double s = ps[k];
+      su += pu[k] * s;
+      sd += pd[k] * s;
+    }
+  }
+  su = block_sum(su, sh);
+  sd = block_sum(sd, sh);
+  if (threadIdx.x == 0) {
+    dqm[(size_t)b * 2 * natoms + a] = su + sd;
+    dqm[(size_t)b * 2 * natoms + natoms + a] = su - sd;
+  }
+}
+
+// Per-orbital spin potentials for a batch of directions (Sec. III.A):
+// u^s_I = sum_J gamma_IJ v_q[J] + sign_s W v_m[I], written to every orbital of
+// atom I in u[(b*2 + s)*np + i]. One wave per (atom, direction).
+__global__ void potentials(const double* __restrict__ gamma, int natoms, double W,
+                           const double* __restrict__ v, int batch, const int* __restrict__ offsets,
+                           int np, double* __restrict__ u, const int* __restrict__ stop) {
+  if (stop != nullptr && *stop != 0) return;
+  const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+  const int lane = threadIdx.x & (WAVE - 1);
+  if (wid >= natoms * batch) return;
+  const int b = wid / natoms, a = wid - b * natoms;
+  const double* vb = v + (size_t)b * 2 * natoms;
+  const double* g = gamma + (size_t)a * natoms;
+  double s = 0.0;
+  for (int j = lane; j < natoms; j += WAVE) s += g[j] * vb[j];
+  s = wave_sum(s);
+  const double up = s + W * vb[natoms + a];
+  const double dn = s - W * vb[natoms + a];
+  for (int i = offsets[a] + lane; i < offsets[a + 1]; i += WAVE) {
+    u[((size_t)b * 2 + 0) * np + i] = up;
+    u[((size_t)b * 2 + 1) * np + i] = dn;
+  }
+}
+
+// Combine the two spins (Sec. II.C, III.A): dmu from the diagonal of X,
+// Mulliken sums per atom, and q1 = (dn_up + dn_dn, dn_up - dn_dn).
+//   xdiag[(b*2+s)*np + i], part[(b*2+s)][p][np], t[s*natoms + I] = sum_{i in I}
+//   sum_k C_ik w_k G_ik (the response to a unit chemical-potential shift),
+//   wsum = sum_s sum_i w_i.
+// Grid: (ceil(natoms / blockDim), batch).
+__global__ void combine(const double* __restrict__ xdiag, const double* __restrict__ part, int nparts,
+                        const double* __restrict__ w_up, const double* __restrict__ w_dn,
+                        const double* __restrict__ wsum_p, const double* __restrict__ t, int nb, int np,
+                        const int* __restrict__ offsets, int natoms, double* __restrict__ q1,
+                        const int* __restrict__ stop) {
+  if (stop != nullptr && *stop != 0) return;
+  __shared__ double sh[17];
+  const int b = blockIdx.y;
+  const double* xu = xdiag + ((size_t)b * 2 + 0) * np;
+  const double* xd = xdiag + ((size_t)b * 2 + 1) * np;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) s += w_up[i] * xu[i] + w_dn[i] * xd[i];
+  s = block_sum(s, sh);
+  const double wsum = *wsum_p;
+  const double dmu = wsum > 0.0 ? s / wsum : 0.0;
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= natoms) return;
+  double dn[2];
+  for (int sp = 0; sp < 2; ++sp) {
+    const double* pp = part + ((size_t)b * 2 + sp) * nparts * np;
+    double acc = 0.0;
+    for (int i = offsets[a]; i < offsets[a + 1]; ++i)
+      for (int p = 0; p < nparts; ++p) acc += pp[(size_t)p * np + i];
+    dn[sp] = acc + dmu * t[sp * natoms + a];
+  }
+  q1[(size_t)b * 2 * natoms + a] = dn[0] + dn[1];
+  q1[(size_t)b * 2 * natoms + natoms + a] = dn[0] - dn[1];
+}
+
+// sum of both spins' w (one block).
+__global__ void sum_two(const double* __restrict__ a, const double* __restrict__ b, int n,
+                        double* __restrict__ out) {
+  __shared__ double sh[17];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s += a[i] + b[i];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) *out = s;
+}
+
+// ---------------------------------------------------------------------------
+// Krylov loop (Sec. II.G)
+
+struct KrylovState {
+  int rank;       // accepted directions
+  int stop;       // 1 after a breakdown (or a zero starting vector)
+  int status;     // 0 ok, 1 breakdown, -5 singular Gram matrix
+  int pad;
+  double min_pivot, max_pivot;
+};
+
+__global__ void krylov_reset(KrylovState* st) {
+  if (threadIdx.x == 0) {
+    st->rank = 0; st->stop = 0; st->status = 0; st->pad = 0;
+    st->min_pivot = 0.0; st->max_pivot = 0.0;
+  }
+}
+
+// y = K0 (x - sub) (sub may be null), or -(x - sub) when K0 is null.
+// One wave per row. Skipped after a breakdown when stop is given.
+__global__ void precondition(const double* __restrict__ K0, const double* __restrict__ x,
+                             const double* __restrict__ sub, double* __restrict__ y, int n2,
+                             const int* __restrict__ stop) {
+  if (stop != nullptr && *stop != 0) return;
+  const int row = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+  const int lane = threadIdx.x & (WAVE - 1);
+  if (row >= n2) return;
+  if (K0 == nullptr) {
+    if (lane == 0) y[row] = -(x[row] - (sub ? sub[row] : 0.0));
+    return;
+  }
+  const double* kr = K0 + (size_t)row * n2;
+  double s = 0.0;
+  for (int j = lane; j < n2; j += WAVE) s += kr[j] * (x[j] - (sub ? sub[j] : 0.0));
+  s = wave_sum(s);
+  if (lane == 0) y[row] = s;
+}
+
+// Orthogonalize src against the accepted directions V[0..rank) with modified
+// Gram-Schmidt, two passes; accept it as V[rank] if its norm kept more than
+// BREAKDOWN_TOL of its starting norm, else stop the expansion. One block.
+__global__ void __launch_bounds__(1024) krylov_orthonormalize(const double* __restrict__ src,
+                                                              double* __restrict__ V, int n2,
+                                                              KrylovState* st) {
+  __shared__ double sh[17];
+  if (st->stop) return;
+  const int rank = st->rank;
+  constexpr int PER = 8;  // n2 <= 8 * 1024
+  double w[PER];
+  double nn = 0.0;
+#pragma unroll
+  for (int e = 0; e < PER; ++e) {
+    const int i = threadIdx.x + e * blockDim.x;
+    w[e] = i < n2 ? src[i] : 0.0;
+    nn += w[e] * w[e];
+  }
+  const double start = sqrt(block_sum(nn, sh));
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int j = 0; j < rank; ++j) {
+      const double* vj = V + (size_t)j * n2;
+      double d = 0.0;
+#pragma unroll
+      for (int e = 0; e < PER; ++e) {
+        const int i = threadIdx.x + e * blockDim.x;
+        if (i < n2) d += vj[i] * w[e];
+      }
+      d = block_sum(d, sh);
+#pragma unroll
+      for (int e = 0; e < PER; ++e) {
+        const int i = threadIdx.x + e * blockDim.x;
+        if (i < n2) w[e] -= d * vj[i];
+      }
+    }
+  }
+  nn = 0.0;
+#pragma unroll
+  for (int e = 0; e < PER; ++e) nn += w[e] * w[e];
+  const double nrm = sqrt(block_sum(nn, sh));
+  if (!(nrm > BREAKDOWN_TOL * start) || rank >= MAX_RANK) {
+    if (threadIdx.x == 0) {
+      st->stop = 1;
+      if (rank > 0) st->status = 1;
+    }
+    return;
+  }
+  double* vr = V + (size_t)rank * n2;
+#pragma unroll
+  for (int e = 0; e < PER; ++e) {
+    const int i = threadIdx.x + e * blockDim.x;
+    if (i < n2) vr[i] = w[e] / nrm;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) st->rank = rank + 1;
+}
+
+// O = F~^T F~, rhs = F~^T f~, Cholesky O = L L^T, c = O^-1 rhs, x = V c.
+// On a non-positive pivot x = 0 and status = -5. One block.
+__global__ void __launch_bounds__(1024) krylov_solve(const double* __restrict__ V,
+                                                     const double* __restrict__ Ft,
+                                                     const double* __restrict__ ftilde, int n2,
+                                                     KrylovState* st, double* __restrict__ x) {
+  __shared__ double sh[17];
+  __shared__ double O[MAX_RANK][MAX_RANK + 1];
+  __shared__ double c[MAX_RANK];
+  __shared__ int ok;
+  const int r = st->rank;
+  for (int a = 0; a < r; ++a) {
+    for (int b = 0; b <= a; ++b) {
+      double d = 0.0;
+      for (int i = threadIdx.x; i < n2; i += blockDim.x) d += Ft[(size_t)a * n2 + i] * Ft[(size_t)b * n2 + i];
+      d = block_sum(d, sh);
+      if (threadIdx.x == 0) { O[a][b] = d; O[b][a] = d; }
+    }
+    double d = 0.0;
+    for (int i = threadIdx.x; i < n2; i += blockDim.x) d += Ft[(size_t)a * n2 + i] * ftilde[i];
+    d = block_sum(d, sh);
+    if (threadIdx.x == 0) c[a] = d;
+  }
+  if (threadIdx.x == 0) {
+    ok = 1;
+    double pmin = 0.0, pmax = 0.0;
+    // in-place Cholesky: lower triangle of O holds L
+    for (int j = 0; j < r && ok; ++j) {
+      double dj = O[j][j];
+      for (int k = 0; k < j; ++k) dj -= O[j][k] * O[j][k];
+      if (!(dj > 0.0)) { ok = 0; break; }
+      pmin = (j == 0) ? dj : fmin(pmin, dj);
+      pmax = (j == 0) ? dj : fmax(pmax, dj);
+      const double ljj = sqrt(dj);
+      O[j][j] = ljj;
+      for (int i = j + 1; i < r; ++i) {
+        double s = O[i][j];
+        for (int k = 0; k < j; ++k) s -= O[i][k] * O[j][k];
+        O[i][j] = s / ljj;
+      }
+    }
+    if (ok) {
+      for (int i = 0; i < r; ++i) {  // L y = rhs
+        double s = c[i];
+        for (int k = 0; k < i; ++k) s -= O[i][k] * c[k];
+        c[i] = s / O[i][i];
+      }
+      for (int i = r - 1; i >= 0; --i) {  // L^T c = y
+        double s = c[i];
+        for (int k = i + 1; k < r; ++k) s -= O[k][i] * c[k];
+        c[i] = s / O[i][i];
+      }
+    } else {
+      st->status = -5;
+    }
+    st->min_pivot = pmin;
+    st->max_pivot = pmax;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n2; i += blockDim.x) {
+    double s = 0.0;
+    if (ok)
+      for (int k = 0; k < r; ++k) s += c[k] * V[(size_t)k * n2 + i];
+    x[i] = s;
+  }
+}
+
+}  // namespace kk

@@ -1,0 +1,188 @@
+"""Thin Python binding of libkrylov_kernel.so (C ABI in include/krylov_kernel.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library. Tensors must be float64, contiguous, on a ROCm device; the handle's
+stream is the current torch stream at creation unless one is given.
+If the library is missing this module raises at import time instead of
+falling back to anything else.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+PKG_DIR = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG_DIR, "libkrylov_kernel.so")
+
+KK_OK, KK_BREAKDOWN = 0, 1
+KK_EINVAL, KK_ENOMEM, KK_EHIP, KK_ENOTPREPARED, KK_ESINGULAR = -1, -2, -3, -4, -5
+KK_FP64 = 0
+STATUS_NAMES = {0: "KK_OK", 1: "KK_BREAKDOWN", -1: "KK_EINVAL", -2: "KK_ENOMEM", -3: "KK_EHIP",
+                -4: "KK_ENOTPREPARED", -5: "KK_ESINGULAR"}
+
+# Every function the header declares, with (restype, argtypes).
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_D = ctypes.c_double
+SIGNATURES = {
+    "kk_create": (_I, [ctypes.POINTER(_P), _P]),
+    "kk_destroy": (_I, [_P]),
+    "kk_prepare": (_I, [_P, _I, _P, _I, _P, _P, _P, _P, _P, _P, _P, _D, _D, _D, _I]),
+    "kk_get_mu": (_I, [_P, ctypes.POINTER(_D)]),
+    "density_response_batch": (_I, [_P, _I, _P, _P]),
+    "mulliken_project": (_I, [_P, _I, _P, _P, _P]),
+    "krylov_kernel_apply": (_I, [_P, _P, _I, _P, _P, _P]),
+    "kk_last_error": (ctypes.c_char_p, []),
+    "kk_profile_enable": (_I, [_P, _I]),
+    "kk_profile_reset": (_I, [_P]),
+    "kk_profile_read": (_I, [_P, _I, ctypes.POINTER(_D), ctypes.POINTER(_I)]),
+}
+
+
+class KKInfo(ctypes.Structure):
+    _fields_ = [("rank_used", _I), ("status", _I), ("min_pivot", _D), ("max_pivot", _D)]
+
+
+class KKError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"HIP library {path} is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+LIB = load_library()
+
+
+def last_error() -> str:
+    return LIB.kk_last_error().decode()
+
+
+def _check(status: int, where: str, ok=(KK_OK,)) -> int:
+    if status not in ok:
+        raise KKError(status, where, last_error())
+    return status
+
+
+def _dev(t, name: str, numel: int | None = None):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda" or t.dtype != torch.float64 or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float64 tensor on the GPU")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+@dataclass
+class KrylovInfo:
+    rank_used: int
+    status: int
+    min_pivot: float
+    max_pivot: float
+
+
+class Handle:
+    """One library handle bound to one HIP stream."""
+
+    def __init__(self, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        self._h = ctypes.c_void_p()
+        _check(LIB.kk_create(ctypes.byref(self._h), ctypes.c_void_p(stream.cuda_stream)), "kk_create")
+        self.n_atoms = None
+        self.n_basis = None
+
+    def close(self):
+        if self._h:
+            _check(LIB.kk_destroy(self._h), "kk_destroy")
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def prepare(self, offsets, S, Z, Q_up, Q_dn, eps_up, eps_dn, gamma, W: float, kT: float,
+                n_electrons: float):
+        off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int32))
+        n, nb = len(off) - 1, int(off[-1])
+        _check(LIB.kk_prepare(
+            self._h, n, off.ctypes.data_as(ctypes.c_void_p), nb,
+            _dev(S, "S", nb * nb), _dev(Z, "Z", nb * nb), _dev(Q_up, "Q_up", nb * nb),
+            _dev(Q_dn, "Q_dn", nb * nb), _dev(eps_up, "eps_up", nb), _dev(eps_dn, "eps_dn", nb),
+            _dev(gamma, "gamma", n * n), float(W), float(kT), float(n_electrons), KK_FP64),
+            "kk_prepare")
+        self.n_atoms, self.n_basis = n, nb
+        return self
+
+    @property
+    def mu(self) -> float:
+        out = ctypes.c_double()
+        _check(LIB.kk_get_mu(self._h, ctypes.byref(out)), "kk_get_mu")
+        return out.value
+
+    def density_response_batch(self, v, out=None):
+        import torch
+        v2 = v.reshape(-1, 2 * self.n_atoms)
+        if out is None:
+            out = torch.empty_like(v2)
+        _check(LIB.density_response_batch(self._h, v2.shape[0], _dev(v2, "v"),
+                                          _dev(out, "q1", v2.numel())), "density_response_batch")
+        return out
+
+    def mulliken_project(self, dD_up, dD_dn, out=None):
+        import torch
+        nb = self.n_basis
+        batch = dD_up.numel() // (nb * nb)
+        if out is None:
+            out = torch.empty(batch, 2 * self.n_atoms, dtype=torch.float64, device=dD_up.device)
+        _check(LIB.mulliken_project(self._h, batch, _dev(dD_up, "dD_up", batch * nb * nb),
+                                    _dev(dD_dn, "dD_dn", batch * nb * nb),
+                                    _dev(out, "dqm", batch * 2 * self.n_atoms)), "mulliken_project")
+        return out
+
+    def krylov_kernel_apply(self, delta, m: int, K0=None, out=None, info: bool = True):
+        """K delta; returns (out, KrylovInfo or None). info=True synchronizes."""
+        import torch
+        n2 = 2 * self.n_atoms
+        if out is None:
+            out = torch.empty(n2, dtype=torch.float64, device=delta.device)
+        k0p = _dev(K0, "K0", n2 * n2) if K0 is not None else ctypes.c_void_p()
+        if info:
+            inf = KKInfo()
+            _check(LIB.krylov_kernel_apply(self._h, _dev(delta, "delta", n2), int(m), k0p,
+                                           _dev(out, "Kdelta", n2), ctypes.byref(inf)),
+                   "krylov_kernel_apply", ok=(KK_OK, KK_BREAKDOWN, KK_ESINGULAR))
+            return out, KrylovInfo(inf.rank_used, inf.status, inf.min_pivot, inf.max_pivot)
+        _check(LIB.krylov_kernel_apply(self._h, _dev(delta, "delta", n2), int(m), k0p,
+                                       _dev(out, "Kdelta", n2), None), "krylov_kernel_apply")
+        return out, None
+
+    def profile_enable(self, on: bool = True):
+        _check(LIB.kk_profile_enable(self._h, 1 if on else 0), "kk_profile_enable")
+
+    def profile_reset(self):
+        _check(LIB.kk_profile_reset(self._h), "kk_profile_reset")
+
+    def profile_read(self, kernel_id: int):
+        ms, cnt = ctypes.c_double(), ctypes.c_int()
+        _check(LIB.kk_profile_read(self._h, kernel_id, ctypes.byref(ms), ctypes.byref(cnt)), "kk_profile_read")
+        return ms.value, cnt.value

@@ -1,0 +1,164 @@
+"""Parity of the HIP path with the FP64 oracle, element by element, on
+identical prepared inputs (same Z, Q, eps handed to both).
+
+Tolerance: 1e-10 relative (2-norm) for every FP64 output, the bound the
+FP64 path is held to. Expected agreement is ~1e-14 x cond(O) for the kernel.
+"""
+
+import numpy as np
+import pytest
+
+from tests.gpu_helpers import handle_from_expansion, rel, t
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import oracle  # noqa: E402
+from oracle.expansion import expansion_point  # noqa: E402
+from oracle.krylov import jacobian_exact, kernel_apply  # noqa: E402
+from oracle.response import response  # noqa: E402
+from synth import make_system  # noqa: E402
+
+
+def _case(n_cells=None, n_atoms=None, seed=0, **kw):
+    sysd = make_system(n_cells, n_atoms=n_atoms, seed=seed, **kw)
+    ep = expansion_point(sysd)
+    return sysd, ep, handle_from_expansion(sysd, ep)
+
+
+@pytest.fixture(scope="module")
+def fe16():
+    return _case(2, seed=16)
+
+
+@pytest.fixture(scope="module")
+def fe128():
+    return _case(4, seed=128)
+
+
+def test_mu_matches_oracle(fe16):
+    sysd, ep, h = fe16
+    assert abs(h.mu - ep["mu"]) <= 1e-12 * abs(ep["mu"])
+
+
+def test_response_fe16_batch(fe16):
+    sysd, ep, h = fe16
+    N = sysd["n_atoms"]
+    V = np.random.default_rng(1).standard_normal((11, 2 * N))  # > one launch chunk
+    got = h.density_response_batch(t(V)).cpu().numpy()
+    for b in range(V.shape[0]):
+        assert rel(got[b], response(sysd, ep, V[b])) < TOL, b
+
+
+def test_response_fe128(fe128):
+    sysd, ep, h = fe128
+    N = sysd["n_atoms"]
+    V = np.random.default_rng(2).standard_normal((2, 2 * N))
+    got = h.density_response_batch(t(V)).cpu().numpy()
+    for b in range(2):
+        assert rel(got[b], response(sysd, ep, V[b])) < TOL
+
+
+def test_response_is_deterministic(fe128):
+    sysd, ep, h = fe128
+    v = t(np.random.default_rng(3).standard_normal(2 * sysd["n_atoms"]))
+    a = h.density_response_batch(v).cpu().numpy()
+    b = h.density_response_batch(v).cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("n_atoms", [17, 37, 131])
+def test_response_ragged_clusters(n_atoms):
+    """Open clusters: Nb = 9N not a multiple of the tile (padding path)."""
+    sysd, ep, h = _case(n_atoms=n_atoms, seed=10_000 + n_atoms)
+    v = np.random.default_rng(n_atoms).standard_normal(2 * n_atoms)
+    got = h.density_response_batch(t(v)).cpu().numpy()[0]
+    assert rel(got, response(sysd, ep, v)) < TOL
+
+
+def test_response_exact_degeneracies():
+    """S = I, diagonal H with repeated levels: ties take the phi(0) = 1 branch."""
+    N, per = 6, 9
+    nb = N * per
+    onsite = np.tile([-4.0, 2.0, 2.0, 2.0, -8.5, -8.5, -8.5, -8.5, -8.5], N)
+    g = np.random.default_rng(4).normal(size=(N, N))
+    sysd = dict(H0=np.diag(onsite), S=np.eye(nb), gamma=g @ g.T / N + np.eye(N), W=-0.4,
+                kT=0.25, n_electrons=8.0 * N, offsets=np.arange(0, nb + 1, per, dtype=np.int32),
+                n_ref=np.zeros(2 * N), n_atoms=N)
+    ep = expansion_point(sysd)
+    h = handle_from_expansion(sysd, ep)
+    v = np.random.default_rng(5).standard_normal(2 * N)
+    got = h.density_response_batch(t(v)).cpu().numpy()[0]
+    assert rel(got, response(sysd, ep, v)) < TOL
+
+
+def test_kernel_fe16(fe16):
+    sysd, ep, h = fe16
+    got, info = h.krylov_kernel_apply(t(sysd["delta"]), 4)
+    ref, parts = kernel_apply(sysd, ep, sysd["delta"], 4, return_parts=True)
+    assert info.rank_used == parts["rank"] == 4
+    assert info.status == 0
+    assert rel(got.cpu().numpy(), ref) < TOL
+
+
+def test_kernel_fe16_dense_preconditioner(fe16):
+    sysd, ep, h = fe16
+    n2 = 2 * sysd["n_atoms"]
+    K0 = -np.eye(n2) + 0.05 * np.random.default_rng(13).standard_normal((n2, n2))
+    got, info = h.krylov_kernel_apply(t(sysd["delta"]), 5, K0=t(K0))
+    ref = kernel_apply(sysd, ep, sysd["delta"], 5, K0)
+    assert rel(got.cpu().numpy(), ref) < TOL
+
+
+def test_kernel_fe128(fe128):
+    sysd, ep, h = fe128
+    got, info = h.krylov_kernel_apply(t(sysd["delta"]), 8)
+    ref = kernel_apply(sysd, ep, sysd["delta"], 8)
+    assert info.rank_used == 8
+    assert rel(got.cpu().numpy(), ref) < TOL
+
+
+def test_kernel_full_rank_is_inverse_jacobian(fe16):
+    sysd, ep, h = fe16
+    n2 = 2 * sysd["n_atoms"]
+    got, info = h.krylov_kernel_apply(t(sysd["delta"]), n2)
+    assert info.rank_used == n2
+    exact = np.linalg.solve(jacobian_exact(sysd, ep), sysd["delta"])
+    assert rel(got.cpu().numpy(), exact) < TOL
+
+
+def test_kernel_breakdown_and_zero(fe16):
+    sysd, ep, h = fe16
+    from paper_2303_03529_amd import krylov
+    J = jacobian_exact(sysd, ep)
+    lam, vecs = np.linalg.eig(J)
+    k = int(np.argmin(np.abs(lam.imag) + (np.abs(lam.imag) > 0) * 1e9))
+    x = vecs[:, k].real
+    got, info = h.krylov_kernel_apply(t(x), 4)
+    assert info.rank_used == 1 and info.status == krylov.KK_BREAKDOWN
+    assert rel(got.cpu().numpy(), x / lam[k].real) < 1e-9
+    z, info = h.krylov_kernel_apply(t(np.zeros(2 * sysd["n_atoms"])), 4)
+    assert info.rank_used == 0 and not torch.any(z)
+
+
+def test_mulliken_project(fe16):
+    sysd, ep, h = fe16
+    nb = sysd["n_basis"]
+    rng = np.random.default_rng(6)
+    A, B = rng.standard_normal((2, 3, nb, nb))
+    got = h.mulliken_project(t(A), t(B)).cpu().numpy()
+    for b in range(3):
+        assert rel(got[b], oracle.mulliken(A[b], B[b], sysd["S"], sysd["offsets"])) < TOL
+
+
+def test_invalid_m_is_rejected(fe16):
+    sysd, ep, h = fe16
+    from paper_2303_03529_amd import krylov
+    with pytest.raises(krylov.KKError) as e:
+        h.krylov_kernel_apply(t(sysd["delta"]), 0)
+    assert e.value.status == krylov.KK_EINVAL

@@ -46,7 +46,17 @@ typedef enum {
   KK_ESINGULAR = -5      /* the m x m Gram matrix O is not positive definite       */
 } kk_status;
 
-typedef enum { KK_FP64 = 0 } kk_precision;
+/*
+ * Arithmetic of the two dense transforms of each response.
+ *   KK_FP64       everything in FP64 (FP64 MFMA).
+ *   KK_MIXED_F16  the two transforms as three FP16 MFMA products of hi/lo
+ *                 splits (~22 significant bits per operand, FP32 accumulation);
+ *                 the Fermi divided differences, the chemical-potential shift,
+ *                 the Mulliken sums and the Krylov m x m solve stay FP64.
+ *                 Responses and kernel results agree with FP64 to ~1e-7
+ *                 relative on the bcc-Fe workloads (not a guaranteed bound).
+ */
+typedef enum { KK_FP64 = 0, KK_MIXED_F16 = 1 } kk_precision;
 
 typedef struct {
   int rank_used;     /* number of Krylov directions actually used (<= m)          */
@@ -77,7 +87,7 @@ kk_status kk_destroy(kk_handle h);
  *   W              Stoner constant (same energy unit as eps)
  *   kT             electronic temperature (> 0, energy unit of eps)
  *   n_electrons    total electron count over both spins, 0 < N_e < 2 Nb
- *   precision      KK_FP64
+ *   precision      KK_FP64 or KK_MIXED_F16 (see kk_precision)
  * The library forms C^sigma = Z Q^sigma, G^sigma = S C^sigma, the occupations
  * f^sigma and solves the common chemical potential mu on the device. The
  * call allocates device memory and synchronizes the stream before returning,

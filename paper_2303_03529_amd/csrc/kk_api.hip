@@ -6,7 +6,7 @@
 //               t_s[I] = sum_{i in I} sum_k C_ik w_k G_ik     (response to a unit mu shift)
 //   S (np x np) for mulliken_project, gamma (N x N), atom offsets (N+1).
 // Per response item (direction b, spin s): u~ (np), Y (np x np), diag X (np),
-// Mulliken partial row sums (2 np/128 x np).
+// Mulliken partial row sums (one row of np per wave column of each tile column).
 //
 // One response (Sec. II.G directional derivative) is four launches per batch:
 //   potentials -> gemm<FERMI> (X = 1/2(C^T U~ G + G^T U~ C), Y = F o X) ->
@@ -26,6 +26,7 @@
 #include "krylov_kernel.h"
 #include "kk_gemm.hpp"
 #include "kk_kernels.hpp"
+#include "kk_gemm_mixed.hpp"
 
 namespace {
 
@@ -72,8 +73,21 @@ struct kk_handle_s {
          *w[2] = {nullptr, nullptr};
   double *t = nullptr, *mu = nullptr, *wsum = nullptr;
   int* offsets = nullptr;
-  int2 *tiles_upper = nullptr, *tiles_full = nullptr;
-  int n_upper = 0, n_full = 0;
+  int2 *tiles_upper = nullptr, *tiles_full = nullptr, *tiles_store = nullptr;
+  int n_upper = 0, n_full = 0, n_store = 0;
+
+  // split-precision state (precision == KK_MIXED_F16)
+  int precision = KK_FP64;
+  double* GT[2] = {nullptr, nullptr};
+  _Float16 *Ch[2] = {nullptr, nullptr}, *Cl[2] = {nullptr, nullptr};
+  _Float16 *CTh[2] = {nullptr, nullptr}, *CTl[2] = {nullptr, nullptr};
+  _Float16 *GTh[2] = {nullptr, nullptr}, *GTl[2] = {nullptr, nullptr};
+  double* mconst = nullptr;  // per spin: s_C, s_G, max column norms of C and G
+  int2 *mtiles_upper = nullptr, *mtiles_full = nullptr;
+  int n_mupper = 0, n_mfull = 0;
+  _Float16 *uct_h = nullptr, *uct_l = nullptr, *ugt_h = nullptr, *ugt_l = nullptr;
+  _Float16 *yh = nullptr, *yl = nullptr;
+  double* msc = nullptr;
 
   // response workspace (grown on demand)
   int chunk_cap = 0;
@@ -95,6 +109,8 @@ struct kk_handle_s {
     ws_owned.clear();
     chunk_cap = 0;
     u = Y = xdiag = part = nullptr;
+    uct_h = uct_l = ugt_h = ugt_l = yh = yl = nullptr;
+    msc = nullptr;
   }
 
   void release() {
@@ -147,15 +163,16 @@ kk_status zero(kk_handle h, double* p, size_t n) {
 }
 
 // Tile orders. Full grid: groups of 8 tile rows, sweep columns inside a group,
-// so the tiles resident on one XCD share A and B panels. Upper triangle: the
-// same grouping restricted to tm <= tn.
-std::vector<int2> tile_order(int T, bool upper) {
+// so the tiles resident on one XCD share A and B panels. Upper: the same
+// order restricted to tiles holding at least one element with m <= n.
+std::vector<int2> tile_order(int np, int bm, int bn, bool upper) {
   std::vector<int2> v;
+  const int TM = np / bm, TN = np / bn;
   const int GROUP = 8;
-  for (int g0 = 0; g0 < T; g0 += GROUP)
-    for (int tn = 0; tn < T; ++tn)
-      for (int tm = g0; tm < std::min(T, g0 + GROUP); ++tm)
-        if (!upper || tm <= tn) v.push_back(make_int2(tm, tn));
+  for (int g0 = 0; g0 < TM; g0 += GROUP)
+    for (int tn = 0; tn < TN; ++tn)
+      for (int tm = g0; tm < std::min(TM, g0 + GROUP); ++tm)
+        if (!upper || tm * bm <= tn * bn + bn - 1) v.push_back(make_int2(tm, tn));
   return v;
 }
 
@@ -181,14 +198,15 @@ struct ProfileScope {
 kk_status launch_gemm(kk_handle h, int epi, kk::GemmArgs& a) {
   const int grid = a.ntiles * a.nitems;
   if (grid <= 0) return KK_OK;
+  if (a.nitems > kk::MAX_GEMM_BATCH) return fail(KK_EINVAL, "internal: too many GEMM items");
   if (epi == kk::EPI_STORE) {
-    kk::gemm_f64<kk::EPI_STORE><<<grid, kk::NTHREADS, 0, h->stream>>>(a);
+    kk::gemm_f64<kk::EPI_STORE, kk::StoreCfg><<<grid, kk::StoreCfg::THREADS, 0, h->stream>>>(a);
   } else if (epi == kk::EPI_FERMI) {
     ProfileScope ps(h, 0);
-    kk::gemm_f64<kk::EPI_FERMI><<<grid, kk::NTHREADS, 0, h->stream>>>(a);
+    kk::gemm_f64<kk::EPI_FERMI, kk::FwdCfg><<<grid, kk::FwdCfg::THREADS, 0, h->stream>>>(a);
   } else {
     ProfileScope ps(h, 1);
-    kk::gemm_f64<kk::EPI_MULLIKEN><<<grid, kk::NTHREADS, 0, h->stream>>>(a);
+    kk::gemm_f64<kk::EPI_MULLIKEN, kk::BackCfg><<<grid, kk::BackCfg::THREADS, 0, h->stream>>>(a);
   }
   LAUNCH_CHECK("gemm_f64");
   return KK_OK;
@@ -201,7 +219,13 @@ kk_status ensure_workspace(kk_handle h, int chunk) {
   h->free_workspace();
   kk_status st;
   if ((st = dalloc_t(h, &h->u, items * np, true))) return st;
-  if ((st = dalloc_t(h, &h->Y, items * np * np, true))) return st;
+  if (h->precision == KK_FP64) {
+    if ((st = dalloc_t(h, &h->Y, items * np * np, true))) return st;
+  } else {
+    for (_Float16** q : {&h->uct_h, &h->uct_l, &h->ugt_h, &h->ugt_l, &h->yh, &h->yl})
+      if ((st = dalloc_t(h, q, items * np * np, true))) return st;
+    if ((st = dalloc_t(h, &h->msc, items * 8, true))) return st;
+  }
   if ((st = dalloc_t(h, &h->xdiag, items * np, true))) return st;
   if ((st = dalloc_t(h, &h->part, items * h->nparts * np, true))) return st;
   if ((st = zero(h, h->u, items * np))) return st;
@@ -210,7 +234,8 @@ kk_status ensure_workspace(kk_handle h, int chunk) {
 }
 
 int max_chunk(kk_handle h) {
-  const size_t per_dir = (size_t)2 * h->np * h->np * sizeof(double);
+  // FP64: one Y per spin; split path: six FP16 matrices per spin
+  const size_t per_dir = (size_t)2 * h->np * h->np * (h->precision == KK_FP64 ? sizeof(double) : 6 * sizeof(_Float16));
   size_t c = WORKSPACE_BUDGET / std::max<size_t>(per_dir, 1);
   return (int)std::max<size_t>(1, std::min<size_t>(c, MAX_CHUNK));
 }
@@ -257,9 +282,133 @@ kk_status response_chunk(kk_handle h, int batch, const double* v, double* q1, co
   return KK_OK;
 }
 
+kk_status launch_mixed(kk_handle h, int epi, kk::MixedArgs& a) {
+  const int grid = a.ntiles * a.nitems;
+  if (grid <= 0) return KK_OK;
+  if (a.nitems > kk::MAX_GEMM_BATCH) return fail(KK_EINVAL, "internal: too many GEMM items");
+  if (epi == kk::EPI_FERMI) {
+    ProfileScope ps(h, 0);
+    kk::gemm_mixed<kk::EPI_FERMI, kk::MFwdCfg><<<grid, kk::MFwdCfg::THREADS, 0, h->stream>>>(a);
+  } else {
+    ProfileScope ps(h, 1);
+    kk::gemm_mixed<kk::EPI_MULLIKEN, kk::MBackCfg><<<grid, kk::MBackCfg::THREADS, 0, h->stream>>>(a);
+  }
+  LAUNCH_CHECK("gemm_mixed");
+  return KK_OK;
+}
+
+// Split-precision responses: same steps as response_chunk, with the two
+// transforms on FP16 x 3 MFMA products (Y kept as an FP16 split).
+kk_status response_chunk_mixed(kk_handle h, int batch, const double* v, double* q1, const int* stop) {
+  const int N = h->natoms, np = h->np;
+  const size_t np2 = (size_t)np * np;
+  {
+    const int waves = N * batch, threads = 256;
+    const int blocks = (waves * kk::WAVE + threads - 1) / threads;
+    kk::potentials<<<blocks, threads, 0, h->stream>>>(h->gamma, N, h->W, v, batch, h->offsets, np,
+                                                       h->u, stop);
+    LAUNCH_CHECK("potentials");
+  }
+  kk::mixed_scales<<<2 * batch, 1024, 0, h->stream>>>(h->u, np, h->mconst, h->beta, h->msc, stop);
+  LAUNCH_CHECK("mixed_scales");
+  for (int z = 0; z < 2 * batch; ++z) {
+    const int s = z & 1;
+    const int blocks = (int)std::min<size_t>((np2 + 255) / 256, 16384);
+    kk::split_scaled_columns<<<blocks, 256, 0, h->stream>>>(h->CT[s], np, h->u + (size_t)z * np,
+                                                             h->msc + z * 8 + 3, h->uct_h + z * np2,
+                                                             h->uct_l + z * np2, stop);
+    LAUNCH_CHECK("split_scaled_columns");
+    kk::split_scaled_columns<<<blocks, 256, 0, h->stream>>>(h->GT[s], np, h->u + (size_t)z * np,
+                                                             h->msc + z * 8 + 4, h->ugt_h + z * np2,
+                                                             h->ugt_l + z * np2, stop);
+    LAUNCH_CHECK("split_scaled_columns");
+  }
+  kk::MixedArgs fa{};
+  fa.n = np; fa.k_half = np; fa.two_halves = 1; fa.ntiles = h->n_mupper; fa.nitems = 2 * batch;
+  fa.tiles = h->mtiles_upper; fa.stop = stop; fa.beta = h->beta;
+  kk::MixedArgs ba{};
+  ba.n = np; ba.k_half = np; ba.two_halves = 0; ba.ntiles = h->n_mfull; ba.nitems = 2 * batch;
+  ba.tiles = h->mtiles_full; ba.stop = stop; ba.beta = h->beta;
+  for (int z = 0; z < 2 * batch; ++z) {
+    const int s = z & 1;
+    kk::MixedItem& fi = fa.item[z];
+    fi.a0h = h->uct_h + z * np2; fi.a0l = h->uct_l + z * np2; fi.b0h = h->GTh[s]; fi.b0l = h->GTl[s];
+    fi.a1h = h->ugt_h + z * np2; fi.a1l = h->ugt_l + z * np2; fi.b1h = h->CTh[s]; fi.b1l = h->CTl[s];
+    fi.yh = h->yh + z * np2; fi.yl = h->yl + z * np2;
+    fi.eps = h->eps[s]; fi.f = h->f[s]; fi.fc = h->fc[s]; fi.w = h->w[s];
+    fi.xdiag = h->xdiag + (size_t)z * np;
+    fi.sc = h->msc + z * 8;
+    kk::MixedItem& bi = ba.item[z];
+    bi.a0h = h->Ch[s]; bi.a0l = h->Cl[s]; bi.b0h = h->yh + z * np2; bi.b0l = h->yl + z * np2;
+    bi.g = h->G[s];
+    bi.part = h->part + (size_t)z * h->nparts * np;
+    bi.sc = h->msc + z * 8 + 2;
+  }
+  kk_status st;
+  if ((st = launch_mixed(h, kk::EPI_FERMI, fa))) return st;
+  if ((st = launch_mixed(h, kk::EPI_MULLIKEN, ba))) return st;
+  {
+    const int threads = 256;
+    dim3 grid((N + threads - 1) / threads, batch);
+    kk::combine<<<grid, threads, 0, h->stream>>>(h->xdiag, h->part, h->nparts, h->w[0], h->w[1],
+                                                  h->wsum, h->t, h->nb, np, h->offsets, N, q1, stop);
+    LAUNCH_CHECK("combine");
+  }
+  return KK_OK;
+}
+
+kk_status response_any(kk_handle h, int batch, const double* v, double* q1, const int* stop) {
+  return h->precision == KK_FP64 ? response_chunk(h, batch, v, q1, stop)
+                                 : response_chunk_mixed(h, batch, v, q1, stop);
+}
+
 kk_status check_handle(kk_handle h) {
   if (!h) return fail(KK_EINVAL, "handle is NULL");
   if (!h->prepared) return fail(KK_ENOTPREPARED, "kk_prepare has not succeeded on this handle");
+  return KK_OK;
+}
+
+// Split-precision operands, once per prepared expansion point: G^T (FP64) and
+// the FP16 splits of C, C^T, G^T with their power-of-two scales.
+kk_status prepare_mixed(kk_handle h) {
+  const int np = h->np;
+  const size_t np2 = (size_t)np * np;
+  kk_status st;
+  if ((st = dalloc_t(h, &h->mconst, 8))) return st;
+  double *rmax = nullptr, *rn2 = nullptr;
+  if ((st = dalloc_t(h, &rmax, (size_t)4 * np))) return st;
+  rn2 = rmax + 2 * np;
+  std::vector<int2> up, full;
+  for (int s = 0; s < 2; ++s) {
+    if ((st = dalloc_t(h, &h->GT[s], np2))) return st;
+    for (_Float16** q : {&h->Ch[s], &h->Cl[s], &h->CTh[s], &h->CTl[s], &h->GTh[s], &h->GTl[s]})
+      if ((st = dalloc_t(h, q, np2))) return st;
+    dim3 pg(np / 32, np / 32), pb(256);
+    kk::transpose_sq<<<pg, pb, 0, h->stream>>>(h->G[s], h->GT[s], np);
+    LAUNCH_CHECK("transpose G");
+    // rows of C^T are columns of C; rows of G^T columns of G
+    kk::row_stats<<<np, 1024, 0, h->stream>>>(h->CT[s], np, rmax, rn2);
+    LAUNCH_CHECK("row_stats");
+    kk::row_stats<<<np, 1024, 0, h->stream>>>(h->GT[s], np, rmax + np, rn2 + np);
+    LAUNCH_CHECK("row_stats");
+    kk::const_scales<<<1, 1024, 0, h->stream>>>(rmax, rn2, rmax + np, rn2 + np, np, h->mconst + 4 * s);
+    LAUNCH_CHECK("const_scales");
+    kk::split_matrix<<<pg, pb, 0, h->stream>>>(h->C[s], np, 0, h->mconst + 4 * s, h->Ch[s], h->Cl[s]);
+    kk::split_matrix<<<pg, pb, 0, h->stream>>>(h->CT[s], np, 0, h->mconst + 4 * s, h->CTh[s], h->CTl[s]);
+    kk::split_matrix<<<pg, pb, 0, h->stream>>>(h->GT[s], np, 0, h->mconst + 4 * s + 1, h->GTh[s], h->GTl[s]);
+    LAUNCH_CHECK("split_matrix");
+  }
+  up = tile_order(np, kk::MFwdCfg::BM, kk::MFwdCfg::BN, true);
+  full = tile_order(np, kk::MBackCfg::BM, kk::MBackCfg::BN, false);
+  h->n_mupper = (int)up.size();
+  h->n_mfull = (int)full.size();
+  if ((st = dalloc_t(h, &h->mtiles_upper, up.size()))) return st;
+  if ((st = dalloc_t(h, &h->mtiles_full, full.size()))) return st;
+  HIP_OR_FAIL(hipMemcpyAsync(h->mtiles_upper, up.data(), sizeof(int2) * up.size(), hipMemcpyHostToDevice,
+                             h->stream));
+  HIP_OR_FAIL(hipMemcpyAsync(h->mtiles_full, full.data(), sizeof(int2) * full.size(), hipMemcpyHostToDevice,
+                             h->stream));
+  HIP_OR_FAIL(hipStreamSynchronize(h->stream));
   return KK_OK;
 }
 
@@ -298,7 +447,8 @@ kk_status kk_prepare(kk_handle h, int n_atoms, const int* atom_offsets, int n_ba
   if (!(kT > 0.0)) return fail(KK_EINVAL, "kk_prepare: kT must be > 0");
   if (!(n_electrons > 0.0 && n_electrons < 2.0 * n_basis))
     return fail(KK_EINVAL, "kk_prepare: need 0 < n_electrons < 2 n_basis");
-  if (precision != KK_FP64) return fail(KK_EINVAL, "kk_prepare: unsupported precision %d", precision);
+  if (precision != KK_FP64 && precision != KK_MIXED_F16)
+    return fail(KK_EINVAL, "kk_prepare: unsupported precision %d", precision);
   if (atom_offsets[0] != 0 || atom_offsets[n_atoms] != n_basis)
     return fail(KK_EINVAL, "kk_prepare: atom_offsets must start at 0 and end at n_basis");
   for (int a = 0; a < n_atoms; ++a)
@@ -306,9 +456,14 @@ kk_status kk_prepare(kk_handle h, int n_atoms, const int* atom_offsets, int n_ba
       return fail(KK_EINVAL, "kk_prepare: atom_offsets must be strictly increasing (atom %d)", a);
 
   h->release();
-  const int nb = n_basis, np = (nb + kk::TILE - 1) / kk::TILE * kk::TILE;
+  const bool mixed = precision == KK_MIXED_F16;
+  const int pad = mixed ? kk::MIXED_PAD : kk::PAD;
+  const int nb = n_basis, np = (nb + pad - 1) / pad * pad;
   const size_t np2 = (size_t)np * np;
-  h->natoms = n_atoms; h->nb = nb; h->np = np; h->nparts = 2 * (np / kk::TILE);
+  h->precision = precision;
+  h->natoms = n_atoms; h->nb = nb; h->np = np;
+  h->nparts = mixed ? (np / kk::MBackCfg::BN) * kk::MBackCfg::WAVES_N
+                    : (np / kk::BackCfg::BN) * kk::BackCfg::WAVES_N;
   h->W = W; h->kT = kT; h->beta = 1.0 / kT; h->n_e = n_electrons;
 
   kk_status st;
@@ -327,12 +482,15 @@ kk_status kk_prepare(kk_handle h, int n_atoms, const int* atom_offsets, int n_ba
   if ((st = dalloc_t(h, &h->mu, 1))) return st;
   if ((st = dalloc_t(h, &h->wsum, 1))) return st;
   if ((st = dalloc_t(h, &h->offsets, (size_t)n_atoms + 1))) return st;
-  const int T = np / kk::TILE;
-  std::vector<int2> up = tile_order(T, true), full = tile_order(T, false);
+  std::vector<int2> up = tile_order(np, kk::FwdCfg::BM, kk::FwdCfg::BN, true);
+  std::vector<int2> full = tile_order(np, kk::BackCfg::BM, kk::BackCfg::BN, false);
+  std::vector<int2> stt = tile_order(np, kk::StoreCfg::BM, kk::StoreCfg::BN, false);
   h->n_upper = (int)up.size();
   h->n_full = (int)full.size();
+  h->n_store = (int)stt.size();
   if ((st = dalloc_t(h, &h->tiles_upper, up.size()))) return st;
   if ((st = dalloc_t(h, &h->tiles_full, full.size()))) return st;
+  if ((st = dalloc_t(h, &h->tiles_store, stt.size()))) return st;
   const int n2 = 2 * n_atoms;
   if ((st = dalloc_t(h, &h->V, (size_t)kk::MAX_RANK * n2))) return st;
   if ((st = dalloc_t(h, &h->Ft, (size_t)kk::MAX_RANK * n2))) return st;
@@ -345,6 +503,8 @@ kk_status kk_prepare(kk_handle h, int n_atoms, const int* atom_offsets, int n_ba
   HIP_OR_FAIL(hipMemcpyAsync(h->tiles_upper, up.data(), sizeof(int2) * up.size(), hipMemcpyHostToDevice,
                              h->stream));
   HIP_OR_FAIL(hipMemcpyAsync(h->tiles_full, full.data(), sizeof(int2) * full.size(), hipMemcpyHostToDevice,
+                             h->stream));
+  HIP_OR_FAIL(hipMemcpyAsync(h->tiles_store, stt.data(), sizeof(int2) * stt.size(), hipMemcpyHostToDevice,
                              h->stream));
   HIP_OR_FAIL(hipMemcpyAsync(h->gamma, gamma, sizeof(double) * n_atoms * n_atoms, hipMemcpyDeviceToDevice,
                              h->stream));
@@ -362,7 +522,7 @@ kk_status kk_prepare(kk_handle h, int n_atoms, const int* atom_offsets, int n_ba
     LAUNCH_CHECK("pad_copy Q");
   }
   kk::GemmArgs a{};
-  a.n = np; a.k_half = np; a.two_halves = 0; a.ntiles = h->n_full; a.tiles = h->tiles_full;
+  a.n = np; a.k_half = np; a.two_halves = 0; a.ntiles = h->n_store; a.tiles = h->tiles_store;
   a.stop = nullptr; a.nitems = 2;
   for (int s = 0; s < 2; ++s) {  // C_s[m][n] = sum_k Z^T[k][m] Q_s[k][n]
     a.item[s] = kk::GemmItem{};
@@ -392,6 +552,7 @@ kk_status kk_prepare(kk_handle h, int n_atoms, const int* atom_offsets, int n_ba
   kk::atom_row_dots<<<n_atoms, 256, 0, h->stream>>>(h->C[0], h->C[1], np, h->G[0], h->G[1], np, h->w[0],
                                                      h->w[1], np, h->offsets, n_atoms, h->t);
   LAUNCH_CHECK("atom_row_dots");
+  if (mixed && (st = prepare_mixed(h))) return st;
   HIP_OR_FAIL(hipStreamSynchronize(h->stream));
   h->prepared = true;
   g_err.clear();
@@ -417,7 +578,7 @@ kk_status density_response_batch(kk_handle h, int batch, const double* v, double
   const size_t n2 = 2 * (size_t)h->natoms;
   for (int b0 = 0; b0 < batch; b0 += chunk) {
     const int nbat = std::min(chunk, batch - b0);
-    if ((st = response_chunk(h, nbat, v + b0 * n2, q1 + b0 * n2, nullptr))) return st;
+    if ((st = response_any(h, nbat, v + b0 * n2, q1 + b0 * n2, nullptr))) return st;
   }
   g_err.clear();
   return KK_OK;
@@ -457,7 +618,7 @@ kk_status krylov_kernel_apply(kk_handle h, const double* delta, int m, const dou
     kk::krylov_orthonormalize<<<1, 1024, 0, h->stream>>>(src, h->V, n2, h->kst);
     LAUNCH_CHECK("krylov_orthonormalize");
     const double* vk = h->V + (size_t)k * n2;
-    if ((st = response_chunk(h, 1, vk, h->q1, stop))) return st;
+    if ((st = response_any(h, 1, vk, h->q1, stop))) return st;
     kk::precondition<<<gv_blocks, gv_threads, 0, h->stream>>>(K0, h->q1, vk, h->Ft + (size_t)k * n2, n2,
                                                                stop);
     LAUNCH_CHECK("precondition");

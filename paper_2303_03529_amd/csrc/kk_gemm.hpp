@@ -3,25 +3,26 @@
 // Every dense contraction of the response runs through one kernel shape:
 //   acc[m][n] = sum_k A[k][m] * B[k][n]
 // with both operands stored k-major (row k contiguous along m or n), padded to
-// a multiple of the 128 x 128 tile so no access needs a bounds check. In that
-// layout the forward eigenbasis transform X = C^T U~ G (+ its transpose) and
-// the back-transform P = C Y (with C^T stored) read both panels along rows,
-// which is the coalesced direction.
+// a multiple of 128 so no access needs a bounds check. In that layout the
+// forward eigenbasis transform X = C^T U~ G (+ its transpose) and the
+// back-transform P = C Y (with C^T stored) read both panels along rows, which
+// is the coalesced direction.
 //
-// Tile: 128 x 128 per 256-thread workgroup, 4 waves in 2 x 2, each wave a
-// 64 x 64 block made of 4 x 4 v_mfma_f64_16x16x4 accumulators (64 doubles per
-// lane). K advances 16 per stage through double-buffered LDS (64 KiB), with the
-// next stage's global loads in flight while the current stage is multiplied.
+// Tile: BM x BN per workgroup of WAVES_M x WAVES_N waves; each wave owns a
+// (BM/WAVES_M) x (BN/WAVES_N) block of v_mfma_f64_16x16x4 accumulators. K
+// advances BK per stage through double-buffered LDS with the next stage's
+// global loads in flight while the current stage is multiplied.
 //
 // Epilogues
 //   EPI_STORE   out[m][n] = acc                                (setup products)
 //   EPI_FERMI   Sec. II.C first-order Fermi response in the eigenbasis:
 //               X = 1/2 acc (acc accumulates C^T U~ G + G^T U~ C over a K of
-//               2 Nb), Y_mn = F_mn X_mn for m != n written to (m,n) and (n,m),
+//               2 Nb), Y_mn = F_mn X_mn for m < n written to (m,n) and (n,m),
 //               Y_mm = -w_m X_mm and X_mm saved for the chemical-potential
-//               shift. Only upper-triangle tiles are launched.
-//   EPI_MULLIKEN  Sec. III.A Mulliken rows: part[p][m] = sum_{n in tile half}
-//               acc[m][n] * G[m][n]; the caller sums the parts per atom.
+//               shift. Tiles entirely below the diagonal are not launched;
+//               elements below it are skipped.
+//   EPI_MULLIKEN  Sec. III.A Mulliken rows: part[p][m] = sum over the wave's
+//               columns n of acc[m][n] * G[m][n]; the caller sums the parts.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -29,10 +30,9 @@
 namespace kk {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
 
-constexpr int TILE = 128;   // M and N tile
-constexpr int BK = 16;      // K per LDS stage
-constexpr int NTHREADS = 256;
+constexpr int PAD = 128;    // every padded dimension is a multiple of this
 constexpr int MAX_GEMM_BATCH = 16;
 
 enum { EPI_STORE = 0, EPI_FERMI = 1, EPI_MULLIKEN = 2 };
@@ -50,11 +50,11 @@ struct GemmItem {
   const double* fc;     // 1 - f
   const double* w;      // beta f (1 - f)
   double* xdiag;        // EPI_FERMI: diag X
-  double* part;         // EPI_MULLIKEN: [2 * n / TILE][n]
+  double* part;         // EPI_MULLIKEN: [parts][n]
 };
 
 struct GemmArgs {
-  int n;          // padded dimension (multiple of TILE); M = N = n, row stride n
+  int n;          // padded dimension; M = N = n, row stride n
   int k_half;     // rows per K half (= n)
   int two_halves; // 1: K runs over both halves (a0,b0) then (a1,b1)
   int ntiles;     // tiles per item
@@ -88,8 +88,33 @@ __device__ __forceinline__ double fermi_divided_difference(double em, double fm,
   return -beta * flo * fchi * phi;
 }
 
-template <int EPI>
-__global__ __launch_bounds__(NTHREADS, 2) void gemm_f64(const GemmArgs args) {
+template <int BM_, int BN_, int BK_, int WAVES_M_, int WAVES_N_, int MINB_>
+struct TileCfg {
+  static constexpr int BM = BM_, BN = BN_, BK = BK_;
+  static constexpr int WAVES_M = WAVES_M_, WAVES_N = WAVES_N_;
+  static constexpr int THREADS = 64 * WAVES_M * WAVES_N;
+  static constexpr int WTM = BM / WAVES_M / 16;  // MFMA tiles per wave along m
+  static constexpr int WTN = BN / WAVES_N / 16;  // along n
+  static constexpr int MIN_BLOCKS = MINB_;
+  // global -> LDS staging: each thread moves double2 pieces
+  static constexpr int A_PIECES = BK * BM / 2 / THREADS;
+  static constexpr int B_PIECES = BK * BN / 2 / THREADS;
+  static_assert(BM % (16 * WAVES_M) == 0 && BN % (16 * WAVES_N) == 0, "wave tiling");
+  static_assert(BK % 4 == 0, "BK");
+  static_assert(A_PIECES >= 1 && B_PIECES >= 1, "staging");
+  static_assert((BK * BM / 2) % THREADS == 0 && (BK * BN / 2) % THREADS == 0, "staging split");
+  static_assert(PAD % BM == 0 && PAD % BN == 0, "tile must divide the padding");
+  static constexpr int LDS_BYTES = 2 * BK * (BM + BN) * 8;
+};
+
+template <int EPI, class Cfg>
+__global__ __launch_bounds__(Cfg::THREADS, Cfg::MIN_BLOCKS) void gemm_f64(const GemmArgs args) {
+  constexpr int BM = Cfg::BM, BN = Cfg::BN, BK = Cfg::BK;
+  constexpr int WTM = Cfg::WTM, WTN = Cfg::WTN;
+  constexpr int AP = Cfg::A_PIECES, BP = Cfg::B_PIECES;
+  constexpr int APR = BM / 2;  // double2 pieces per A row
+  constexpr int BPR = BN / 2;
+
   if (args.stop != nullptr && *args.stop != 0) return;
   const int total = args.ntiles * args.nitems;
   const int logical = xcd_remap(blockIdx.x, total);
@@ -97,62 +122,58 @@ __global__ __launch_bounds__(NTHREADS, 2) void gemm_f64(const GemmArgs args) {
   const int2 tile = args.tiles[logical - z * args.ntiles];
   const GemmItem& it = args.item[z];
   const int n = args.n;
-  const int m0 = tile.x * TILE, n0 = tile.y * TILE;
+  const int m0 = tile.x * BM, n0 = tile.y * BN;
 
-  __shared__ double As[2][BK][TILE];
-  __shared__ double Bs[2][BK][TILE];
+  __shared__ double As[2][BK][BM];
+  __shared__ double Bs[2][BK][BN];
 
   const int tid = threadIdx.x;
-  const int lrow = tid >> 6;         // 0..3, plus 4 * j
-  const int lcol = (tid & 63) * 2;   // two doubles per thread per row
   const int nk = (args.two_halves ? 2 * args.k_half : args.k_half) / BK;
   const int wave = tid >> 6, lane = tid & 63;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / Cfg::WAVES_N, wn = wave % Cfg::WAVES_N;
   const int lr = lane >> 4, lc = lane & 15;
 
-  d4 acc[4][4];
+  d4 acc[WTM][WTN];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < WTM; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = (d4){0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < WTN; ++j) acc[i][j] = (d4){0.0, 0.0, 0.0, 0.0};
 
-  double2 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
-#define KK_GLOAD(kt)                                                                   \
-  {                                                                                    \
-    int k0 = (kt) * BK;                                                                \
-    const double* A = it.a0;                                                           \
-    const double* B = it.b0;                                                           \
-    if (args.two_halves && k0 >= args.k_half) {                                        \
-      A = it.a1; B = it.b1; k0 -= args.k_half;                                         \
-    }                                                                                  \
-    const double* pa = A + (size_t)(k0 + lrow) * n + m0 + lcol;                        \
-    const double* pb = B + (size_t)(k0 + lrow) * n + n0 + lcol;                        \
-    const size_t st4 = (size_t)4 * n;                                                  \
-    ra0 = *reinterpret_cast<const double2*>(pa);                                       \
-    ra1 = *reinterpret_cast<const double2*>(pa + st4);                                 \
-    ra2 = *reinterpret_cast<const double2*>(pa + 2 * st4);                             \
-    ra3 = *reinterpret_cast<const double2*>(pa + 3 * st4);                             \
-    rb0 = *reinterpret_cast<const double2*>(pb);                                       \
-    rb1 = *reinterpret_cast<const double2*>(pb + st4);                                 \
-    rb2 = *reinterpret_cast<const double2*>(pb + 2 * st4);                             \
-    rb3 = *reinterpret_cast<const double2*>(pb + 3 * st4);                             \
-    if constexpr (EPI == EPI_FERMI) {                                                  \
-      const double* sc = it.scale + k0 + lrow;                                         \
-      const double s0 = sc[0], s1 = sc[4], s2 = sc[8], s3 = sc[12];                    \
-      ra0.x *= s0; ra0.y *= s0; ra1.x *= s1; ra1.y *= s1;                              \
-      ra2.x *= s2; ra2.y *= s2; ra3.x *= s3; ra3.y *= s3;                              \
-    }                                                                                  \
+  d2 ra[AP], rb[BP];
+
+#define KK_GLOAD(kt)                                                                        \
+  {                                                                                         \
+    int k0 = (kt) * BK;                                                                     \
+    const double* A = it.a0;                                                                \
+    const double* B = it.b0;                                                                \
+    if (args.two_halves && k0 >= args.k_half) {                                             \
+      A = it.a1; B = it.b1; k0 -= args.k_half;                                              \
+    }                                                                                       \
+    _Pragma("unroll") for (int p = 0; p < AP; ++p) {                                        \
+      const int idx = tid + p * Cfg::THREADS;                                               \
+      const int row = idx / APR, col = (idx % APR) * 2;                                     \
+      ra[p] = *reinterpret_cast<const d2*>(A + (size_t)(k0 + row) * n + m0 + col);     \
+      if constexpr (EPI == EPI_FERMI) {                                                     \
+        const double s = it.scale[k0 + row];                                                \
+        ra[p] *= s;                                                                         \
+      }                                                                                     \
+    }                                                                                       \
+    _Pragma("unroll") for (int p = 0; p < BP; ++p) {                                        \
+      const int idx = tid + p * Cfg::THREADS;                                               \
+      const int row = idx / BPR, col = (idx % BPR) * 2;                                     \
+      rb[p] = *reinterpret_cast<const d2*>(B + (size_t)(k0 + row) * n + n0 + col);     \
+    }                                                                                       \
   }
-#define KK_LSTORE(buf)                                                                 \
-  {                                                                                    \
-    *reinterpret_cast<double2*>(&As[buf][lrow][lcol]) = ra0;                           \
-    *reinterpret_cast<double2*>(&As[buf][lrow + 4][lcol]) = ra1;                       \
-    *reinterpret_cast<double2*>(&As[buf][lrow + 8][lcol]) = ra2;                       \
-    *reinterpret_cast<double2*>(&As[buf][lrow + 12][lcol]) = ra3;                      \
-    *reinterpret_cast<double2*>(&Bs[buf][lrow][lcol]) = rb0;                           \
-    *reinterpret_cast<double2*>(&Bs[buf][lrow + 4][lcol]) = rb1;                       \
-    *reinterpret_cast<double2*>(&Bs[buf][lrow + 8][lcol]) = rb2;                       \
-    *reinterpret_cast<double2*>(&Bs[buf][lrow + 12][lcol]) = rb3;                      \
+#define KK_LSTORE(buf)                                                                      \
+  {                                                                                         \
+    _Pragma("unroll") for (int p = 0; p < AP; ++p) {                                        \
+      const int idx = tid + p * Cfg::THREADS;                                               \
+      *reinterpret_cast<d2*>(&As[buf][idx / APR][(idx % APR) * 2]) = ra[p];            \
+    }                                                                                       \
+    _Pragma("unroll") for (int p = 0; p < BP; ++p) {                                        \
+      const int idx = tid + p * Cfg::THREADS;                                               \
+      *reinterpret_cast<d2*>(&Bs[buf][idx / BPR][(idx % BPR) * 2]) = rb[p];            \
+    }                                                                                       \
   }
 
   KK_GLOAD(0);
@@ -165,15 +186,15 @@ __global__ __launch_bounds__(NTHREADS, 2) void gemm_f64(const GemmArgs args) {
     if (more) KK_GLOAD(kt + 1);
 #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
-      double a[4], b[4];
+      double a[WTM], b[WTN];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[buf][kk * 4 + lr][wm * 64 + i * 16 + lc];
+      for (int i = 0; i < WTM; ++i) a[i] = As[buf][kk * 4 + lr][wm * (BM / Cfg::WAVES_M) + i * 16 + lc];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[buf][kk * 4 + lr][wn * 64 + j * 16 + lc];
+      for (int j = 0; j < WTN; ++j) b[j] = Bs[buf][kk * 4 + lr][wn * (BN / Cfg::WAVES_N) + j * 16 + lc];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < WTM; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < WTN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     if (more) KK_LSTORE(buf ^ 1);
@@ -183,37 +204,35 @@ __global__ __launch_bounds__(NTHREADS, 2) void gemm_f64(const GemmArgs args) {
 #undef KK_LSTORE
 
   // Accumulator element (i, j, r) of this lane sits at
-  //   m = m0 + wm*64 + i*16 + lr + 4r,  n = n0 + wn*64 + j*16 + lc.
+  //   m = m0 + wm*(BM/WAVES_M) + i*16 + lr + 4r,  n = n0 + wn*(BN/WAVES_N) + j*16 + lc.
+  const int mw = m0 + wm * (BM / Cfg::WAVES_M) + lr;
+  const int nw = n0 + wn * (BN / Cfg::WAVES_N) + lc;
   if constexpr (EPI == EPI_STORE) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < WTM; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < WTN; ++j)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int m = m0 + wm * 64 + i * 16 + lr + 4 * r;
-          const int c = n0 + wn * 64 + j * 16 + lc;
-          it.out[(size_t)m * n + c] = acc[i][j][r];
-        }
+        for (int r = 0; r < 4; ++r)
+          it.out[(size_t)(mw + i * 16 + 4 * r) * n + nw + j * 16] = acc[i][j][r];
   } else if constexpr (EPI == EPI_FERMI) {
-    const bool diag_tile = tile.x == tile.y;
     const double beta = args.beta;
-    double en[4], fn[4], fcn[4];
+    double en[WTN], fn[WTN], fcn[WTN];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int c = n0 + wn * 64 + j * 16 + lc;
+    for (int j = 0; j < WTN; ++j) {
+      const int c = nw + j * 16;
       en[j] = it.eps[c]; fn[j] = it.f[c]; fcn[j] = it.fc[c];
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < WTM; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wm * 64 + i * 16 + lr + 4 * r;
+        const int m = mw + i * 16 + 4 * r;
         const double em = it.eps[m], fm = it.f[m], fcm = it.fc[m];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int c = n0 + wn * 64 + j * 16 + lc;
-          if (diag_tile && m > c) continue;
+        for (int j = 0; j < WTN; ++j) {
+          const int c = nw + j * 16;
+          if (m > c) continue;
           const double x = 0.5 * acc[i][j][r];
           if (m == c) {
             it.xdiag[m] = x;
@@ -226,18 +245,15 @@ __global__ __launch_bounds__(NTHREADS, 2) void gemm_f64(const GemmArgs args) {
         }
       }
   } else {  // EPI_MULLIKEN
-    const int p = tile.y * 2 + wn;
+    const int p = tile.y * Cfg::WAVES_N + wn;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < WTM; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wm * 64 + i * 16 + lr + 4 * r;
+        const int m = mw + i * 16 + 4 * r;
         double s = 0.0;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int c = n0 + wn * 64 + j * 16 + lc;
-          s += acc[i][j][r] * it.g[(size_t)m * n + c];
-        }
+        for (int j = 0; j < WTN; ++j) s += acc[i][j][r] * it.g[(size_t)m * n + nw + j * 16];
         s += __shfl_xor(s, 1);
         s += __shfl_xor(s, 2);
         s += __shfl_xor(s, 4);
@@ -246,5 +262,33 @@ __global__ __launch_bounds__(NTHREADS, 2) void gemm_f64(const GemmArgs args) {
       }
   }
 }
+
+// Configurations. The default (128 x 128 tile, 8 waves of 32 x 64, two
+// workgroups and 16 waves per CU) was the fastest of the shapes below for
+// both transforms at Nb = 9216 and 3888 on MI355X; the others stay available
+// for re-tuning (-DKK_FWD_CFG=..., -DKK_BACK_CFG=...).
+using Cfg128x128 = TileCfg<128, 128, 16, 2, 2, 2>;
+using Cfg128x64 = TileCfg<128, 64, 16, 2, 2, 2>;
+using Cfg64x128 = TileCfg<64, 128, 16, 2, 2, 2>;
+using Cfg128x128w8 = TileCfg<128, 128, 16, 4, 2, 2>;
+using Cfg128x128k32 = TileCfg<128, 128, 32, 2, 2, 1>;
+using Cfg128x128k8 = TileCfg<128, 128, 8, 2, 2, 2>;
+using Cfg64x64 = TileCfg<64, 64, 16, 2, 2, 3>;
+
+using Cfg128x128w16 = TileCfg<128, 128, 16, 4, 4, 1>;
+using Cfg128x128w8n = TileCfg<128, 128, 16, 2, 4, 2>;
+
+#ifndef KK_FWD_CFG
+#define KK_FWD_CFG Cfg128x128w8
+#endif
+#ifndef KK_BACK_CFG
+#define KK_BACK_CFG Cfg128x128w8
+#endif
+#ifndef KK_STORE_CFG
+#define KK_STORE_CFG Cfg128x128w8
+#endif
+using FwdCfg = KK_FWD_CFG;
+using BackCfg = KK_BACK_CFG;
+using StoreCfg = KK_STORE_CFG;
 
 }  // namespace kk

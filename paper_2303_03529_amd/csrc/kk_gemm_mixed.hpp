@@ -1,0 +1,380 @@
+// Split-precision (FP16 x 3) MFMA transforms for gfx950.
+//
+// Each FP64 operand M is held as two FP16 matrices, M_hi = fp16(s M) and
+// M_lo = fp16(s M - M_hi), with a power-of-two scale s chosen so that
+// max |s M| <= 2^14. Their sum carries ~22 significant bits. A product is
+// formed from three FP16 MFMA products, A_hi B_hi + A_hi B_lo + A_lo B_hi,
+// accumulated in FP32 by v_mfma_f32_32x32x16_f16; the dropped A_lo B_lo term
+// and the FP32 accumulation leave a relative error of a few 1e-7 per entry.
+// Everything outside the products stays FP64: the unscaling, the Fermi
+// divided differences and their Hadamard product, the diagonal capture for
+// the chemical-potential shift and the Mulliken dot products with G.
+//
+// Layout (NT form): out[m][n] = sum_k At[m][k] * Bt[n][k] with At, Bt stored
+// row-major with k contiguous, so each lane's 8 FP16 MFMA operands are one
+// 16-byte LDS read. The forward transform uses
+//   At = (U~ C)^T, Bt = G^T over the first K half and At = (U~ G)^T, Bt = C^T
+//   over the second (the two halves share one scale), giving C^T U~ G + G^T U~ C;
+// the back-transform uses At = C (row i, k = l) and Bt = Y (symmetric, so
+// row k of Y is column k).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "kk_gemm.hpp"
+
+namespace kk {
+
+constexpr int MIXED_PAD = 256;  // padded dimension of the split-precision path
+
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef float f16x __attribute__((ext_vector_type(16)));
+
+struct MixedItem {
+  const _Float16 *a0h, *a0l, *b0h, *b0l;  // first K half (At, Bt), [n][n], k contiguous
+  const _Float16 *a1h, *a1l, *b1h, *b1l;  // second K half (forward transform only)
+  _Float16 *yh, *yl;                      // forward: Y split at scale sc[1]
+  const double* g;                        // back: G (FP64)
+  const double *eps, *f, *fc, *w;         // forward: spectrum
+  double* xdiag;                          // forward: diag X
+  double* part;                           // back: Mulliken partials [parts][n]
+  const double* sc;                       // device scalars: [0] = 1 / product scale, [1] = Y scale
+};
+
+struct MixedArgs {
+  int n, k_half, two_halves, ntiles, nitems;
+  const int2* tiles;
+  const int* stop;
+  double beta;
+  MixedItem item[MAX_GEMM_BATCH];
+};
+
+template <int BM_, int BN_, int BK_, int WAVES_M_, int WAVES_N_, int MINB_>
+struct MixedCfg {
+  static constexpr int BM = BM_, BN = BN_, BK = BK_;
+  static constexpr int WAVES_M = WAVES_M_, WAVES_N = WAVES_N_;
+  static constexpr int THREADS = 64 * WAVES_M * WAVES_N;
+  static constexpr int WTM = BM / WAVES_M / 32;
+  static constexpr int WTN = BN / WAVES_N / 32;
+  static constexpr int MIN_BLOCKS = MINB_;
+  static constexpr int KP = BK + 8;                 // padded LDS row (halves)
+  static constexpr int CHUNKS = (BM + BN) * BK / 8 * 2;  // 16-byte pieces per stage (hi + lo)
+  static constexpr int PER_THREAD = CHUNKS / THREADS;
+  static_assert(BM % (32 * WAVES_M) == 0 && BN % (32 * WAVES_N) == 0, "wave tiling");
+  static_assert(BK % 16 == 0, "BK");
+  static_assert(CHUNKS % THREADS == 0, "staging split");
+  static_assert(MIXED_PAD % BM == 0 && MIXED_PAD % BN == 0, "tile must divide the padding");
+};
+
+__device__ __forceinline__ void split_store(double v, _Float16* hi, _Float16* lo) {
+  const _Float16 h = (_Float16)(float)v;
+  *hi = h;
+  *lo = (_Float16)(float)(v - (double)h);
+}
+
+template <int EPI, class Cfg>
+__global__ __launch_bounds__(Cfg::THREADS, Cfg::MIN_BLOCKS) void gemm_mixed(const MixedArgs args) {
+  constexpr int BM = Cfg::BM, BN = Cfg::BN, BK = Cfg::BK, KP = Cfg::KP;
+  constexpr int WTM = Cfg::WTM, WTN = Cfg::WTN, PT = Cfg::PER_THREAD;
+  constexpr int CPR = BK / 8;  // 16-byte chunks per row per matrix
+
+  if (args.stop != nullptr && *args.stop != 0) return;
+  const int total = args.ntiles * args.nitems;
+  const int logical = xcd_remap(blockIdx.x, total);
+  const int z = logical / args.ntiles;
+  const int2 tile = args.tiles[logical - z * args.ntiles];
+  const MixedItem& it = args.item[z];
+  const int n = args.n;
+  const int m0 = tile.x * BM, n0 = tile.y * BN;
+
+  // [buf][hi/lo][row][k]
+  __shared__ __attribute__((aligned(16))) _Float16 As[2][2][BM][KP];
+  __shared__ __attribute__((aligned(16))) _Float16 Bs[2][2][BN][KP];
+
+  const int tid = threadIdx.x;
+  const int nk = (args.two_halves ? 2 * args.k_half : args.k_half) / BK;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wm = wave / Cfg::WAVES_N, wn = wave % Cfg::WAVES_N;
+  const int l32 = lane & 31, lh = lane >> 5;
+
+  f16x acc[WTM][WTN];
+#pragma unroll
+  for (int i = 0; i < WTM; ++i)
+#pragma unroll
+    for (int j = 0; j < WTN; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  h8 stage[PT];
+
+  // Piece p of this thread: c = tid + p*THREADS enumerates (matrix, hi/lo, row, chunk)
+  // with A pieces first: [hi rows BM][lo rows BM] then B: [hi rows BN][lo rows BN].
+#define KK_MLOAD(kt)                                                                         \
+  {                                                                                          \
+    int k0 = (kt) * BK;                                                                      \
+    const _Float16 *ah = it.a0h, *al = it.a0l, *bh = it.b0h, *bl = it.b0l;                   \
+    if (args.two_halves && k0 >= args.k_half) {                                              \
+      ah = it.a1h; al = it.a1l; bh = it.b1h; bl = it.b1l; k0 -= args.k_half;                 \
+    }                                                                                        \
+    _Pragma("unroll") for (int p = 0; p < PT; ++p) {                                         \
+      const int c = tid + p * Cfg::THREADS;                                                  \
+      const int row = c / CPR, ch = c % CPR;                                                 \
+      const _Float16* src;                                                                   \
+      if (row < BM) src = ah + (size_t)(m0 + row) * n;                                       \
+      else if (row < 2 * BM) src = al + (size_t)(m0 + row - BM) * n;                         \
+      else if (row < 2 * BM + BN) src = bh + (size_t)(n0 + row - 2 * BM) * n;               \
+      else src = bl + (size_t)(n0 + row - 2 * BM - BN) * n;                                  \
+      stage[p] = *reinterpret_cast<const h8*>(src + k0 + ch * 8);                            \
+    }                                                                                        \
+  }
+#define KK_MSTORE(buf)                                                                       \
+  {                                                                                          \
+    _Pragma("unroll") for (int p = 0; p < PT; ++p) {                                         \
+      const int c = tid + p * Cfg::THREADS;                                                  \
+      const int row = c / CPR, ch = c % CPR;                                                 \
+      _Float16* dst;                                                                         \
+      if (row < BM) dst = &As[buf][0][row][0];                                               \
+      else if (row < 2 * BM) dst = &As[buf][1][row - BM][0];                                 \
+      else if (row < 2 * BM + BN) dst = &Bs[buf][0][row - 2 * BM][0];                       \
+      else dst = &Bs[buf][1][row - 2 * BM - BN][0];                                          \
+      *reinterpret_cast<h8*>(dst + ch * 8) = stage[p];                                       \
+    }                                                                                        \
+  }
+
+  KK_MLOAD(0);
+  KK_MSTORE(0);
+  __syncthreads();
+
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    const bool more = kt + 1 < nk;
+    if (more) KK_MLOAD(kt + 1);
+#pragma unroll
+    for (int ks = 0; ks < BK / 16; ++ks) {
+      h8 ah[WTM], al[WTM], bh[WTN], bl[WTN];
+      const int kofs = ks * 16 + lh * 8;
+#pragma unroll
+      for (int i = 0; i < WTM; ++i) {
+        const int r = wm * (BM / Cfg::WAVES_M) + i * 32 + l32;
+        ah[i] = *reinterpret_cast<const h8*>(&As[buf][0][r][kofs]);
+        al[i] = *reinterpret_cast<const h8*>(&As[buf][1][r][kofs]);
+      }
+#pragma unroll
+      for (int j = 0; j < WTN; ++j) {
+        const int r = wn * (BN / Cfg::WAVES_N) + j * 32 + l32;
+        bh[j] = *reinterpret_cast<const h8*>(&Bs[buf][0][r][kofs]);
+        bl[j] = *reinterpret_cast<const h8*>(&Bs[buf][1][r][kofs]);
+      }
+#pragma unroll
+      for (int i = 0; i < WTM; ++i)
+#pragma unroll
+        for (int j = 0; j < WTN; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(al[i], bh[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+        }
+    }
+    if (more) KK_MSTORE(buf ^ 1);
+    __syncthreads();
+  }
+#undef KK_MLOAD
+#undef KK_MSTORE
+
+  // Accumulator element (i, j, r) of this lane:
+  //   m = m0 + wm*(BM/WAVES_M) + i*32 + 8*(r/4) + 4*lh + r%4,  n = n0 + wn*(BN/WAVES_N) + j*32 + l32.
+  const double inv = it.sc[0];
+  const int mw = m0 + wm * (BM / Cfg::WAVES_M) + 4 * lh;
+  const int nw = n0 + wn * (BN / Cfg::WAVES_N) + l32;
+  if constexpr (EPI == EPI_FERMI) {
+    const double beta = args.beta, sy = it.sc[1];
+    double en[WTN], fn[WTN], fcn[WTN];
+#pragma unroll
+    for (int j = 0; j < WTN; ++j) {
+      const int c = nw + j * 32;
+      en[j] = it.eps[c]; fn[j] = it.f[c]; fcn[j] = it.fc[c];
+    }
+#pragma unroll
+    for (int i = 0; i < WTM; ++i)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = mw + i * 32 + 8 * (r / 4) + (r % 4);
+        const double em = it.eps[m], fm = it.f[m], fcm = it.fc[m];
+#pragma unroll
+        for (int j = 0; j < WTN; ++j) {
+          const int c = nw + j * 32;
+          if (m > c) continue;
+          const double x = 0.5 * inv * (double)acc[i][j][r];
+          if (m == c) {
+            it.xdiag[m] = x;
+            split_store(-it.w[m] * x * sy, it.yh + (size_t)m * n + m, it.yl + (size_t)m * n + m);
+          } else {
+            const double y = fermi_divided_difference(em, fm, fcm, en[j], fn[j], fcn[j], beta) * x * sy;
+            split_store(y, it.yh + (size_t)m * n + c, it.yl + (size_t)m * n + c);
+            split_store(y, it.yh + (size_t)c * n + m, it.yl + (size_t)c * n + m);
+          }
+        }
+      }
+  } else {  // EPI_MULLIKEN
+    const int p = tile.y * Cfg::WAVES_N + wn;
+#pragma unroll
+    for (int i = 0; i < WTM; ++i)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = mw + i * 32 + 8 * (r / 4) + (r % 4);
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < WTN; ++j) s += (double)acc[i][j][r] * it.g[(size_t)m * n + nw + j * 32];
+        s *= inv;
+        s += __shfl_xor(s, 1);
+        s += __shfl_xor(s, 2);
+        s += __shfl_xor(s, 4);
+        s += __shfl_xor(s, 8);
+        s += __shfl_xor(s, 16);
+        if (l32 == 0) it.part[(size_t)p * n + m] = s;
+      }
+  }
+}
+
+using MCfg128x128 = MixedCfg<128, 128, 32, 2, 2, 2>;
+using MCfg128x128k64 = MixedCfg<128, 128, 64, 2, 2, 1>;
+using MCfg256x128 = MixedCfg<256, 128, 32, 4, 2, 1>;
+
+#ifndef KK_MFWD_CFG
+#define KK_MFWD_CFG MCfg128x128
+#endif
+#ifndef KK_MBACK_CFG
+#define KK_MBACK_CFG MCfg128x128
+#endif
+using MFwdCfg = KK_MFWD_CFG;
+using MBackCfg = KK_MBACK_CFG;
+
+// ---------------------------------------------------------------------------
+// Split helpers
+
+// dst_hi/lo[r][c] = split(scale * src[r][c] (or src[c][r] if transpose)), all np x np.
+__global__ void split_matrix(const double* __restrict__ src, int np, int transpose, const double* __restrict__ scale_p,
+                             _Float16* __restrict__ hi, _Float16* __restrict__ lo) {
+  __shared__ double t[32][33];
+  const double s = *scale_p;
+  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  if (transpose) {
+    for (int k = ty; k < 32; k += 8) t[k][tx] = src[(size_t)(bx + k) * np + by + tx];
+    __syncthreads();
+    for (int k = ty; k < 32; k += 8) {
+      const size_t o = (size_t)(by + k) * np + bx + tx;
+      split_store(s * t[tx][k], hi + o, lo + o);
+    }
+  } else {
+    for (int k = ty; k < 32; k += 8) {
+      const size_t o = (size_t)(by + k) * np + bx + tx;
+      split_store(s * src[o], hi + o, lo + o);
+    }
+  }
+}
+
+// Row-scaled split for the forward A operands: dst[r][c] = split(sc * u[c] * src[r][c]),
+// src = C^T or G^T in FP64 (row r = eigenstate, column c = orbital).
+__global__ void split_scaled_columns(const double* __restrict__ src, int np, const double* __restrict__ u,
+                                     const double* __restrict__ sc_p, _Float16* __restrict__ hi,
+                                     _Float16* __restrict__ lo, const int* __restrict__ stop) {
+  if (stop != nullptr && *stop != 0) return;
+  const double s = *sc_p;
+  const size_t total = (size_t)np * np;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+    const int c = (int)(i % np);
+    split_store(s * u[c] * src[i], hi + i, lo + i);
+  }
+}
+
+// Per-row max |x| and sum x^2 of an np x np FP64 matrix (one block per row).
+__global__ void row_stats(const double* __restrict__ m, int np, double* __restrict__ rmax,
+                          double* __restrict__ rnorm2) {
+  __shared__ double sh[17];
+  __shared__ double shm[1024];
+  const double* row = m + (size_t)blockIdx.x * np;
+  double mx = 0.0, s2 = 0.0;
+  for (int c = threadIdx.x; c < np; c += blockDim.x) {
+    const double v = row[c];
+    mx = fmax(mx, fabs(v));
+    s2 += v * v;
+  }
+  s2 = block_sum(s2, sh);
+  shm[threadIdx.x] = mx;
+  __syncthreads();
+  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) shm[threadIdx.x] = fmax(shm[threadIdx.x], shm[threadIdx.x + st]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    rmax[blockIdx.x] = shm[0];
+    rnorm2[blockIdx.x] = s2;
+  }
+}
+
+__device__ __forceinline__ double pow2_scale(double bound, int top) {
+  // largest power of two s with s * bound <= 2^top (1 if bound is 0)
+  if (!(bound > 0.0)) return 1.0;
+  return ldexp(1.0, top - (int)ceil(log2(bound)));
+}
+
+// Reduce row statistics of C^T and G^T (rows = columns of C and G) into the
+// per-spin constants: [0] s_C, [1] s_G, [2] max column norm of C, [3] of G.
+__global__ void const_scales(const double* __restrict__ cmax, const double* __restrict__ cn2,
+                             const double* __restrict__ gmax, const double* __restrict__ gn2, int np,
+                             double* __restrict__ out) {
+  __shared__ double sm[4][1024];
+  double a = 0, b = 0, c = 0, d = 0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) {
+    a = fmax(a, cmax[i]); b = fmax(b, gmax[i]); c = fmax(c, cn2[i]); d = fmax(d, gn2[i]);
+  }
+  sm[0][threadIdx.x] = a; sm[1][threadIdx.x] = b; sm[2][threadIdx.x] = c; sm[3][threadIdx.x] = d;
+  __syncthreads();
+  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st)
+      for (int q = 0; q < 4; ++q) sm[q][threadIdx.x] = fmax(sm[q][threadIdx.x], sm[q][threadIdx.x + st]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = pow2_scale(sm[0][0], 14);
+    out[1] = pow2_scale(sm[1][0], 14);
+    out[2] = sqrt(sm[2][0]);
+    out[3] = sqrt(sm[3][0]);
+  }
+}
+
+// Per response item z = 2 b + s: scales of the split operands. With
+// umax = max |u~|, s_u = 2^-ceil(log2 umax); |Y| <= (beta/4) umax ncC ncG bounds
+// the Hadamard product (|F| <= beta/4), giving s_Y. Writes
+//   msc[z*8 + 0] = 1/(s_C s_G s_u)  forward unscale
+//   msc[z*8 + 1] = s_Y              scale of the stored Y split
+//   msc[z*8 + 2] = 1/(s_C s_Y)      back-transform unscale
+//   msc[z*8 + 3] = s_C s_u, [4] = s_G s_u  scales of the (U~ C)^T, (U~ G)^T splits
+__global__ void mixed_scales(const double* __restrict__ u, int np, const double* __restrict__ mconst,
+                             double beta, double* __restrict__ msc, const int* __restrict__ stop) {
+  if (stop != nullptr && *stop != 0) return;
+  __shared__ double sm[1024];
+  const int z = blockIdx.x, s = z & 1;
+  const double* uz = u + (size_t)z * np;
+  double mx = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) mx = fmax(mx, fabs(uz[i]));
+  sm[threadIdx.x] = mx;
+  __syncthreads();
+  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + st]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double umax = sm[0];
+    const double sC = mconst[s * 4 + 0], sG = mconst[s * 4 + 1];
+    const double su = pow2_scale(umax, 0);
+    const double sY = pow2_scale(0.25 * beta * umax * mconst[s * 4 + 2] * mconst[s * 4 + 3], 14);
+    msc[z * 8 + 0] = 1.0 / (sC * sG * su);
+    msc[z * 8 + 1] = sY;
+    msc[z * 8 + 2] = 1.0 / (sC * sY);
+    msc[z * 8 + 3] = sC * su;
+    msc[z * 8 + 4] = sG * su;
+  }
+}
+
+}  // namespace kk

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(PKG_DIR, "libkrylov_kernel.so")
 
 KK_OK, KK_BREAKDOWN = 0, 1
 KK_EINVAL, KK_ENOMEM, KK_EHIP, KK_ENOTPREPARED, KK_ESINGULAR = -1, -2, -3, -4, -5
-KK_FP64 = 0
+KK_FP64, KK_MIXED_F16 = 0, 1
 STATUS_NAMES = {0: "KK_OK", 1: "KK_BREAKDOWN", -1: "KK_EINVAL", -2: "KK_ENOMEM", -3: "KK_EHIP",
                 -4: "KK_ENOTPREPARED", -5: "KK_ESINGULAR"}
 
@@ -121,14 +121,14 @@ class Handle:
             pass
 
     def prepare(self, offsets, S, Z, Q_up, Q_dn, eps_up, eps_dn, gamma, W: float, kT: float,
-                n_electrons: float):
+                n_electrons: float, precision: int = KK_FP64):
         off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int32))
         n, nb = len(off) - 1, int(off[-1])
         _check(LIB.kk_prepare(
             self._h, n, off.ctypes.data_as(ctypes.c_void_p), nb,
             _dev(S, "S", nb * nb), _dev(Z, "Z", nb * nb), _dev(Q_up, "Q_up", nb * nb),
             _dev(Q_dn, "Q_dn", nb * nb), _dev(eps_up, "eps_up", nb), _dev(eps_dn, "eps_dn", nb),
-            _dev(gamma, "gamma", n * n), float(W), float(kT), float(n_electrons), KK_FP64),
+            _dev(gamma, "gamma", n * n), float(W), float(kT), float(n_electrons), int(precision)),
             "kk_prepare")
         self.n_atoms, self.n_basis = n, nb
         return self

@@ -34,11 +34,13 @@ Recipe (all energies in eV, lengths in Angstrom unless stated):
   * W = -0.015 Hartree (one Stoner constant for all atoms and shells).
   * N_e = 8 valence electrons per atom over both spins.
   * delta (charge then magnetization, length 2N): iid N(0, 0.01).
-  * expansion point n_ref = (n_q, n_m): n_q iid N(0, 0.05), n_m = 2.2 + iid
-    N(0, 0.1) per atom, so that the two spin Hamiltonians have different
-    eigenvectors (a uniform moment would only shift the spectrum rigidly).
+  * expansion point n_ref = (n_q, n_m): neutral atoms n_q = 0 and moments
+    n_m = 2.2 + iid N(0, 0.1) per atom, so that the two spin Hamiltonians have
+    different eigenvectors (a uniform moment would only shift the spectrum
+    rigidly). Random charges are avoided because the unscreened gamma turns
+    them into onsite potentials of several eV in large cells.
   Draw order from numpy PCG64 default_rng(seed): displacements, onsite,
-  H blocks, S blocks, delta, n_q, n_m.
+  H blocks, S blocks, delta, n_m.
 
 Clusters (open boundaries) take the n sites of an 8x8x8-cell bcc lattice
 nearest its centre (ties broken by site index) and use no images.
@@ -139,7 +141,7 @@ def make_system(n_cells: int | None = None, *, n_atoms: int | None = None, seed:
     hvals = rng.standard_normal((iu_i.size, 45))
     svals = rng.standard_normal((iu_i.size, 45))
     delta = rng.normal(0.0, 0.01, size=2 * n)
-    n_q = rng.normal(0.0, 0.05, size=n)
+    n_q = np.zeros(n)
     n_m = 2.2 + rng.normal(0.0, 0.1, size=n)
     if uniform_moment:
         n_q = np.zeros(n)

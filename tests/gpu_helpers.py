@@ -13,24 +13,24 @@ def t(x):
     return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=DEV)
 
 
-def handle_from_expansion(sysd: dict, ep: dict):
+def handle_from_expansion(sysd: dict, ep: dict, precision: int = 0):
     """HIP handle prepared with the oracle's own Z, Q, eps (identical inputs)."""
     from paper_2303_03529_amd import krylov
     h = krylov.Handle()
     h.prepare(sysd["offsets"], t(sysd["S"]), t(ep["Z"]), t(ep["Q"][0]), t(ep["Q"][1]),
               t(ep["eps"][0]), t(ep["eps"][1]), t(sysd["gamma"]), sysd["W"], sysd["kT"],
-              sysd["n_electrons"])
+              sysd["n_electrons"], precision)
     return h
 
 
-def handle_from_device_setup(sysd: dict):
+def handle_from_device_setup(sysd: dict, precision: int = 0):
     """HIP handle prepared from a device-side eigensolve (independent of the oracle)."""
     from paper_2303_03529_amd import krylov
     from paper_2303_03529_amd.caller_setup import expansion_point_device
     e = expansion_point_device(sysd, DEV)
     h = krylov.Handle()
     h.prepare(sysd["offsets"], e["S"], e["Z"], e["Q_up"], e["Q_dn"], e["eps_up"], e["eps_dn"],
-              e["gamma"], sysd["W"], sysd["kT"], sysd["n_electrons"])
+              e["gamma"], sysd["W"], sysd["kT"], sysd["n_electrons"], precision)
     del e
     return h
 

@@ -27,6 +27,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 FP64_MFMA_PEAK_TFLOPS = 78.6
+FP16_MFMA_PEAK_TFLOPS = 2500.0  # dense; the split form spends three FP16 products per FP64 product
 HBM_PEAK_GBS = 8000.0
 
 
@@ -39,6 +40,8 @@ def parse():
     ap.add_argument("--rank", type=int, default=12)
     ap.add_argument("--seed", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
+                    help="transform arithmetic: FP64 MFMA, or FP16 x 3 split products")
     ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "traffic_fp64_1024.json"))
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB elementwise copy kernel 3 times (scales HBM counters)")
@@ -100,9 +103,21 @@ def main():
     sysd = make_system(args.cells, seed=args.seed)
     N, nb, m = sysd["n_atoms"], sysd["n_basis"], args.rank
     e = expansion_point_device(sysd, dev)
+    prec = krylov.KK_FP64 if args.precision == "fp64" else krylov.KK_MIXED_F16
     h = krylov.Handle()
     h.prepare(sysd["offsets"], e["S"], e["Z"], e["Q_up"], e["Q_dn"], e["eps_up"], e["eps_dn"],
-              e["gamma"], sysd["W"], sysd["kT"], sysd["n_electrons"])
+              e["gamma"], sysd["W"], sysd["kT"], sysd["n_electrons"], prec)
+    ref = None
+    if prec != krylov.KK_FP64:
+        # FP64 path on the same prepared inputs, for the error of the split-precision form
+        h64 = krylov.Handle()
+        h64.prepare(sysd["offsets"], e["S"], e["Z"], e["Q_up"], e["Q_dn"], e["eps_up"], e["eps_dn"],
+                    e["gamma"], sysd["W"], sysd["kT"], sysd["n_electrons"], krylov.KK_FP64)
+        d64 = torch.as_tensor(sysd["delta"], dtype=torch.float64, device=dev)
+        ref, _ = h64.krylov_kernel_apply(d64, args.rank)
+        ref = ref.cpu().numpy()
+        h64.close()
+        del h64
     del e
     torch.cuda.empty_cache()
     delta = torch.as_tensor(sysd["delta"], dtype=torch.float64, device=dev)
@@ -133,6 +148,9 @@ def main():
     h.profile_enable(False)
     _, info = h.krylov_kernel_apply(delta, m, out=out, info=True)
     assert info.rank_used == m, info
+    err_vs_fp64 = None
+    if ref is not None:
+        err_vs_fp64 = float(np.linalg.norm(out.cpu().numpy() - ref) / np.linalg.norm(ref))
 
     elapsed = t1 - t0
     value = args.steps / elapsed
@@ -145,14 +163,15 @@ def main():
     avg_ms = kernels[dom][0]
     achieved = flops_launch / (avg_ms * 1e-3) / 1e12
     traffic = None
-    if os.path.exists(args.traffic_file):
+    if prec == krylov.KK_FP64 and os.path.exists(args.traffic_file):
         tr = json.load(open(args.traffic_file))
         if (tr.get("kernel") == dom and tr.get("n_basis") == nb
                 and tr.get("source_digest") == gemm_source_digest()):
             traffic = tr.get("bytes_per_launch")
+    peak = FP64_MFMA_PEAK_TFLOPS if prec == krylov.KK_FP64 else FP16_MFMA_PEAK_TFLOPS / 3.0
     roofline = {
-        "bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_MFMA_PEAK_TFLOPS,
-        "unit": "TFLOP/s", "frac": round(achieved / FP64_MFMA_PEAK_TFLOPS, 4), "traffic": traffic,
+        "bound": "mfma", "achieved": round(achieved, 3), "peak": round(peak, 2),
+        "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": traffic,
         "kernel": dom, "avg_launch_ms": round(avg_ms, 4),
         "flops_per_launch": flops_launch,
         "other_kernel_avg_ms": {k: round(v[0], 4) for k, v in kernels.items() if k != dom},
@@ -169,13 +188,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if prec == krylov.KK_FP64 else "f16x3+f64",
         "data": "synthetic",
         "config": {"workload": f"bcc Fe {N} atoms ({args.cells}^3 cells), Nb={nb}, rank m={m}, "
-                               "FP64 path, K0=-I",
+                               f"{'FP64' if prec == krylov.KK_FP64 else 'split FP16x3'} transforms, K0=-I",
                    "n_atoms": N, "n_basis": nb, "rank": m, "seed": args.seed},
         "update_tflops": update_flops / (elapsed / args.steps) / 1e12,
-        "mfma_util_update": update_flops / (elapsed / args.steps) / 1e12 / FP64_MFMA_PEAK_TFLOPS,
+        "mfma_util_update": update_flops / (elapsed / args.steps) / 1e12 / peak,
+        "err_vs_fp64": err_vs_fp64,
         "roofline": roofline,
         "cpu_baseline": None,
     }

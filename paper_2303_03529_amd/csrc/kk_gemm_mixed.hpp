@@ -49,20 +49,20 @@ struct MixedArgs {
   MixedItem item[MAX_GEMM_BATCH];
 };
 
-template <int BM_, int BN_, int BK_, int WAVES_M_, int WAVES_N_, int MINB_>
+template <int BM_, int BN_, int BK_, int WAVES_M_, int WAVES_N_, int MINB_, int FLUSH_ = 0>
 struct MixedCfg {
   static constexpr int BM = BM_, BN = BN_, BK = BK_;
+  // FLUSH > 0: accumulate FLUSH stages in a fresh FP32 accumulator, then add it
+  // to a running FP32 total (two-level summation, smaller rounding growth).
+  static constexpr int FLUSH = FLUSH_;
   static constexpr int WAVES_M = WAVES_M_, WAVES_N = WAVES_N_;
   static constexpr int THREADS = 64 * WAVES_M * WAVES_N;
   static constexpr int WTM = BM / WAVES_M / 32;
   static constexpr int WTN = BN / WAVES_N / 32;
   static constexpr int MIN_BLOCKS = MINB_;
   static constexpr int KP = BK + 8;                 // padded LDS row (halves)
-  static constexpr int CHUNKS = (BM + BN) * BK / 8 * 2;  // 16-byte pieces per stage (hi + lo)
-  static constexpr int PER_THREAD = CHUNKS / THREADS;
   static_assert(BM % (32 * WAVES_M) == 0 && BN % (32 * WAVES_N) == 0, "wave tiling");
   static_assert(BK % 16 == 0, "BK");
-  static_assert(CHUNKS % THREADS == 0, "staging split");
   static_assert(MIXED_PAD % BM == 0 && MIXED_PAD % BN == 0, "tile must divide the padding");
 };
 
@@ -75,7 +75,7 @@ __device__ __forceinline__ void split_store(double v, _Float16* hi, _Float16* lo
 template <int EPI, class Cfg>
 __global__ __launch_bounds__(Cfg::THREADS, Cfg::MIN_BLOCKS) void gemm_mixed(const MixedArgs args) {
   constexpr int BM = Cfg::BM, BN = Cfg::BN, BK = Cfg::BK, KP = Cfg::KP;
-  constexpr int WTM = Cfg::WTM, WTN = Cfg::WTN, PT = Cfg::PER_THREAD;
+  constexpr int WTM = Cfg::WTM, WTN = Cfg::WTN;
   constexpr int CPR = BK / 8;  // 16-byte chunks per row per matrix
 
   if (args.stop != nullptr && *args.stop != 0) return;
@@ -98,17 +98,41 @@ __global__ __launch_bounds__(Cfg::THREADS, Cfg::MIN_BLOCKS) void gemm_mixed(cons
   const int l32 = lane & 31, lh = lane >> 5;
 
   f16x acc[WTM][WTN];
+  f16x tot[Cfg::FLUSH > 0 ? WTM : 1][Cfg::FLUSH > 0 ? WTN : 1];
 #pragma unroll
   for (int i = 0; i < WTM; ++i)
 #pragma unroll
     for (int j = 0; j < WTN; ++j)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+  if constexpr (Cfg::FLUSH > 0) {
+#pragma unroll
+    for (int i = 0; i < WTM; ++i)
+#pragma unroll
+      for (int j = 0; j < WTN; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) tot[i][j][r] = 0.f;
+  }
 
-  h8 stage[PT];
+  // Staging: each thread moves APM 16-byte pieces of A_hi and of A_lo, and BPM
+  // of B_hi and B_lo, per stage. Offsets are fixed for the whole K loop.
+  constexpr int APM = BM * CPR / Cfg::THREADS, BPM = BN * CPR / Cfg::THREADS;
+  static_assert(APM * Cfg::THREADS == BM * CPR && BPM * Cfg::THREADS == BN * CPR, "piece split");
+  int aoff[APM], boff[BPM], alds[APM], blds[BPM];
+#pragma unroll
+  for (int p = 0; p < APM; ++p) {
+    const int c = tid + p * Cfg::THREADS, row = c / CPR, ch = c % CPR;
+    aoff[p] = (m0 + row) * n + ch * 8;
+    alds[p] = row * KP + ch * 8;
+  }
+#pragma unroll
+  for (int p = 0; p < BPM; ++p) {
+    const int c = tid + p * Cfg::THREADS, row = c / CPR, ch = c % CPR;
+    boff[p] = (n0 + row) * n + ch * 8;
+    blds[p] = row * KP + ch * 8;
+  }
+  h8 sah[APM], sal[APM], sbh[BPM], sbl[BPM];
 
-  // Piece p of this thread: c = tid + p*THREADS enumerates (matrix, hi/lo, row, chunk)
-  // with A pieces first: [hi rows BM][lo rows BM] then B: [hi rows BN][lo rows BN].
 #define KK_MLOAD(kt)                                                                         \
   {                                                                                          \
     int k0 = (kt) * BK;                                                                      \
@@ -116,28 +140,25 @@ __global__ __launch_bounds__(Cfg::THREADS, Cfg::MIN_BLOCKS) void gemm_mixed(cons
     if (args.two_halves && k0 >= args.k_half) {                                              \
       ah = it.a1h; al = it.a1l; bh = it.b1h; bl = it.b1l; k0 -= args.k_half;                 \
     }                                                                                        \
-    _Pragma("unroll") for (int p = 0; p < PT; ++p) {                                         \
-      const int c = tid + p * Cfg::THREADS;                                                  \
-      const int row = c / CPR, ch = c % CPR;                                                 \
-      const _Float16* src;                                                                   \
-      if (row < BM) src = ah + (size_t)(m0 + row) * n;                                       \
-      else if (row < 2 * BM) src = al + (size_t)(m0 + row - BM) * n;                         \
-      else if (row < 2 * BM + BN) src = bh + (size_t)(n0 + row - 2 * BM) * n;               \
-      else src = bl + (size_t)(n0 + row - 2 * BM - BN) * n;                                  \
-      stage[p] = *reinterpret_cast<const h8*>(src + k0 + ch * 8);                            \
+    ah += k0; al += k0; bh += k0; bl += k0;                                                  \
+    _Pragma("unroll") for (int p = 0; p < APM; ++p) {                                        \
+      sah[p] = *reinterpret_cast<const h8*>(ah + aoff[p]);                                   \
+      sal[p] = *reinterpret_cast<const h8*>(al + aoff[p]);                                   \
+    }                                                                                        \
+    _Pragma("unroll") for (int p = 0; p < BPM; ++p) {                                        \
+      sbh[p] = *reinterpret_cast<const h8*>(bh + boff[p]);                                   \
+      sbl[p] = *reinterpret_cast<const h8*>(bl + boff[p]);                                   \
     }                                                                                        \
   }
 #define KK_MSTORE(buf)                                                                       \
   {                                                                                          \
-    _Pragma("unroll") for (int p = 0; p < PT; ++p) {                                         \
-      const int c = tid + p * Cfg::THREADS;                                                  \
-      const int row = c / CPR, ch = c % CPR;                                                 \
-      _Float16* dst;                                                                         \
-      if (row < BM) dst = &As[buf][0][row][0];                                               \
-      else if (row < 2 * BM) dst = &As[buf][1][row - BM][0];                                 \
-      else if (row < 2 * BM + BN) dst = &Bs[buf][0][row - 2 * BM][0];                       \
-      else dst = &Bs[buf][1][row - 2 * BM - BN][0];                                          \
-      *reinterpret_cast<h8*>(dst + ch * 8) = stage[p];                                       \
+    _Pragma("unroll") for (int p = 0; p < APM; ++p) {                                        \
+      *reinterpret_cast<h8*>(&As[buf][0][0][0] + alds[p]) = sah[p];                          \
+      *reinterpret_cast<h8*>(&As[buf][1][0][0] + alds[p]) = sal[p];                          \
+    }                                                                                        \
+    _Pragma("unroll") for (int p = 0; p < BPM; ++p) {                                        \
+      *reinterpret_cast<h8*>(&Bs[buf][0][0][0] + blds[p]) = sbh[p];                          \
+      *reinterpret_cast<h8*>(&Bs[buf][1][0][0] + blds[p]) = sbl[p];                          \
     }                                                                                        \
   }
 
@@ -165,20 +186,46 @@ __global__ __launch_bounds__(Cfg::THREADS, Cfg::MIN_BLOCKS) void gemm_mixed(cons
         bh[j] = *reinterpret_cast<const h8*>(&Bs[buf][0][r][kofs]);
         bl[j] = *reinterpret_cast<const h8*>(&Bs[buf][1][r][kofs]);
       }
+      // the three products cycle over the accumulators so no MFMA waits on the previous one
 #pragma unroll
       for (int i = 0; i < WTM; ++i)
 #pragma unroll
-        for (int j = 0; j < WTN; ++j) {
+        for (int j = 0; j < WTN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(al[i], bh[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < WTM; ++i)
+#pragma unroll
+        for (int j = 0; j < WTN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < WTM; ++i)
+#pragma unroll
+        for (int j = 0; j < WTN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[i], bh[j], acc[i][j], 0, 0, 0);
-        }
+    }
+    if constexpr (Cfg::FLUSH > 0) {
+      if ((kt + 1) % Cfg::FLUSH == 0 || !more) {
+#pragma unroll
+        for (int i = 0; i < WTM; ++i)
+#pragma unroll
+          for (int j = 0; j < WTN; ++j) {
+            tot[i][j] += acc[i][j];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+          }
+      }
     }
     if (more) KK_MSTORE(buf ^ 1);
     __syncthreads();
   }
 #undef KK_MLOAD
 #undef KK_MSTORE
+  if constexpr (Cfg::FLUSH > 0) {
+#pragma unroll
+    for (int i = 0; i < WTM; ++i)
+#pragma unroll
+      for (int j = 0; j < WTN; ++j) acc[i][j] = tot[i][j];
+  }
 
   // Accumulator element (i, j, r) of this lane:
   //   m = m0 + wm*(BM/WAVES_M) + i*32 + 8*(r/4) + 4*lh + r%4,  n = n0 + wn*(BN/WAVES_N) + j*32 + l32.
@@ -236,14 +283,18 @@ __global__ __launch_bounds__(Cfg::THREADS, Cfg::MIN_BLOCKS) void gemm_mixed(cons
 }
 
 using MCfg128x128 = MixedCfg<128, 128, 32, 2, 2, 2>;
+using MCfg128x128f8 = MixedCfg<128, 128, 32, 2, 2, 2, 8>;
 using MCfg128x128k64 = MixedCfg<128, 128, 64, 2, 2, 1>;
 using MCfg256x128 = MixedCfg<256, 128, 32, 4, 2, 1>;
+using MCfg256x256 = MixedCfg<256, 256, 32, 2, 4, 1>;
+using MCfg256x256f8 = MixedCfg<256, 256, 32, 2, 4, 1, 8>;
+using MCfg128x256 = MixedCfg<128, 256, 32, 2, 4, 1>;
 
 #ifndef KK_MFWD_CFG
-#define KK_MFWD_CFG MCfg128x128
+#define KK_MFWD_CFG MCfg128x128f8
 #endif
 #ifndef KK_MBACK_CFG
-#define KK_MBACK_CFG MCfg128x128
+#define KK_MBACK_CFG MCfg128x128f8
 #endif
 using MFwdCfg = KK_MFWD_CFG;
 using MBackCfg = KK_MBACK_CFG;

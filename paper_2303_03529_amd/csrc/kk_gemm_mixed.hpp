@@ -61,6 +61,8 @@ struct MixedCfg {
   static constexpr int WTN = BN / WAVES_N / 32;
   static constexpr int MIN_BLOCKS = MINB_;
   static constexpr int KP = BK + 8;                 // padded LDS row (halves)
+  static_assert((KP / 8) % 2 == 1, "LDS row stride must be an odd number of 16-byte slots");
+  static_assert(64 % (BK / 8) == 0 && 16 % (BK / 8) == 0, "piece mapping");
   static_assert(BM % (32 * WAVES_M) == 0 && BN % (32 * WAVES_N) == 0, "wave tiling");
   static_assert(BK % 16 == 0, "BK");
   static_assert(MIXED_PAD % BM == 0 && MIXED_PAD % BN == 0, "tile must divide the padding");
@@ -119,15 +121,27 @@ __global__ __launch_bounds__(Cfg::THREADS, Cfg::MIN_BLOCKS) void gemm_mixed(cons
   constexpr int APM = BM * CPR / Cfg::THREADS, BPM = BN * CPR / Cfg::THREADS;
   static_assert(APM * Cfg::THREADS == BM * CPR && BPM * Cfg::THREADS == BN * CPR, "piece split");
   int aoff[APM], boff[BPM], alds[APM], blds[BPM];
+  // Piece c -> (row, chunk): CPR consecutive lanes share a row (coalesced loads),
+  // and the 16 lanes of one LDS write pass take rows r, r + 16/CPR, ... so that
+  // their 16-byte slots (row stride KP = odd multiple of 8 halves) hit distinct banks.
+  auto piece = [](int c, int& row, int& ch) __attribute__((always_inline)) {
+    constexpr int RPW = 64 / CPR;          // rows per wave-instruction
+    constexpr int RPP = 16 / CPR;          // rows per 16-lane pass
+    const int l = c % 64, q = l / CPR;
+    row = (c / 64) * RPW + (q % RPP) * (RPW / RPP) + q / RPP;
+    ch = l % CPR;
+  };
 #pragma unroll
   for (int p = 0; p < APM; ++p) {
-    const int c = tid + p * Cfg::THREADS, row = c / CPR, ch = c % CPR;
+    int row, ch;
+    piece(tid + p * Cfg::THREADS, row, ch);
     aoff[p] = (m0 + row) * n + ch * 8;
     alds[p] = row * KP + ch * 8;
   }
 #pragma unroll
   for (int p = 0; p < BPM; ++p) {
-    const int c = tid + p * Cfg::THREADS, row = c / CPR, ch = c % CPR;
+    int row, ch;
+    piece(tid + p * Cfg::THREADS, row, ch);
     boff[p] = (n0 + row) * n + ch * 8;
     blds[p] = row * KP + ch * 8;
   }

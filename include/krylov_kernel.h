@@ -59,10 +59,11 @@ typedef enum {
 typedef enum { KK_FP64 = 0, KK_MIXED_F16 = 1 } kk_precision;
 
 typedef struct {
-  int rank_used;     /* number of Krylov directions actually used (<= m)          */
-  int status;        /* KK_OK, KK_BREAKDOWN or KK_ESINGULAR                        */
-  double min_pivot;  /* smallest Cholesky pivot of O (squared diagonal of L)       */
-  double max_pivot;  /* largest Cholesky pivot of O                                */
+  int rank_used;       /* number of Krylov directions actually used (<= m)          */
+  int status;          /* KK_OK, KK_BREAKDOWN or KK_ESINGULAR                        */
+  double min_pivot;    /* smallest Cholesky pivot of O (squared diagonal of L)       */
+  double max_pivot;    /* largest Cholesky pivot of O                                */
+  double ls_residual;  /* ||F~ c - f~|| / ||f~||: residual of the projected problem  */
 } kk_info;
 
 /* Create a handle bound to hip_stream (a hipStream_t; NULL = the null stream).
@@ -139,6 +140,42 @@ kk_status mulliken_project(kk_handle h, int batch, const double *dD_up, const do
  */
 kk_status krylov_kernel_apply(kk_handle h, const double *delta, int m, const double *K0,
                               double *Kdelta, kk_info *info);
+
+/*
+ * krylov_kernel_apply_adaptive -- the same kernel with the rank chosen on the
+ * device: directions are added one at a time (at most m_max) and the expansion
+ * stops as soon as the projected residual ||F~ c - f~|| / ||f~|| is <= tol, the
+ * residual the rank-k kernel leaves in the preconditioned Newton step. This is
+ * the adaptive low-rank update used for SCF acceleration (Sec. III.C; the paper
+ * uses 2-3 ranks per step and defers the criterion to earlier work, so this
+ * criterion is this library's). tol = 0 behaves like krylov_kernel_apply.
+ * Arguments and errors as krylov_kernel_apply; info->rank_used reports the rank.
+ */
+kk_status krylov_kernel_apply_adaptive(kk_handle h, const double *delta, int m_max, double tol,
+                                       const double *K0, double *Kdelta, kk_info *info);
+
+/*
+ * kk_ground_state_charges -- the ground-state map q[n] at the prepared
+ * expansion point (Sec. II.C, III.A): Mulliken populations of
+ * D^sigma = C^sigma f^sigma C^sigma^T, written as (q, m) = (n_up + n_dn - ref,
+ * n_up - n_dn) to qm (device, 2N). reference (device, N, or NULL for none) is
+ * the neutral-atom electron count of each atom, the Mulliken contribution of
+ * D0, so the charges come out as net charges.
+ */
+kk_status kk_ground_state_charges(kk_handle h, const double *reference, double *qm);
+
+/*
+ * kk_xlbomd_update -- extended-Lagrangian integration step for the electronic
+ * coordinates (Sec. II.F, modified Verlet with weak dissipation):
+ *   n(t+dt) = 2 n(t) - n(t-dt) - kappa Kf + alpha sum_{k=0..k_max} c_k n(t - k dt)
+ *   n_hist  device, (k_max+1) x 2N, row k = n(t - k dt) (k_max >= 1 needs two rows)
+ *   Kf      device 2N: the kernel applied to the residual q[n(t)] - n(t)
+ *   kappa   dt^2 omega^2;  alpha, c (device, k_max+1): dissipation coefficients
+ *   n_new   device 2N output (must not overlap n_hist)
+ * The paper takes kappa, alpha and c_k from earlier work; they are inputs here.
+ */
+kk_status kk_xlbomd_update(kk_handle h, const double *n_hist, int k_max, const double *Kf, double kappa,
+                           double alpha, const double *c, double *n_new);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char *kk_last_error(void);

@@ -39,16 +39,37 @@ def _apply_k0(K0, x):
     return -x if K0 is None else K0 @ x
 
 
+def _projected_solve(Fm, ftilde):
+    """c minimizing ||F~ c - f~|| via the normal equations O c = F~^T f~ (Cholesky)."""
+    O = Fm.T @ Fm
+    rhs = Fm.T @ ftilde
+    try:
+        c = sla.cho_solve(sla.cho_factor(O, lower=True), rhs)
+        solver = "cholesky"
+    except np.linalg.LinAlgError:
+        c = np.linalg.lstsq(Fm, ftilde, rcond=None)[0]
+        solver = "lstsq"
+    res = np.linalg.norm(Fm @ c - ftilde) / np.linalg.norm(ftilde)
+    return c, O, solver, res
+
+
 def kernel_apply(sysd: dict, ep: dict, delta: np.ndarray, m: int, K0: np.ndarray | None = None,
-                 return_parts: bool = False):
-    """K delta ~ (K0 J)^-1 K0 delta with a rank-m Krylov basis."""
+                 return_parts: bool = False, tol: float = 0.0):
+    """K delta ~ (K0 J)^-1 K0 delta with a rank-m Krylov basis.
+
+    tol > 0 chooses the rank adaptively: after each new direction the projected
+    problem is solved and the expansion stops once ||F~ c - f~|| / ||f~|| <= tol
+    (at most m directions). Sec. III.C uses a few ranks per SCF step chosen
+    adaptively; this residual criterion is our reading.
+    """
     delta = np.asarray(delta, dtype=np.float64)
     ftilde = _apply_k0(K0, delta)
     nrm0 = np.linalg.norm(ftilde)
     V, Ft, Q1 = [], [], []
     if nrm0 == 0.0:
         out = np.zeros_like(delta)
-        return (out, dict(V=V, Ft=Ft, q1=Q1, rank=0, c=np.zeros(0), O=np.zeros((0, 0)))) if return_parts else out
+        return (out, dict(V=V, Ft=Ft, q1=Q1, rank=0, c=np.zeros(0), O=np.zeros((0, 0)),
+                          ls_residual=0.0)) if return_parts else out
     r = ftilde
     for k in range(m):
         w = r.copy()
@@ -67,20 +88,17 @@ def kernel_apply(sysd: dict, ep: dict, delta: np.ndarray, m: int, K0: np.ndarray
         Ft.append(ftk)
         Q1.append(q1)
         r = ftk
+        if tol > 0.0 and len(V) < m:
+            if _projected_solve(np.array(Ft).T, ftilde)[3] <= tol:
+                break
     rank = len(V)
     Vm = np.array(V).T                    # 2N x rank
     Fm = np.array(Ft).T
-    O = Fm.T @ Fm
-    rhs = Fm.T @ ftilde
-    try:
-        c = sla.cho_solve(sla.cho_factor(O, lower=True), rhs)
-        solver = "cholesky"
-    except np.linalg.LinAlgError:
-        c = np.linalg.lstsq(Fm, ftilde, rcond=None)[0]
-        solver = "lstsq"
+    c, O, solver, res = _projected_solve(Fm, ftilde)
     out = Vm @ c
     if return_parts:
-        return out, dict(V=Vm, Ft=Fm, q1=np.array(Q1).T, rank=rank, c=c, O=O, solver=solver)
+        return out, dict(V=Vm, Ft=Fm, q1=np.array(Q1).T, rank=rank, c=c, O=O, solver=solver,
+                         ls_residual=res)
     return out
 
 

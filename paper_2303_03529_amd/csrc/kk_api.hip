@@ -88,6 +88,7 @@ struct kk_handle_s {
   _Float16 *uct_h = nullptr, *uct_l = nullptr, *ugt_h = nullptr, *ugt_l = nullptr;
   _Float16 *yh = nullptr, *yl = nullptr;
   double* msc = nullptr;
+  double* mscratch = nullptr;  // 4 np doubles: row statistics for the split scales
 
   // response workspace (grown on demand)
   int chunk_cap = 0;
@@ -368,21 +369,79 @@ kk_status check_handle(kk_handle h) {
   return KK_OK;
 }
 
+// Every device buffer of a prepared handle for its (natoms, np, precision),
+// plus the tile tables (which depend only on np).
+kk_status allocate_prepared(kk_handle h) {
+  const int np = h->np, n_atoms = h->natoms;
+  const size_t np2 = (size_t)np * np;
+  kk_status st;
+  if ((st = dalloc_t(h, &h->S, np2))) return st;
+  for (int s = 0; s < 2; ++s) {
+    if ((st = dalloc_t(h, &h->C[s], np2))) return st;
+    if ((st = dalloc_t(h, &h->CT[s], np2))) return st;
+    if ((st = dalloc_t(h, &h->G[s], np2))) return st;
+    if ((st = dalloc_t(h, &h->eps[s], np))) return st;
+    if ((st = dalloc_t(h, &h->f[s], np))) return st;
+    if ((st = dalloc_t(h, &h->fc[s], np))) return st;
+    if ((st = dalloc_t(h, &h->w[s], np))) return st;
+  }
+  if ((st = dalloc_t(h, &h->gamma, (size_t)n_atoms * n_atoms))) return st;
+  if ((st = dalloc_t(h, &h->t, (size_t)2 * n_atoms))) return st;
+  if ((st = dalloc_t(h, &h->mu, 1))) return st;
+  if ((st = dalloc_t(h, &h->wsum, 1))) return st;
+  if ((st = dalloc_t(h, &h->offsets, (size_t)n_atoms + 1))) return st;
+  std::vector<int2> up = tile_order(np, kk::FwdCfg::BM, kk::FwdCfg::BN, true);
+  std::vector<int2> full = tile_order(np, kk::BackCfg::BM, kk::BackCfg::BN, false);
+  std::vector<int2> stt = tile_order(np, kk::StoreCfg::BM, kk::StoreCfg::BN, false);
+  h->n_upper = (int)up.size();
+  h->n_full = (int)full.size();
+  h->n_store = (int)stt.size();
+  if ((st = dalloc_t(h, &h->tiles_upper, up.size()))) return st;
+  if ((st = dalloc_t(h, &h->tiles_full, full.size()))) return st;
+  if ((st = dalloc_t(h, &h->tiles_store, stt.size()))) return st;
+  const int n2 = 2 * n_atoms;
+  if ((st = dalloc_t(h, &h->V, (size_t)kk::MAX_RANK * n2))) return st;
+  if ((st = dalloc_t(h, &h->Ft, (size_t)kk::MAX_RANK * n2))) return st;
+  if ((st = dalloc_t(h, &h->ftilde, (size_t)n2))) return st;
+  if ((st = dalloc_t(h, &h->q1, (size_t)n2))) return st;
+  if ((st = dalloc_t(h, &h->kst, 1))) return st;
+  HIP_OR_FAIL(hipMemcpyAsync(h->tiles_upper, up.data(), sizeof(int2) * up.size(), hipMemcpyHostToDevice,
+                             h->stream));
+  HIP_OR_FAIL(hipMemcpyAsync(h->tiles_full, full.data(), sizeof(int2) * full.size(), hipMemcpyHostToDevice,
+                             h->stream));
+  HIP_OR_FAIL(hipMemcpyAsync(h->tiles_store, stt.data(), sizeof(int2) * stt.size(), hipMemcpyHostToDevice,
+                             h->stream));
+  if (h->precision == KK_MIXED_F16) {
+    if ((st = dalloc_t(h, &h->mconst, 8))) return st;
+    if ((st = dalloc_t(h, &h->mscratch, (size_t)4 * np))) return st;
+    for (int s = 0; s < 2; ++s) {
+      if ((st = dalloc_t(h, &h->GT[s], np2))) return st;
+      for (_Float16** q : {&h->Ch[s], &h->Cl[s], &h->CTh[s], &h->CTl[s], &h->GTh[s], &h->GTl[s]})
+        if ((st = dalloc_t(h, q, np2))) return st;
+    }
+    std::vector<int2> mup = tile_order(np, kk::MFwdCfg::BM, kk::MFwdCfg::BN, true);
+    std::vector<int2> mfull = tile_order(np, kk::MBackCfg::BM, kk::MBackCfg::BN, false);
+    h->n_mupper = (int)mup.size();
+    h->n_mfull = (int)mfull.size();
+    if ((st = dalloc_t(h, &h->mtiles_upper, mup.size()))) return st;
+    if ((st = dalloc_t(h, &h->mtiles_full, mfull.size()))) return st;
+    HIP_OR_FAIL(hipMemcpyAsync(h->mtiles_upper, mup.data(), sizeof(int2) * mup.size(), hipMemcpyHostToDevice,
+                               h->stream));
+    HIP_OR_FAIL(hipMemcpyAsync(h->mtiles_full, mfull.data(), sizeof(int2) * mfull.size(),
+                               hipMemcpyHostToDevice, h->stream));
+  }
+  // the host tile vectors must outlive the copies
+  HIP_OR_FAIL(hipStreamSynchronize(h->stream));
+  return KK_OK;
+}
+
 // Split-precision operands, once per prepared expansion point: G^T (FP64) and
 // the FP16 splits of C, C^T, G^T with their power-of-two scales.
 kk_status prepare_mixed(kk_handle h) {
   const int np = h->np;
-  const size_t np2 = (size_t)np * np;
-  kk_status st;
-  if ((st = dalloc_t(h, &h->mconst, 8))) return st;
-  double *rmax = nullptr, *rn2 = nullptr;
-  if ((st = dalloc_t(h, &rmax, (size_t)4 * np))) return st;
-  rn2 = rmax + 2 * np;
-  std::vector<int2> up, full;
+  double* rmax = h->mscratch;
+  double* rn2 = rmax + 2 * np;
   for (int s = 0; s < 2; ++s) {
-    if ((st = dalloc_t(h, &h->GT[s], np2))) return st;
-    for (_Float16** q : {&h->Ch[s], &h->Cl[s], &h->CTh[s], &h->CTl[s], &h->GTh[s], &h->GTl[s]})
-      if ((st = dalloc_t(h, q, np2))) return st;
     dim3 pg(np / 32, np / 32), pb(256);
     kk::transpose_sq<<<pg, pb, 0, h->stream>>>(h->G[s], h->GT[s], np);
     LAUNCH_CHECK("transpose G");
@@ -398,17 +457,6 @@ kk_status prepare_mixed(kk_handle h) {
     kk::split_matrix<<<pg, pb, 0, h->stream>>>(h->GT[s], np, 0, h->mconst + 4 * s + 1, h->GTh[s], h->GTl[s]);
     LAUNCH_CHECK("split_matrix");
   }
-  up = tile_order(np, kk::MFwdCfg::BM, kk::MFwdCfg::BN, true);
-  full = tile_order(np, kk::MBackCfg::BM, kk::MBackCfg::BN, false);
-  h->n_mupper = (int)up.size();
-  h->n_mfull = (int)full.size();
-  if ((st = dalloc_t(h, &h->mtiles_upper, up.size()))) return st;
-  if ((st = dalloc_t(h, &h->mtiles_full, full.size()))) return st;
-  HIP_OR_FAIL(hipMemcpyAsync(h->mtiles_upper, up.data(), sizeof(int2) * up.size(), hipMemcpyHostToDevice,
-                             h->stream));
-  HIP_OR_FAIL(hipMemcpyAsync(h->mtiles_full, full.data(), sizeof(int2) * full.size(), hipMemcpyHostToDevice,
-                             h->stream));
-  HIP_OR_FAIL(hipStreamSynchronize(h->stream));
   return KK_OK;
 }
 
@@ -455,56 +503,23 @@ kk_status kk_prepare(kk_handle h, int n_atoms, const int* atom_offsets, int n_ba
     if (atom_offsets[a + 1] <= atom_offsets[a])
       return fail(KK_EINVAL, "kk_prepare: atom_offsets must be strictly increasing (atom %d)", a);
 
-  h->release();
   const bool mixed = precision == KK_MIXED_F16;
   const int pad = mixed ? kk::MIXED_PAD : kk::PAD;
   const int nb = n_basis, np = (nb + pad - 1) / pad * pad;
-  const size_t np2 = (size_t)np * np;
-  h->precision = precision;
-  h->natoms = n_atoms; h->nb = nb; h->np = np;
-  h->nparts = mixed ? (np / kk::MBackCfg::BN) * kk::MBackCfg::WAVES_N
-                    : (np / kk::BackCfg::BN) * kk::BackCfg::WAVES_N;
-  h->W = W; h->kT = kT; h->beta = 1.0 / kT; h->n_e = n_electrons;
-
+  // Re-preparing the same shape (an SCF or MD loop) reuses every buffer.
+  const bool reuse = h->prepared && h->natoms == n_atoms && h->nb == nb && h->precision == precision;
+  h->prepared = false;
   kk_status st;
-  if ((st = dalloc_t(h, &h->S, np2))) return st;
-  for (int s = 0; s < 2; ++s) {
-    if ((st = dalloc_t(h, &h->C[s], np2))) return st;
-    if ((st = dalloc_t(h, &h->CT[s], np2))) return st;
-    if ((st = dalloc_t(h, &h->G[s], np2))) return st;
-    if ((st = dalloc_t(h, &h->eps[s], np))) return st;
-    if ((st = dalloc_t(h, &h->f[s], np))) return st;
-    if ((st = dalloc_t(h, &h->fc[s], np))) return st;
-    if ((st = dalloc_t(h, &h->w[s], np))) return st;
+  if (!reuse) {
+    h->release();
+    h->precision = precision;
+    h->natoms = n_atoms; h->nb = nb; h->np = np;
+    h->nparts = mixed ? (np / kk::MBackCfg::BN) * kk::MBackCfg::WAVES_N
+                      : (np / kk::BackCfg::BN) * kk::BackCfg::WAVES_N;
+    if ((st = allocate_prepared(h))) return st;
   }
-  if ((st = dalloc_t(h, &h->gamma, (size_t)n_atoms * n_atoms))) return st;
-  if ((st = dalloc_t(h, &h->t, (size_t)2 * n_atoms))) return st;
-  if ((st = dalloc_t(h, &h->mu, 1))) return st;
-  if ((st = dalloc_t(h, &h->wsum, 1))) return st;
-  if ((st = dalloc_t(h, &h->offsets, (size_t)n_atoms + 1))) return st;
-  std::vector<int2> up = tile_order(np, kk::FwdCfg::BM, kk::FwdCfg::BN, true);
-  std::vector<int2> full = tile_order(np, kk::BackCfg::BM, kk::BackCfg::BN, false);
-  std::vector<int2> stt = tile_order(np, kk::StoreCfg::BM, kk::StoreCfg::BN, false);
-  h->n_upper = (int)up.size();
-  h->n_full = (int)full.size();
-  h->n_store = (int)stt.size();
-  if ((st = dalloc_t(h, &h->tiles_upper, up.size()))) return st;
-  if ((st = dalloc_t(h, &h->tiles_full, full.size()))) return st;
-  if ((st = dalloc_t(h, &h->tiles_store, stt.size()))) return st;
-  const int n2 = 2 * n_atoms;
-  if ((st = dalloc_t(h, &h->V, (size_t)kk::MAX_RANK * n2))) return st;
-  if ((st = dalloc_t(h, &h->Ft, (size_t)kk::MAX_RANK * n2))) return st;
-  if ((st = dalloc_t(h, &h->ftilde, (size_t)n2))) return st;
-  if ((st = dalloc_t(h, &h->q1, (size_t)n2))) return st;
-  if ((st = dalloc_t(h, &h->kst, 1))) return st;
-
+  h->W = W; h->kT = kT; h->beta = 1.0 / kT; h->n_e = n_electrons;
   HIP_OR_FAIL(hipMemcpyAsync(h->offsets, atom_offsets, sizeof(int) * (n_atoms + 1), hipMemcpyHostToDevice,
-                             h->stream));
-  HIP_OR_FAIL(hipMemcpyAsync(h->tiles_upper, up.data(), sizeof(int2) * up.size(), hipMemcpyHostToDevice,
-                             h->stream));
-  HIP_OR_FAIL(hipMemcpyAsync(h->tiles_full, full.data(), sizeof(int2) * full.size(), hipMemcpyHostToDevice,
-                             h->stream));
-  HIP_OR_FAIL(hipMemcpyAsync(h->tiles_store, stt.data(), sizeof(int2) * stt.size(), hipMemcpyHostToDevice,
                              h->stream));
   HIP_OR_FAIL(hipMemcpyAsync(h->gamma, gamma, sizeof(double) * n_atoms * n_atoms, hipMemcpyDeviceToDevice,
                              h->stream));
@@ -597,14 +612,19 @@ kk_status mulliken_project(kk_handle h, int batch, const double* dD_up, const do
   return KK_OK;
 }
 
-kk_status krylov_kernel_apply(kk_handle h, const double* delta, int m, const double* K0, double* Kdelta,
-                              kk_info* info) {
+}  // extern "C"
+
+namespace {
+
+kk_status krylov_run(kk_handle h, const char* who, const double* delta, int m, double tol, const double* K0,
+                     double* Kdelta, kk_info* info) {
   kk_status st = check_handle(h);
   if (st) return st;
   const int n2 = 2 * h->natoms;
-  if (!delta || !Kdelta) return fail(KK_EINVAL, "krylov_kernel_apply: NULL array argument");
+  if (!delta || !Kdelta) return fail(KK_EINVAL, "%s: NULL array argument", who);
   if (m < 1 || m > std::min(n2, kk::MAX_RANK))
-    return fail(KK_EINVAL, "krylov_kernel_apply: need 1 <= m <= min(2N, %d), got %d", kk::MAX_RANK, m);
+    return fail(KK_EINVAL, "%s: need 1 <= m <= min(2N, %d), got %d", who, kk::MAX_RANK, m);
+  if (!(tol >= 0.0)) return fail(KK_EINVAL, "%s: tolerance must be >= 0", who);
   if ((st = ensure_workspace(h, 1))) return st;
   const int* stop = &h->kst->stop;
   const int gv_threads = 256, gv_blocks = (n2 * kk::WAVE + gv_threads - 1) / gv_threads;
@@ -622,8 +642,12 @@ kk_status krylov_kernel_apply(kk_handle h, const double* delta, int m, const dou
     kk::precondition<<<gv_blocks, gv_threads, 0, h->stream>>>(K0, h->q1, vk, h->Ft + (size_t)k * n2, n2,
                                                                stop);
     LAUNCH_CHECK("precondition");
+    if (tol > 0.0 && k + 1 < m) {  // residual of the rank-(k+1) solve; may end the expansion
+      kk::krylov_solve<<<1, 1024, 0, h->stream>>>(h->V, h->Ft, h->ftilde, n2, h->kst, Kdelta, tol);
+      LAUNCH_CHECK("krylov_solve");
+    }
   }
-  kk::krylov_solve<<<1, 1024, 0, h->stream>>>(h->V, h->Ft, h->ftilde, n2, h->kst, Kdelta);
+  kk::krylov_solve<<<1, 1024, 0, h->stream>>>(h->V, h->Ft, h->ftilde, n2, h->kst, Kdelta, 0.0);
   LAUNCH_CHECK("krylov_solve");
   if (info) {
     kk::KrylovState hs;
@@ -633,10 +657,54 @@ kk_status krylov_kernel_apply(kk_handle h, const double* delta, int m, const dou
     info->status = hs.status;
     info->min_pivot = hs.min_pivot;
     info->max_pivot = hs.max_pivot;
+    info->ls_residual = hs.ls_residual;
     g_err.clear();
-    if (hs.status == KK_ESINGULAR) return fail(KK_ESINGULAR, "krylov_kernel_apply: Gram matrix not positive definite");
+    if (hs.status == KK_ESINGULAR) return fail(KK_ESINGULAR, "%s: Gram matrix not positive definite", who);
     return hs.status == 1 ? KK_BREAKDOWN : KK_OK;
   }
+  g_err.clear();
+  return KK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+kk_status krylov_kernel_apply(kk_handle h, const double* delta, int m, const double* K0, double* Kdelta,
+                              kk_info* info) {
+  return krylov_run(h, "krylov_kernel_apply", delta, m, 0.0, K0, Kdelta, info);
+}
+
+kk_status krylov_kernel_apply_adaptive(kk_handle h, const double* delta, int m_max, double tol,
+                                       const double* K0, double* Kdelta, kk_info* info) {
+  return krylov_run(h, "krylov_kernel_apply_adaptive", delta, m_max, tol, K0, Kdelta, info);
+}
+
+kk_status kk_ground_state_charges(kk_handle h, const double* reference, double* qm) {
+  kk_status st = check_handle(h);
+  if (st) return st;
+  if (!qm) return fail(KK_EINVAL, "kk_ground_state_charges: NULL output");
+  if ((st = ensure_workspace(h, 1))) return st;
+  const int N = h->natoms;
+  // populations per spin into the first 2N doubles of the response scratch
+  kk::atom_row_dots<<<N, 256, 0, h->stream>>>(h->C[0], h->C[1], h->np, h->G[0], h->G[1], h->np, h->f[0],
+                                               h->f[1], h->np, h->offsets, N, h->q1);
+  LAUNCH_CHECK("atom_row_dots");
+  kk::mix_spins<<<(N + 255) / 256, 256, 0, h->stream>>>(h->q1, reference, N, qm);
+  LAUNCH_CHECK("mix_spins");
+  g_err.clear();
+  return KK_OK;
+}
+
+kk_status kk_xlbomd_update(kk_handle h, const double* n_hist, int k_max, const double* Kf, double kappa,
+                           double alpha, const double* c, double* n_new) {
+  kk_status st = check_handle(h);
+  if (st) return st;
+  if (!n_hist || !Kf || !n_new || (k_max >= 0 && !c)) return fail(KK_EINVAL, "kk_xlbomd_update: NULL array argument");
+  if (k_max < 0 || k_max > 32) return fail(KK_EINVAL, "kk_xlbomd_update: need 0 <= k_max <= 32");
+  const int n2 = 2 * h->natoms;
+  kk::xlbomd_update<<<(n2 + 255) / 256, 256, 0, h->stream>>>(n_hist, k_max, n2, Kf, kappa, alpha, c, n_new);
+  LAUNCH_CHECK("xlbomd_update");
   g_err.clear();
   return KK_OK;
 }

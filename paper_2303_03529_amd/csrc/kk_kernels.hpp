@@ -268,16 +268,17 @@ __global__ void sum_two(const double* __restrict__ a, const double* __restrict__
 
 struct KrylovState {
   int rank;       // accepted directions
-  int stop;       // 1 after a breakdown (or a zero starting vector)
+  int stop;       // 1 after a breakdown, a zero starting vector or reaching the residual target
   int status;     // 0 ok, 1 breakdown, -5 singular Gram matrix
   int pad;
   double min_pivot, max_pivot;
+  double ls_residual;  // ||F~ c - f~|| / ||f~|| of the last solve
 };
 
 __global__ void krylov_reset(KrylovState* st) {
   if (threadIdx.x == 0) {
     st->rank = 0; st->stop = 0; st->status = 0; st->pad = 0;
-    st->min_pivot = 0.0; st->max_pivot = 0.0;
+    st->min_pivot = 0.0; st->max_pivot = 0.0; st->ls_residual = 1.0;
   }
 }
 
@@ -358,12 +359,15 @@ __global__ void __launch_bounds__(1024) krylov_orthonormalize(const double* __re
   if (threadIdx.x == 0) st->rank = rank + 1;
 }
 
-// O = F~^T F~, rhs = F~^T f~, Cholesky O = L L^T, c = O^-1 rhs, x = V c.
-// On a non-positive pivot x = 0 and status = -5. One block.
+// O = F~^T F~, rhs = F~^T f~, Cholesky O = L L^T, c = O^-1 rhs, x = V c, and the
+// projected residual ||F~ c - f~|| / ||f~|| formed explicitly. On a non-positive
+// pivot x = 0 and status = -5. With stop_tol > 0 a residual <= stop_tol ends the
+// expansion (used by the adaptive-rank call after each direction). One block.
 __global__ void __launch_bounds__(1024) krylov_solve(const double* __restrict__ V,
                                                      const double* __restrict__ Ft,
                                                      const double* __restrict__ ftilde, int n2,
-                                                     KrylovState* st, double* __restrict__ x) {
+                                                     KrylovState* st, double* __restrict__ x,
+                                                     double stop_tol) {
   __shared__ double sh[17];
   __shared__ double O[MAX_RANK][MAX_RANK + 1];
   __shared__ double c[MAX_RANK];
@@ -417,12 +421,53 @@ __global__ void __launch_bounds__(1024) krylov_solve(const double* __restrict__ 
     st->max_pivot = pmax;
   }
   __syncthreads();
+  double rr = 0.0, ff = 0.0;
   for (int i = threadIdx.x; i < n2; i += blockDim.x) {
-    double s = 0.0;
+    double s = 0.0, fi = 0.0;
     if (ok)
-      for (int k = 0; k < r; ++k) s += c[k] * V[(size_t)k * n2 + i];
+      for (int k = 0; k < r; ++k) {
+        s += c[k] * V[(size_t)k * n2 + i];
+        fi += c[k] * Ft[(size_t)k * n2 + i];
+      }
     x[i] = s;
+    const double e = fi - ftilde[i];
+    rr += e * e;
+    ff += ftilde[i] * ftilde[i];
   }
+  rr = block_sum(rr, sh);
+  ff = block_sum(ff, sh);
+  if (threadIdx.x == 0) {
+    const double res = ff > 0.0 ? sqrt(rr / ff) : 0.0;
+    st->ls_residual = res;
+    if (stop_tol > 0.0 && ok && res <= stop_tol) st->stop = 1;
+  }
+}
+
+// (q, m) Mulliken vector of per-spin atom populations: out = (p_up + p_dn - ref, p_up - p_dn),
+// ref = neutral-atom populations (may be null).
+__global__ void mix_spins(const double* __restrict__ p, const double* __restrict__ ref, int natoms,
+                          double* __restrict__ out) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= natoms) return;
+  const double u = p[a], d = p[natoms + a];
+  out[a] = u + d - (ref ? ref[a] : 0.0);
+  out[natoms + a] = u - d;
+}
+
+// Extended-Lagrangian update of the electronic coordinates (Sec. II.F):
+//   n(t+dt) = 2 n(t) - n(t-dt) - kappa K f + alpha sum_k c_k n(t - k dt),
+// hist[k] = n(t - k dt) for k = 0..kmax (row-major (kmax+1) x n2), Kf the
+// kernel applied to the residual f = q[n] - n, c on the device.
+__global__ void xlbomd_update(const double* __restrict__ hist, int kmax, int n2, const double* __restrict__ Kf,
+                              double kappa, double alpha, const double* __restrict__ c,
+                              double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n2) return;
+  const double n0 = hist[i];
+  const double n1 = kmax >= 1 ? hist[(size_t)n2 + i] : n0;
+  double diss = 0.0;
+  for (int k = 0; k <= kmax; ++k) diss += c[k] * hist[(size_t)k * n2 + i];
+  out[i] = 2.0 * n0 - n1 - kappa * Kf[i] + alpha * diss;
 }
 
 }  // namespace kk

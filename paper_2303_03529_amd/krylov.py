@@ -36,6 +36,9 @@ SIGNATURES = {
     "density_response_batch": (_I, [_P, _I, _P, _P]),
     "mulliken_project": (_I, [_P, _I, _P, _P, _P]),
     "krylov_kernel_apply": (_I, [_P, _P, _I, _P, _P, _P]),
+    "krylov_kernel_apply_adaptive": (_I, [_P, _P, _I, _D, _P, _P, _P]),
+    "kk_ground_state_charges": (_I, [_P, _P, _P]),
+    "kk_xlbomd_update": (_I, [_P, _P, _I, _P, _D, _D, _P, _P]),
     "kk_last_error": (ctypes.c_char_p, []),
     "kk_profile_enable": (_I, [_P, _I]),
     "kk_profile_reset": (_I, [_P]),
@@ -44,7 +47,8 @@ SIGNATURES = {
 
 
 class KKInfo(ctypes.Structure):
-    _fields_ = [("rank_used", _I), ("status", _I), ("min_pivot", _D), ("max_pivot", _D)]
+    _fields_ = [("rank_used", _I), ("status", _I), ("min_pivot", _D), ("max_pivot", _D),
+                ("ls_residual", _D)]
 
 
 class KKError(RuntimeError):
@@ -94,6 +98,7 @@ class KrylovInfo:
     status: int
     min_pivot: float
     max_pivot: float
+    ls_residual: float
 
 
 class Handle:
@@ -171,10 +176,45 @@ class Handle:
             _check(LIB.krylov_kernel_apply(self._h, _dev(delta, "delta", n2), int(m), k0p,
                                            _dev(out, "Kdelta", n2), ctypes.byref(inf)),
                    "krylov_kernel_apply", ok=(KK_OK, KK_BREAKDOWN, KK_ESINGULAR))
-            return out, KrylovInfo(inf.rank_used, inf.status, inf.min_pivot, inf.max_pivot)
+            return out, KrylovInfo(inf.rank_used, inf.status, inf.min_pivot, inf.max_pivot, inf.ls_residual)
         _check(LIB.krylov_kernel_apply(self._h, _dev(delta, "delta", n2), int(m), k0p,
                                        _dev(out, "Kdelta", n2), None), "krylov_kernel_apply")
         return out, None
+
+    def krylov_kernel_apply_adaptive(self, delta, m_max: int, tol: float, K0=None, out=None):
+        """Adaptive-rank K delta; returns (out, KrylovInfo). Synchronizes."""
+        import torch
+        n2 = 2 * self.n_atoms
+        if out is None:
+            out = torch.empty(n2, dtype=torch.float64, device=delta.device)
+        k0p = _dev(K0, "K0", n2 * n2) if K0 is not None else ctypes.c_void_p()
+        inf = KKInfo()
+        _check(LIB.krylov_kernel_apply_adaptive(self._h, _dev(delta, "delta", n2), int(m_max), float(tol), k0p,
+                                                _dev(out, "Kdelta", n2), ctypes.byref(inf)),
+               "krylov_kernel_apply_adaptive", ok=(KK_OK, KK_BREAKDOWN, KK_ESINGULAR))
+        return out, KrylovInfo(inf.rank_used, inf.status, inf.min_pivot, inf.max_pivot, inf.ls_residual)
+
+    def ground_state_charges(self, reference=None, out=None):
+        """q[n] at the prepared point; reference (device, N) = neutral-atom populations."""
+        import torch
+        if out is None:
+            out = torch.empty(2 * self.n_atoms, dtype=torch.float64, device="cuda")
+        ref = _dev(reference, "reference", self.n_atoms) if reference is not None else ctypes.c_void_p()
+        _check(LIB.kk_ground_state_charges(self._h, ref, _dev(out, "qm", 2 * self.n_atoms)),
+               "kk_ground_state_charges")
+        return out
+
+    def xlbomd_update(self, n_hist, Kf, kappa: float, alpha: float, c, out=None):
+        """n_hist (k_max+1, 2N) with row k = n(t - k dt); c (k_max+1,) on the device."""
+        import torch
+        n2 = 2 * self.n_atoms
+        kmax = n_hist.shape[0] - 1
+        if out is None:
+            out = torch.empty(n2, dtype=torch.float64, device=n_hist.device)
+        _check(LIB.kk_xlbomd_update(self._h, _dev(n_hist, "n_hist", (kmax + 1) * n2), kmax, _dev(Kf, "Kf", n2),
+                                    float(kappa), float(alpha), _dev(c, "c", kmax + 1), _dev(out, "n_new", n2)),
+               "kk_xlbomd_update")
+        return out
 
     def profile_enable(self, on: bool = True):
         _check(LIB.kk_profile_enable(self._h, 1 if on else 0), "kk_profile_enable")

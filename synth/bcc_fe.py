@@ -117,7 +117,8 @@ def make_system(n_cells: int | None = None, *, n_atoms: int | None = None, seed:
 
     Give either n_cells (periodic supercell of 2 n_cells^3 atoms) or n_atoms
     (open cluster). Returns a dict of float64 numpy arrays and scalars:
-      H0 (Nb,Nb), S (Nb,Nb), gamma (N,N), W, kT, n_electrons, offsets (N+1,),
+      H0 (Nb,Nb), S (Nb,Nb), gamma (N,N), W, kT, n_electrons, valence (N,)
+      (neutral-atom electron counts, the Mulliken reference), offsets (N+1,),
       positions (N,3), delta (2N,), n_ref (2N,), box (L or None).
     uniform_moment=True replaces n_ref by (0, 2.2) for every atom.
     """
@@ -184,6 +185,7 @@ def make_system(n_cells: int | None = None, *, n_atoms: int | None = None, seed:
     return dict(
         H0=H0, S=S, gamma=gamma, W=W_HARTREE * HARTREE_EV, kT=KT_EV,
         n_electrons=float(ELECTRONS_PER_ATOM * n),
+        valence=np.full(n, float(ELECTRONS_PER_ATOM)),
         offsets=np.arange(0, nb + 1, ORBITALS_PER_ATOM, dtype=np.int32),
         positions=pos, delta=delta, n_ref=np.concatenate([n_q, n_m]),
         box=box, n_atoms=n, n_basis=nb, seed=seed,

@@ -177,6 +177,54 @@ kk_status kk_ground_state_charges(kk_handle h, const double *reference, double *
 kk_status kk_xlbomd_update(kk_handle h, const double *n_hist, int k_max, const double *Kf, double kappa,
                            double alpha, const double *c, double *n_new);
 
+/*
+ * Batched form: many independent systems (e.g. uneven Fe clusters) updated
+ * together. Every step of the Krylov loop is one launch for all systems (the
+ * two transforms are persistent kernels over a global tile list sorted by
+ * cost); the whole rank-m update is captured once into a hipGraph on the
+ * batch's private stream and replayed, ordered after the caller's stream by
+ * events. The first update autotunes the tile shape per system size (64 x 64
+ * tiles below a threshold, the single-system shape above) and the number of
+ * persistent workgroups per CU by timing every candidate on the batch itself.
+ */
+typedef struct kk_batch_s *kk_batch;
+
+/* Create a batch ordered after hip_stream (a hipStream_t; NULL = the null stream). */
+kk_status kk_batch_create(kk_batch *b, void *hip_stream);
+
+/* Release the batch, its systems and its graph (synchronizes). */
+kk_status kk_batch_destroy(kk_batch b);
+
+/*
+ * kk_batch_prepare -- kk_prepare for each of n_systems systems (1..4096).
+ * Every argument is a HOST array of length n_systems; entries of the pointer
+ * arrays are what kk_prepare takes for that system (atom_offsets[i] a host
+ * array, the matrices and vectors device arrays). Synchronizes. Replaces any
+ * previous preparation of the batch (and its tuning and graph).
+ */
+kk_status kk_batch_prepare(kk_batch b, int n_systems, const int *n_atoms, const int *const *atom_offsets,
+                           const double *const *S, const double *const *Z, const double *const *Q_up,
+                           const double *const *Q_dn, const double *const *eps_up, const double *const *eps_dn,
+                           const double *const *gamma, const double *W, const double *kT,
+                           const double *n_electrons, int precision);
+
+/*
+ * krylov_kernel_apply_batch -- krylov_kernel_apply with K0 = -I for every
+ * system of the batch. delta and Kdelta are HOST arrays of n_systems device
+ * pointers (2 N_i doubles each); 1 <= m <= min(2 N_i, 64). info, if non-NULL,
+ * is a HOST array of n_systems entries and makes the call synchronize; the
+ * return value is then KK_ESINGULAR or KK_BREAKDOWN if any system reports it.
+ * The first call (and the first after kk_batch_prepare) runs the autotuner;
+ * a call with a different m captures a new graph.
+ */
+kk_status krylov_kernel_apply_batch(kk_batch b, const double *const *delta, int m, double *const *Kdelta,
+                                    kk_info *info);
+
+/* Tuning chosen by the autotuner: the largest padded size that uses 64 x 64
+ * tiles (0 = none), persistent workgroups per CU, and the fastest update's
+ * time in milliseconds. */
+kk_status kk_batch_tuning(kk_batch b, int *small_np_max, int *workgroups_per_cu, double *update_ms);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char *kk_last_error(void);
 

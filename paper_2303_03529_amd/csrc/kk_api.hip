@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -742,6 +743,479 @@ kk_status kk_profile_read(kk_handle h, int kernel_id, double* total_ms, int* lau
   }
   *total_ms = tot;
   *launches = cnt;
+  return KK_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Batched form: many independent systems, one graph launch per update.
+
+#include "kk_batch.hpp"
+
+namespace {
+
+// Tile configurations a batch chooses between: large systems use the default
+// transforms, systems with np <= small_np_max use 64 x 64 tiles.
+using BSmallF64 = kk::Cfg64x64;
+using BSmallMx = kk::MCfg64x64f8;
+
+struct TileClass {
+  int4* fwd = nullptr;
+  int4* back = nullptr;
+  int nfwd = 0, nback = 0;
+};
+
+}  // namespace
+
+struct kk_batch_s {
+  hipStream_t user_stream = nullptr;
+  hipStream_t stream = nullptr;  // private stream (a capturable, non-null stream)
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  int ns = 0, precision = KK_FP64, maxN = 0, max_np = 0;
+  bool prepared = false;
+  std::vector<kk_handle> sys;
+  std::vector<void*> owned;
+  kk::SysDesc* d_sys = nullptr;
+  void* d_items_fwd = nullptr;   // BatchItemF64 or BatchItemMixed, 2 per system
+  void* d_items_back = nullptr;
+  TileClass cls[2];              // 0: large tiles, 1: small tiles
+  const double** d_delta = nullptr;
+  double** d_out = nullptr;
+  kk::KrylovState* d_info = nullptr;
+  std::vector<const double*> h_delta;
+  std::vector<double*> h_out;
+  std::vector<int> np_of;
+  std::vector<kk::SysDesc> h_sys;   // host copy of the descriptors (nparts depends on the tile class)
+  std::vector<int> parts_large, parts_small;
+  // tuning state
+  int small_np_max = 0, grid_mult = 2;
+  bool tuned = false;
+  double tuned_ms = 0.0;
+  // graph
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int graph_m = -1;
+
+  void drop_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    graph_m = -1;
+  }
+  void release() {
+    if (stream) (void)hipStreamSynchronize(stream);
+    drop_graph();
+    for (kk_handle h : sys) kk_destroy(h);
+    sys.clear();
+    for (void* p : owned) (void)hipFree(p);
+    owned.clear();
+    for (auto& c : cls) c = TileClass{};
+    d_sys = nullptr; d_items_fwd = d_items_back = nullptr; d_delta = nullptr; d_out = nullptr; d_info = nullptr;
+    prepared = false;
+    tuned = false;
+  }
+};
+
+namespace {
+
+template <typename T>
+kk_status balloc(kk_batch b, T** p, size_t count) {
+  void* q = nullptr;
+  kk_status st = dalloc(b->owned, &q, count * sizeof(T));
+  *p = static_cast<T*>(q);
+  return st;
+}
+
+int cu_count() {
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  return cus;
+}
+
+// Build the tile lists of both classes for a threshold: items (2 per system)
+// sorted by decreasing np so the persistent workgroups start with the costly tiles.
+kk_status build_tile_lists(kk_batch b, int small_np_max) {
+  const bool mixed = b->precision == KK_MIXED_F16;
+  std::vector<int> order(b->ns);
+  for (int i = 0; i < b->ns; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return b->np_of[x] > b->np_of[y]; });
+  std::vector<int4> lists[2][2];
+  for (int i : order) {
+    const int np = b->np_of[i];
+    const int c = np <= small_np_max ? 1 : 0;
+    int bm, bn, sbm, sbn;
+    if (mixed) { bm = kk::MFwdCfg::BM; bn = kk::MFwdCfg::BN; sbm = BSmallMx::BM; sbn = BSmallMx::BN; }
+    else { bm = kk::FwdCfg::BM; bn = kk::FwdCfg::BN; sbm = BSmallF64::BM; sbn = BSmallF64::BN; }
+    const int tbm = c ? sbm : bm, tbn = c ? sbn : bn;
+    for (int s = 0; s < 2; ++s) {
+      const int item = 2 * i + s;
+      for (const int2& t : tile_order(np, tbm, tbn, true)) lists[c][0].push_back(make_int4(item, t.x, t.y, 0));
+      for (const int2& t : tile_order(np, tbm, tbn, false)) lists[c][1].push_back(make_int4(item, t.x, t.y, 0));
+    }
+  }
+  for (int i = 0; i < b->ns; ++i)
+    b->h_sys[i].nparts = b->np_of[i] <= small_np_max ? b->parts_small[i] : b->parts_large[i];
+  HIP_OR_FAIL(hipMemcpyAsync(b->d_sys, b->h_sys.data(), sizeof(kk::SysDesc) * b->ns, hipMemcpyHostToDevice,
+                             b->stream));
+  for (int c = 0; c < 2; ++c) {
+    TileClass& tc = b->cls[c];
+    tc.nfwd = (int)lists[c][0].size();
+    tc.nback = (int)lists[c][1].size();
+    if (!tc.fwd) {  // capacity for every tile of either class: the larger per-system count (small tiles)
+      size_t capf = 0, capb = 0;
+      for (int i = 0; i < b->ns; ++i) {
+        const int np = b->np_of[i];
+        const int sb = mixed ? BSmallMx::BM : BSmallF64::BM;
+        capf += 2 * (size_t)(np / sb) * (np / sb + 1) / 2 + 2 * (np / sb);
+        capb += 2 * (size_t)(np / sb) * (np / sb);
+      }
+      kk_status st;
+      if ((st = balloc(b, &tc.fwd, capf + 1))) return st;
+      if ((st = balloc(b, &tc.back, capb + 1))) return st;
+    }
+    if (tc.nfwd)
+      HIP_OR_FAIL(hipMemcpyAsync(tc.fwd, lists[c][0].data(), sizeof(int4) * tc.nfwd, hipMemcpyHostToDevice, b->stream));
+    if (tc.nback)
+      HIP_OR_FAIL(hipMemcpyAsync(tc.back, lists[c][1].data(), sizeof(int4) * tc.nback, hipMemcpyHostToDevice,
+                                 b->stream));
+  }
+  HIP_OR_FAIL(hipStreamSynchronize(b->stream));
+  return KK_OK;
+}
+
+template <int EPI, class Cfg, class Item>
+kk_status launch_persistent(kk_batch b, const Item* items, const int4* tiles, int ntiles, int two_halves) {
+  if (ntiles == 0) return KK_OK;
+  const int grid = std::min(ntiles, cu_count() * b->grid_mult);
+  if constexpr (std::is_same<Item, kk::BatchItemF64>::value)
+    kk::b_gemm_f64<EPI, Cfg><<<grid, Cfg::THREADS, 0, b->stream>>>(items, tiles, ntiles, two_halves);
+  else
+    kk::b_gemm_mixed<EPI, Cfg><<<grid, Cfg::THREADS, 0, b->stream>>>(items, tiles, ntiles, two_halves);
+  LAUNCH_CHECK("b_gemm");
+  return KK_OK;
+}
+
+// Every kernel of one batched rank-m update, in order, on the private stream.
+kk_status enqueue_update(kk_batch b, int m) {
+  const int ns = b->ns;
+  const int bx_vec = (2 * b->maxN + 255) / 256;
+  kk::b_reset<<<ns, 64, 0, b->stream>>>(b->d_sys);
+  LAUNCH_CHECK("b_reset");
+  kk::b_init<<<dim3(bx_vec, ns), 256, 0, b->stream>>>(b->d_sys, b->d_delta);
+  LAUNCH_CHECK("b_init");
+  const bool mixed = b->precision == KK_MIXED_F16;
+  kk_status st;
+  for (int k = 0; k < m; ++k) {
+    kk::b_orth<<<ns, 1024, 0, b->stream>>>(b->d_sys, k);
+    LAUNCH_CHECK("b_orth");
+    kk::b_potentials<<<dim3((b->maxN * kk::WAVE + 255) / 256, ns), 256, 0, b->stream>>>(b->d_sys, k);
+    LAUNCH_CHECK("b_potentials");
+    if (mixed) {
+      kk::b_mixed_scales<<<dim3(2, ns), 1024, 0, b->stream>>>(b->d_sys);
+      LAUNCH_CHECK("b_mixed_scales");
+      const size_t np2 = (size_t)b->max_np * b->max_np;
+      const int blocks = (int)std::min<size_t>((np2 + 255) / 256, 2048);
+      kk::b_split<<<dim3(blocks, 4, ns), 256, 0, b->stream>>>(b->d_sys);
+      LAUNCH_CHECK("b_split");
+      auto* fi = static_cast<const kk::BatchItemMixed*>(b->d_items_fwd);
+      auto* bi = static_cast<const kk::BatchItemMixed*>(b->d_items_back);
+      if ((st = launch_persistent<kk::EPI_FERMI, kk::MFwdCfg>(b, fi, b->cls[0].fwd, b->cls[0].nfwd, 1))) return st;
+      if ((st = launch_persistent<kk::EPI_FERMI, BSmallMx>(b, fi, b->cls[1].fwd, b->cls[1].nfwd, 1))) return st;
+      if ((st = launch_persistent<kk::EPI_MULLIKEN, kk::MBackCfg>(b, bi, b->cls[0].back, b->cls[0].nback, 0)))
+        return st;
+      if ((st = launch_persistent<kk::EPI_MULLIKEN, BSmallMx>(b, bi, b->cls[1].back, b->cls[1].nback, 0)))
+        return st;
+    } else {
+      auto* fi = static_cast<const kk::BatchItemF64*>(b->d_items_fwd);
+      auto* bi = static_cast<const kk::BatchItemF64*>(b->d_items_back);
+      if ((st = launch_persistent<kk::EPI_FERMI, kk::FwdCfg>(b, fi, b->cls[0].fwd, b->cls[0].nfwd, 1))) return st;
+      if ((st = launch_persistent<kk::EPI_FERMI, BSmallF64>(b, fi, b->cls[1].fwd, b->cls[1].nfwd, 1))) return st;
+      if ((st = launch_persistent<kk::EPI_MULLIKEN, kk::BackCfg>(b, bi, b->cls[0].back, b->cls[0].nback, 0)))
+        return st;
+      if ((st = launch_persistent<kk::EPI_MULLIKEN, BSmallF64>(b, bi, b->cls[1].back, b->cls[1].nback, 0)))
+        return st;
+    }
+    kk::b_combine<<<dim3((b->maxN + 255) / 256, ns), 256, 0, b->stream>>>(b->d_sys);
+    LAUNCH_CHECK("b_combine");
+    kk::b_precond<<<dim3(bx_vec, ns), 256, 0, b->stream>>>(b->d_sys, k);
+    LAUNCH_CHECK("b_precond");
+  }
+  kk::b_solve<<<ns, 1024, 0, b->stream>>>(b->d_sys, b->d_out);
+  LAUNCH_CHECK("b_solve");
+  kk::b_info<<<(ns + 255) / 256, 256, 0, b->stream>>>(b->d_sys, ns, b->d_info);
+  LAUNCH_CHECK("b_info");
+  return KK_OK;
+}
+
+kk_status upload_pointer_tables(kk_batch b, const double* const* delta, double* const* out) {
+  for (int i = 0; i < b->ns; ++i) {
+    b->h_delta[i] = delta[i];
+    b->h_out[i] = out[i];
+  }
+  HIP_OR_FAIL(hipMemcpyAsync(b->d_delta, b->h_delta.data(), sizeof(double*) * b->ns, hipMemcpyHostToDevice,
+                             b->stream));
+  HIP_OR_FAIL(hipMemcpyAsync(b->d_out, b->h_out.data(), sizeof(double*) * b->ns, hipMemcpyHostToDevice,
+                             b->stream));
+  return KK_OK;
+}
+
+// Autotuner: time one update for every (small-tile threshold, workgroups per CU)
+// candidate on the batch's own systems and keep the fastest.
+kk_status autotune(kk_batch b, int m) {
+  const int thresholds[] = {0, 512, 1024, 1 << 30};
+  const int mults[] = {1, 2, 4};
+  hipEvent_t e0, e1;
+  HIP_OR_FAIL(hipEventCreate(&e0));
+  HIP_OR_FAIL(hipEventCreate(&e1));
+  double best = 1e300;
+  int best_t = 0, best_m = 2;
+  kk_status st = KK_OK;
+  for (int th : thresholds) {
+    if ((st = build_tile_lists(b, th))) break;
+    for (int gm : mults) {
+      b->grid_mult = gm;
+      if ((st = enqueue_update(b, m))) break;  // warm-up
+      (void)hipEventRecord(e0, b->stream);
+      if ((st = enqueue_update(b, m))) break;
+      (void)hipEventRecord(e1, b->stream);
+      if (hipEventSynchronize(e1) != hipSuccess) { st = fail(KK_EHIP, "autotune: event sync failed"); break; }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best) { best = ms; best_t = th; best_m = gm; }
+    }
+    if (st) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st) return st;
+  b->small_np_max = best_t;
+  b->grid_mult = best_m;
+  b->tuned_ms = best;
+  b->tuned = true;
+  return build_tile_lists(b, best_t);
+}
+
+}  // namespace
+
+extern "C" {
+
+kk_status kk_batch_create(kk_batch* b, void* hip_stream) {
+  if (!b) return fail(KK_EINVAL, "kk_batch_create: output pointer is NULL");
+  *b = new (std::nothrow) kk_batch_s();
+  if (!*b) return fail(KK_ENOMEM, "kk_batch_create: out of host memory");
+  (*b)->user_stream = static_cast<hipStream_t>(hip_stream);
+  g_err.clear();
+  return KK_OK;
+}
+
+kk_status kk_batch_destroy(kk_batch b) {
+  if (!b) return fail(KK_EINVAL, "kk_batch_destroy: batch is NULL");
+  b->release();
+  if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+  if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+  if (b->stream) (void)hipStreamDestroy(b->stream);
+  delete b;
+  return KK_OK;
+}
+
+kk_status kk_batch_prepare(kk_batch b, int n_systems, const int* n_atoms, const int* const* atom_offsets,
+                           const double* const* S, const double* const* Z, const double* const* Q_up,
+                           const double* const* Q_dn, const double* const* eps_up, const double* const* eps_dn,
+                           const double* const* gamma, const double* W, const double* kT,
+                           const double* n_electrons, int precision) {
+  if (!b) return fail(KK_EINVAL, "kk_batch_prepare: batch is NULL");
+  if (n_systems < 1 || n_systems > 4096) return fail(KK_EINVAL, "kk_batch_prepare: need 1 <= n_systems <= 4096");
+  if (!n_atoms || !atom_offsets || !S || !Z || !Q_up || !Q_dn || !eps_up || !eps_dn || !gamma || !W || !kT ||
+      !n_electrons)
+    return fail(KK_EINVAL, "kk_batch_prepare: NULL array argument");
+  b->release();
+  if (!b->stream) {
+    HIP_OR_FAIL(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+    HIP_OR_FAIL(hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming));
+    HIP_OR_FAIL(hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming));
+  }
+  // inputs are the caller's: wait for its stream before reading them
+  HIP_OR_FAIL(hipEventRecord(b->ev_in, b->user_stream));
+  HIP_OR_FAIL(hipStreamWaitEvent(b->stream, b->ev_in, 0));
+  b->ns = n_systems;
+  b->precision = precision;
+  b->maxN = 0;
+  b->max_np = 0;
+  b->np_of.assign(n_systems, 0);
+  kk_status st;
+  for (int i = 0; i < n_systems; ++i) {
+    kk_handle h = nullptr;
+    if ((st = kk_create(&h, b->stream))) return st;
+    b->sys.push_back(h);
+    const int nb = n_atoms[i] >= 1 && atom_offsets[i] ? atom_offsets[i][n_atoms[i]] : 0;
+    if ((st = kk_prepare(h, n_atoms[i], atom_offsets[i], nb, S[i], Z[i], Q_up[i], Q_dn[i], eps_up[i],
+                         eps_dn[i], gamma[i], W[i], kT[i], n_electrons[i], precision))) {
+      char buf[600];
+      snprintf(buf, sizeof buf, "system %d: %s", i, g_err.c_str());
+      return fail(st, "kk_batch_prepare: %s", buf);
+    }
+    if ((st = ensure_workspace(h, 1))) return st;
+    b->maxN = std::max(b->maxN, h->natoms);
+    b->max_np = std::max(b->max_np, h->np);
+    b->np_of[i] = h->np;
+  }
+  // device descriptors
+  const bool mixed = precision == KK_MIXED_F16;
+  std::vector<kk::SysDesc>& sd = b->h_sys;
+  sd.assign(n_systems, kk::SysDesc{});
+  b->parts_large.assign(n_systems, 0);
+  b->parts_small.assign(n_systems, 0);
+  std::vector<kk::BatchItemF64> f64f, f64b;
+  std::vector<kk::BatchItemMixed> mxf, mxb;
+  for (int i = 0; i < n_systems; ++i) {
+    kk_handle h = b->sys[i];
+    const size_t np = h->np, np2 = np * np;
+    // Mulliken partial rows: one per wave column of a tile column, for either tile class
+    b->parts_large[i] = mixed ? (h->np / kk::MBackCfg::BN) * kk::MBackCfg::WAVES_N
+                              : (h->np / kk::BackCfg::BN) * kk::BackCfg::WAVES_N;
+    b->parts_small[i] = mixed ? (h->np / BSmallMx::BN) * BSmallMx::WAVES_N
+                              : (h->np / BSmallF64::BN) * BSmallF64::WAVES_N;
+    const int part_rows = std::max(b->parts_large[i], b->parts_small[i]);
+    double* part = nullptr;
+    if ((st = balloc(b, &part, (size_t)2 * part_rows * np))) return st;
+    kk::SysDesc& d = sd[i];
+    d.natoms = h->natoms; d.nb = h->nb; d.np = h->np; d.nparts = b->parts_large[i]; d.part_stride = part_rows;
+    d.W = h->W; d.beta = h->beta; d.offsets = h->offsets; d.gamma = h->gamma;
+    d.u = h->u; d.xdiag = h->xdiag; d.part = part;
+    d.w0 = h->w[0]; d.w1 = h->w[1]; d.wsum = h->wsum; d.t = h->t;
+    d.V = h->V; d.Ft = h->Ft; d.ftilde = h->ftilde; d.q1 = h->q1; d.kst = h->kst;
+    d.msc = h->msc; d.mconst = h->mconst;
+    d.CT0 = h->CT[0]; d.CT1 = h->CT[1]; d.GT0 = h->GT[0]; d.GT1 = h->GT[1];
+    d.uct_h = h->uct_h; d.uct_l = h->uct_l; d.ugt_h = h->ugt_h; d.ugt_l = h->ugt_l;
+    for (int s = 0; s < 2; ++s) {
+      if (mixed) {
+        kk::BatchItemMixed fi{}, bi{};
+        fi.n = bi.n = h->np; fi.beta = bi.beta = h->beta; fi.stop = bi.stop = &h->kst->stop;
+        kk::MixedItem& F = fi.g;
+        F.a0h = h->uct_h + s * np2; F.a0l = h->uct_l + s * np2; F.b0h = h->GTh[s]; F.b0l = h->GTl[s];
+        F.a1h = h->ugt_h + s * np2; F.a1l = h->ugt_l + s * np2; F.b1h = h->CTh[s]; F.b1l = h->CTl[s];
+        F.yh = h->yh + s * np2; F.yl = h->yl + s * np2;
+        F.eps = h->eps[s]; F.f = h->f[s]; F.fc = h->fc[s]; F.w = h->w[s];
+        F.xdiag = h->xdiag + s * np; F.sc = h->msc + s * 8;
+        kk::MixedItem& B = bi.g;
+        B.a0h = h->Ch[s]; B.a0l = h->Cl[s]; B.b0h = h->yh + s * np2; B.b0l = h->yl + s * np2;
+        B.g = h->G[s]; B.part = part + (size_t)s * part_rows * np; B.sc = h->msc + s * 8 + 2;
+        mxf.push_back(fi);
+        mxb.push_back(bi);
+      } else {
+        kk::BatchItemF64 fi{}, bi{};
+        fi.n = bi.n = h->np; fi.beta = bi.beta = h->beta; fi.stop = bi.stop = &h->kst->stop;
+        kk::GemmItem& F = fi.g;
+        F.a0 = h->C[s]; F.b0 = h->G[s]; F.a1 = h->G[s]; F.b1 = h->C[s];
+        F.scale = h->u + s * np; F.out = h->Y + s * np2;
+        F.eps = h->eps[s]; F.f = h->f[s]; F.fc = h->fc[s]; F.w = h->w[s]; F.xdiag = h->xdiag + s * np;
+        kk::GemmItem& B = bi.g;
+        B.a0 = h->CT[s]; B.b0 = h->Y + s * np2; B.g = h->G[s]; B.part = part + (size_t)s * part_rows * np;
+        f64f.push_back(fi);
+        f64b.push_back(bi);
+      }
+    }
+  }
+  if ((st = balloc(b, &b->d_sys, n_systems))) return st;
+  HIP_OR_FAIL(hipMemcpyAsync(b->d_sys, sd.data(), sizeof(kk::SysDesc) * n_systems, hipMemcpyHostToDevice, b->stream));
+  if (mixed) {
+    kk::BatchItemMixed *f, *bk;
+    if ((st = balloc(b, &f, mxf.size()))) return st;
+    if ((st = balloc(b, &bk, mxb.size()))) return st;
+    HIP_OR_FAIL(hipMemcpyAsync(f, mxf.data(), sizeof(kk::BatchItemMixed) * mxf.size(), hipMemcpyHostToDevice, b->stream));
+    HIP_OR_FAIL(hipMemcpyAsync(bk, mxb.data(), sizeof(kk::BatchItemMixed) * mxb.size(), hipMemcpyHostToDevice, b->stream));
+    b->d_items_fwd = f;
+    b->d_items_back = bk;
+  } else {
+    kk::BatchItemF64 *f, *bk;
+    if ((st = balloc(b, &f, f64f.size()))) return st;
+    if ((st = balloc(b, &bk, f64b.size()))) return st;
+    HIP_OR_FAIL(hipMemcpyAsync(f, f64f.data(), sizeof(kk::BatchItemF64) * f64f.size(), hipMemcpyHostToDevice, b->stream));
+    HIP_OR_FAIL(hipMemcpyAsync(bk, f64b.data(), sizeof(kk::BatchItemF64) * f64b.size(), hipMemcpyHostToDevice, b->stream));
+    b->d_items_fwd = f;
+    b->d_items_back = bk;
+  }
+  if ((st = balloc(b, &b->d_delta, n_systems))) return st;
+  if ((st = balloc(b, &b->d_out, n_systems))) return st;
+  if ((st = balloc(b, &b->d_info, n_systems))) return st;
+  b->h_delta.assign(n_systems, nullptr);
+  b->h_out.assign(n_systems, nullptr);
+  if ((st = build_tile_lists(b, 0))) return st;
+  HIP_OR_FAIL(hipStreamSynchronize(b->stream));
+  b->prepared = true;
+  g_err.clear();
+  return KK_OK;
+}
+
+kk_status krylov_kernel_apply_batch(kk_batch b, const double* const* delta, int m, double* const* Kdelta,
+                                    kk_info* info) {
+  if (!b) return fail(KK_EINVAL, "krylov_kernel_apply_batch: batch is NULL");
+  if (!b->prepared) return fail(KK_ENOTPREPARED, "kk_batch_prepare has not succeeded on this batch");
+  if (!delta || !Kdelta) return fail(KK_EINVAL, "krylov_kernel_apply_batch: NULL array argument");
+  int min_n2 = 1 << 30;
+  for (int i = 0; i < b->ns; ++i) {
+    if (!delta[i] || !Kdelta[i]) return fail(KK_EINVAL, "krylov_kernel_apply_batch: NULL pointer for system %d", i);
+    min_n2 = std::min(min_n2, 2 * b->sys[i]->natoms);
+  }
+  if (m < 1 || m > std::min(min_n2, kk::MAX_RANK))
+    return fail(KK_EINVAL, "krylov_kernel_apply_batch: need 1 <= m <= min(2N_i, %d), got %d", kk::MAX_RANK, m);
+  HIP_OR_FAIL(hipEventRecord(b->ev_in, b->user_stream));
+  HIP_OR_FAIL(hipStreamWaitEvent(b->stream, b->ev_in, 0));
+  kk_status st;
+  if ((st = upload_pointer_tables(b, delta, Kdelta))) return st;
+  if (!b->tuned) {
+    if ((st = autotune(b, m))) return st;
+    b->drop_graph();
+  }
+  if (b->graph_m != m) {
+    b->drop_graph();
+    HIP_OR_FAIL(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    st = enqueue_update(b, m);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(b->stream, &g);
+    if (st) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return fail(KK_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+    b->graph = g;
+    HIP_OR_FAIL(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    b->graph_m = m;
+  }
+  HIP_OR_FAIL(hipGraphLaunch(b->exec, b->stream));
+  HIP_OR_FAIL(hipEventRecord(b->ev_out, b->stream));
+  HIP_OR_FAIL(hipStreamWaitEvent(b->user_stream, b->ev_out, 0));
+  if (info) {
+    std::vector<kk::KrylovState> hs(b->ns);
+    HIP_OR_FAIL(hipMemcpyAsync(hs.data(), b->d_info, sizeof(kk::KrylovState) * b->ns, hipMemcpyDeviceToHost,
+                               b->stream));
+    HIP_OR_FAIL(hipStreamSynchronize(b->stream));
+    bool breakdown = false, singular = false;
+    for (int i = 0; i < b->ns; ++i) {
+      info[i].rank_used = hs[i].rank;
+      info[i].status = hs[i].status;
+      info[i].min_pivot = hs[i].min_pivot;
+      info[i].max_pivot = hs[i].max_pivot;
+      info[i].ls_residual = hs[i].ls_residual;
+      breakdown |= hs[i].status == 1;
+      singular |= hs[i].status == KK_ESINGULAR;
+    }
+    g_err.clear();
+    if (singular) return fail(KK_ESINGULAR, "krylov_kernel_apply_batch: a Gram matrix is not positive definite");
+    return breakdown ? KK_BREAKDOWN : KK_OK;
+  }
+  g_err.clear();
+  return KK_OK;
+}
+
+kk_status kk_batch_tuning(kk_batch b, int* small_np_max, int* workgroups_per_cu, double* update_ms) {
+  if (!b) return fail(KK_EINVAL, "kk_batch_tuning: batch is NULL");
+  if (!b->tuned) return fail(KK_ENOTPREPARED, "kk_batch_tuning: no update has run yet");
+  if (small_np_max) *small_np_max = b->small_np_max;
+  if (workgroups_per_cu) *workgroups_per_cu = b->grid_mult;
+  if (update_ms) *update_ms = b->tuned_ms;
   return KK_OK;
 }
 

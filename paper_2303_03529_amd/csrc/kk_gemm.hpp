@@ -107,28 +107,23 @@ struct TileCfg {
   static constexpr int LDS_BYTES = 2 * BK * (BM + BN) * 8;
 };
 
+// One output tile: both operands n x n (row stride n), K = k_half or 2 k_half.
+// Ends with a barrier, so a workgroup may run several tiles in sequence.
 template <int EPI, class Cfg>
-__global__ __launch_bounds__(Cfg::THREADS, Cfg::MIN_BLOCKS) void gemm_f64(const GemmArgs args) {
+__device__ __forceinline__ void f64_tile(const GemmItem& it, const int n, const int k_half, const bool two_halves,
+                                         const int2 tile, const double beta_arg) {
   constexpr int BM = Cfg::BM, BN = Cfg::BN, BK = Cfg::BK;
   constexpr int WTM = Cfg::WTM, WTN = Cfg::WTN;
   constexpr int AP = Cfg::A_PIECES, BP = Cfg::B_PIECES;
   constexpr int APR = BM / 2;  // double2 pieces per A row
   constexpr int BPR = BN / 2;
-
-  if (args.stop != nullptr && *args.stop != 0) return;
-  const int total = args.ntiles * args.nitems;
-  const int logical = xcd_remap(blockIdx.x, total);
-  const int z = logical / args.ntiles;
-  const int2 tile = args.tiles[logical - z * args.ntiles];
-  const GemmItem& it = args.item[z];
-  const int n = args.n;
   const int m0 = tile.x * BM, n0 = tile.y * BN;
 
   __shared__ double As[2][BK][BM];
   __shared__ double Bs[2][BK][BN];
 
   const int tid = threadIdx.x;
-  const int nk = (args.two_halves ? 2 * args.k_half : args.k_half) / BK;
+  const int nk = (two_halves ? 2 * k_half : k_half) / BK;
   const int wave = tid >> 6, lane = tid & 63;
   const int wm = wave / Cfg::WAVES_N, wn = wave % Cfg::WAVES_N;
   const int lr = lane >> 4, lc = lane & 15;
@@ -146,8 +141,8 @@ __global__ __launch_bounds__(Cfg::THREADS, Cfg::MIN_BLOCKS) void gemm_f64(const 
     int k0 = (kt) * BK;                                                                     \
     const double* A = it.a0;                                                                \
     const double* B = it.b0;                                                                \
-    if (args.two_halves && k0 >= args.k_half) {                                             \
-      A = it.a1; B = it.b1; k0 -= args.k_half;                                              \
+    if (two_halves && k0 >= k_half) {                                                       \
+      A = it.a1; B = it.b1; k0 -= k_half;                                                   \
     }                                                                                       \
     _Pragma("unroll") for (int p = 0; p < AP; ++p) {                                        \
       const int idx = tid + p * Cfg::THREADS;                                               \
@@ -216,7 +211,7 @@ __global__ __launch_bounds__(Cfg::THREADS, Cfg::MIN_BLOCKS) void gemm_f64(const 
         for (int r = 0; r < 4; ++r)
           it.out[(size_t)(mw + i * 16 + 4 * r) * n + nw + j * 16] = acc[i][j][r];
   } else if constexpr (EPI == EPI_FERMI) {
-    const double beta = args.beta;
+    const double beta = beta_arg;
     double en[WTN], fn[WTN], fcn[WTN];
 #pragma unroll
     for (int j = 0; j < WTN; ++j) {
@@ -261,6 +256,16 @@ __global__ __launch_bounds__(Cfg::THREADS, Cfg::MIN_BLOCKS) void gemm_f64(const 
         if (lc == 0) it.part[(size_t)p * n + m] = s;
       }
   }
+}
+
+template <int EPI, class Cfg>
+__global__ __launch_bounds__(Cfg::THREADS, Cfg::MIN_BLOCKS) void gemm_f64(const GemmArgs args) {
+  if (args.stop != nullptr && *args.stop != 0) return;
+  const int total = args.ntiles * args.nitems;
+  const int logical = xcd_remap(blockIdx.x, total);
+  const int z = logical / args.ntiles;
+  f64_tile<EPI, Cfg>(args.item[z], args.n, args.k_half, args.two_halves != 0,
+                     args.tiles[logical - z * args.ntiles], args.beta);
 }
 
 // Configurations. The default (128 x 128 tile, 8 waves of 32 x 64, two

@@ -74,19 +74,13 @@ __device__ __forceinline__ void split_store(double v, _Float16* hi, _Float16* lo
   *lo = (_Float16)(float)(v - (double)h);
 }
 
+// One output tile (see f64_tile); ends with a barrier.
 template <int EPI, class Cfg>
-__global__ __launch_bounds__(Cfg::THREADS, Cfg::MIN_BLOCKS) void gemm_mixed(const MixedArgs args) {
+__device__ __forceinline__ void mixed_tile(const MixedItem& it, const int n, const int k_half, const bool two_halves,
+                                           const int2 tile, const double beta_arg) {
   constexpr int BM = Cfg::BM, BN = Cfg::BN, BK = Cfg::BK, KP = Cfg::KP;
   constexpr int WTM = Cfg::WTM, WTN = Cfg::WTN;
   constexpr int CPR = BK / 8;  // 16-byte chunks per row per matrix
-
-  if (args.stop != nullptr && *args.stop != 0) return;
-  const int total = args.ntiles * args.nitems;
-  const int logical = xcd_remap(blockIdx.x, total);
-  const int z = logical / args.ntiles;
-  const int2 tile = args.tiles[logical - z * args.ntiles];
-  const MixedItem& it = args.item[z];
-  const int n = args.n;
   const int m0 = tile.x * BM, n0 = tile.y * BN;
 
   // [buf][hi/lo][row][k]
@@ -94,7 +88,7 @@ __global__ __launch_bounds__(Cfg::THREADS, Cfg::MIN_BLOCKS) void gemm_mixed(cons
   __shared__ __attribute__((aligned(16))) _Float16 Bs[2][2][BN][KP];
 
   const int tid = threadIdx.x;
-  const int nk = (args.two_halves ? 2 * args.k_half : args.k_half) / BK;
+  const int nk = (two_halves ? 2 * k_half : k_half) / BK;
   const int wave = tid >> 6, lane = tid & 63;
   const int wm = wave / Cfg::WAVES_N, wn = wave % Cfg::WAVES_N;
   const int l32 = lane & 31, lh = lane >> 5;
@@ -151,8 +145,8 @@ __global__ __launch_bounds__(Cfg::THREADS, Cfg::MIN_BLOCKS) void gemm_mixed(cons
   {                                                                                          \
     int k0 = (kt) * BK;                                                                      \
     const _Float16 *ah = it.a0h, *al = it.a0l, *bh = it.b0h, *bl = it.b0l;                   \
-    if (args.two_halves && k0 >= args.k_half) {                                              \
-      ah = it.a1h; al = it.a1l; bh = it.b1h; bl = it.b1l; k0 -= args.k_half;                 \
+    if (two_halves && k0 >= k_half) {                                                        \
+      ah = it.a1h; al = it.a1l; bh = it.b1h; bl = it.b1l; k0 -= k_half;                      \
     }                                                                                        \
     ah += k0; al += k0; bh += k0; bl += k0;                                                  \
     _Pragma("unroll") for (int p = 0; p < APM; ++p) {                                        \
@@ -247,7 +241,7 @@ __global__ __launch_bounds__(Cfg::THREADS, Cfg::MIN_BLOCKS) void gemm_mixed(cons
   const int mw = m0 + wm * (BM / Cfg::WAVES_M) + 4 * lh;
   const int nw = n0 + wn * (BN / Cfg::WAVES_N) + l32;
   if constexpr (EPI == EPI_FERMI) {
-    const double beta = args.beta, sy = it.sc[1];
+    const double beta = beta_arg, sy = it.sc[1];
     double en[WTN], fn[WTN], fcn[WTN];
 #pragma unroll
     for (int j = 0; j < WTN; ++j) {
@@ -296,6 +290,16 @@ __global__ __launch_bounds__(Cfg::THREADS, Cfg::MIN_BLOCKS) void gemm_mixed(cons
   }
 }
 
+template <int EPI, class Cfg>
+__global__ __launch_bounds__(Cfg::THREADS, Cfg::MIN_BLOCKS) void gemm_mixed(const MixedArgs args) {
+  if (args.stop != nullptr && *args.stop != 0) return;
+  const int total = args.ntiles * args.nitems;
+  const int logical = xcd_remap(blockIdx.x, total);
+  const int z = logical / args.ntiles;
+  mixed_tile<EPI, Cfg>(args.item[z], args.n, args.k_half, args.two_halves != 0,
+                       args.tiles[logical - z * args.ntiles], args.beta);
+}
+
 using MCfg128x128 = MixedCfg<128, 128, 32, 2, 2, 2>;
 using MCfg128x128f8 = MixedCfg<128, 128, 32, 2, 2, 2, 8>;
 using MCfg128x128k64 = MixedCfg<128, 128, 64, 2, 2, 1>;
@@ -303,6 +307,7 @@ using MCfg256x128 = MixedCfg<256, 128, 32, 4, 2, 1>;
 using MCfg256x256 = MixedCfg<256, 256, 32, 2, 4, 1>;
 using MCfg256x256f8 = MixedCfg<256, 256, 32, 2, 4, 1, 8>;
 using MCfg128x256 = MixedCfg<128, 256, 32, 2, 4, 1>;
+using MCfg64x64f8 = MixedCfg<64, 64, 32, 2, 2, 4, 8>;  // small systems of a batch
 
 #ifndef KK_MFWD_CFG
 #define KK_MFWD_CFG MCfg128x128f8
@@ -340,16 +345,24 @@ __global__ void split_matrix(const double* __restrict__ src, int np, int transpo
 
 // Row-scaled split for the forward A operands: dst[r][c] = split(sc * u[c] * src[r][c]),
 // src = C^T or G^T in FP64 (row r = eigenstate, column c = orbital).
-__global__ void split_scaled_columns(const double* __restrict__ src, int np, const double* __restrict__ u,
-                                     const double* __restrict__ sc_p, _Float16* __restrict__ hi,
-                                     _Float16* __restrict__ lo, const int* __restrict__ stop) {
+__device__ __forceinline__ void split_scaled_columns_dev(const double* __restrict__ src, int np,
+                                                         const double* __restrict__ u,
+                                                         const double* __restrict__ sc_p, _Float16* __restrict__ hi,
+                                                         _Float16* __restrict__ lo, const int* __restrict__ stop,
+                                                         int bx, int gdx) {
   if (stop != nullptr && *stop != 0) return;
   const double s = *sc_p;
   const size_t total = (size_t)np * np;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+  for (size_t i = (size_t)bx * blockDim.x + threadIdx.x; i < total; i += (size_t)gdx * blockDim.x) {
     const int c = (int)(i % np);
     split_store(s * u[c] * src[i], hi + i, lo + i);
   }
+}
+
+__global__ void split_scaled_columns(const double* __restrict__ src, int np, const double* __restrict__ u,
+                                     const double* __restrict__ sc_p, _Float16* __restrict__ hi,
+                                     _Float16* __restrict__ lo, const int* __restrict__ stop) {
+  split_scaled_columns_dev(src, np, u, sc_p, hi, lo, stop, blockIdx.x, gridDim.x);
 }
 
 // Per-row max |x| and sum x^2 of an np x np FP64 matrix (one block per row).
@@ -415,11 +428,12 @@ __global__ void const_scales(const double* __restrict__ cmax, const double* __re
 //   msc[z*8 + 1] = s_Y              scale of the stored Y split
 //   msc[z*8 + 2] = 1/(s_C s_Y)      back-transform unscale
 //   msc[z*8 + 3] = s_C s_u, [4] = s_G s_u  scales of the (U~ C)^T, (U~ G)^T splits
-__global__ void mixed_scales(const double* __restrict__ u, int np, const double* __restrict__ mconst,
-                             double beta, double* __restrict__ msc, const int* __restrict__ stop) {
+__device__ __forceinline__ void mixed_scales_dev(const double* __restrict__ u, int np,
+                                                 const double* __restrict__ mconst, double beta,
+                                                 double* __restrict__ msc, const int* __restrict__ stop, int z) {
   if (stop != nullptr && *stop != 0) return;
   __shared__ double sm[1024];
-  const int z = blockIdx.x, s = z & 1;
+  const int s = z & 1;
   const double* uz = u + (size_t)z * np;
   double mx = 0.0;
   for (int i = threadIdx.x; i < np; i += blockDim.x) mx = fmax(mx, fabs(uz[i]));
@@ -440,6 +454,11 @@ __global__ void mixed_scales(const double* __restrict__ u, int np, const double*
     msc[z * 8 + 3] = sC * su;
     msc[z * 8 + 4] = sG * su;
   }
+}
+
+__global__ void mixed_scales(const double* __restrict__ u, int np, const double* __restrict__ mconst,
+                             double beta, double* __restrict__ msc, const int* __restrict__ stop) {
+  mixed_scales_dev(u, np, mconst, beta, msc, stop, blockIdx.x);
 }
 
 }  // namespace kk

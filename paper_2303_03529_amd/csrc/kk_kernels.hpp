@@ -197,11 +197,12 @@ __global__ void mulliken_rows(const double* __restrict__ dup, const double* __re
 // Per-orbital spin potentials for a batch of directions (Sec. III.A):
 // u^s_I = sum_J gamma_IJ v_q[J] + sign_s W v_m[I], written to every orbital of
 // atom I in u[(b*2 + s)*np + i]. One wave per (atom, direction).
-__global__ void potentials(const double* __restrict__ gamma, int natoms, double W,
-                           const double* __restrict__ v, int batch, const int* __restrict__ offsets,
-                           int np, double* __restrict__ u, const int* __restrict__ stop) {
+__device__ __forceinline__ void potentials_dev(const double* __restrict__ gamma, int natoms, double W,
+                                               const double* __restrict__ v, int batch,
+                                               const int* __restrict__ offsets, int np, double* __restrict__ u,
+                                               const int* __restrict__ stop, int bx) {
   if (stop != nullptr && *stop != 0) return;
-  const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+  const int wid = (bx * blockDim.x + threadIdx.x) / WAVE;
   const int lane = threadIdx.x & (WAVE - 1);
   if (wid >= natoms * batch) return;
   const int b = wid / natoms, a = wid - b * natoms;
@@ -218,20 +219,27 @@ __global__ void potentials(const double* __restrict__ gamma, int natoms, double 
   }
 }
 
+__global__ void potentials(const double* __restrict__ gamma, int natoms, double W,
+                           const double* __restrict__ v, int batch, const int* __restrict__ offsets,
+                           int np, double* __restrict__ u, const int* __restrict__ stop) {
+  potentials_dev(gamma, natoms, W, v, batch, offsets, np, u, stop, blockIdx.x);
+}
+
 // Combine the two spins (Sec. II.C, III.A): dmu from the diagonal of X,
 // Mulliken sums per atom, and q1 = (dn_up + dn_dn, dn_up - dn_dn).
 //   xdiag[(b*2+s)*np + i], part[(b*2+s)][p][np], t[s*natoms + I] = sum_{i in I}
 //   sum_k C_ik w_k G_ik (the response to a unit chemical-potential shift),
 //   wsum = sum_s sum_i w_i.
 // Grid: (ceil(natoms / blockDim), batch).
-__global__ void combine(const double* __restrict__ xdiag, const double* __restrict__ part, int nparts,
-                        const double* __restrict__ w_up, const double* __restrict__ w_dn,
-                        const double* __restrict__ wsum_p, const double* __restrict__ t, int nb, int np,
-                        const int* __restrict__ offsets, int natoms, double* __restrict__ q1,
-                        const int* __restrict__ stop) {
+__device__ __forceinline__ void combine_dev(const double* __restrict__ xdiag, const double* __restrict__ part,
+                                            int nparts, int part_stride, const double* __restrict__ w_up,
+                                            const double* __restrict__ w_dn, const double* __restrict__ wsum_p,
+                                            const double* __restrict__ t, int nb, int np,
+                                            const int* __restrict__ offsets, int natoms, double* __restrict__ q1,
+                                            const int* __restrict__ stop, int bx, int by) {
   if (stop != nullptr && *stop != 0) return;
   __shared__ double sh[17];
-  const int b = blockIdx.y;
+  const int b = by;
   const double* xu = xdiag + ((size_t)b * 2 + 0) * np;
   const double* xd = xdiag + ((size_t)b * 2 + 1) * np;
   double s = 0.0;
@@ -239,11 +247,11 @@ __global__ void combine(const double* __restrict__ xdiag, const double* __restri
   s = block_sum(s, sh);
   const double wsum = *wsum_p;
   const double dmu = wsum > 0.0 ? s / wsum : 0.0;
-  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  const int a = bx * blockDim.x + threadIdx.x;
   if (a >= natoms) return;
   double dn[2];
   for (int sp = 0; sp < 2; ++sp) {
-    const double* pp = part + ((size_t)b * 2 + sp) * nparts * np;
+    const double* pp = part + ((size_t)b * 2 + sp) * part_stride * np;
     double acc = 0.0;
     for (int i = offsets[a]; i < offsets[a + 1]; ++i)
       for (int p = 0; p < nparts; ++p) acc += pp[(size_t)p * np + i];
@@ -251,6 +259,15 @@ __global__ void combine(const double* __restrict__ xdiag, const double* __restri
   }
   q1[(size_t)b * 2 * natoms + a] = dn[0] + dn[1];
   q1[(size_t)b * 2 * natoms + natoms + a] = dn[0] - dn[1];
+}
+
+__global__ void combine(const double* __restrict__ xdiag, const double* __restrict__ part, int nparts,
+                        const double* __restrict__ w_up, const double* __restrict__ w_dn,
+                        const double* __restrict__ wsum_p, const double* __restrict__ t, int nb, int np,
+                        const int* __restrict__ offsets, int natoms, double* __restrict__ q1,
+                        const int* __restrict__ stop) {
+  combine_dev(xdiag, part, nparts, nparts, w_up, w_dn, wsum_p, t, nb, np, offsets, natoms, q1, stop, blockIdx.x,
+              blockIdx.y);
 }
 
 // sum of both spins' w (one block).
@@ -305,9 +322,8 @@ __global__ void precondition(const double* __restrict__ K0, const double* __rest
 // Orthogonalize src against the accepted directions V[0..rank) with modified
 // Gram-Schmidt, two passes; accept it as V[rank] if its norm kept more than
 // BREAKDOWN_TOL of its starting norm, else stop the expansion. One block.
-__global__ void __launch_bounds__(1024) krylov_orthonormalize(const double* __restrict__ src,
-                                                              double* __restrict__ V, int n2,
-                                                              KrylovState* st) {
+__device__ __forceinline__ void orth_dev(const double* __restrict__ src, double* __restrict__ V, int n2,
+                                         KrylovState* st) {
   __shared__ double sh[17];
   if (st->stop) return;
   const int rank = st->rank;
@@ -359,15 +375,19 @@ __global__ void __launch_bounds__(1024) krylov_orthonormalize(const double* __re
   if (threadIdx.x == 0) st->rank = rank + 1;
 }
 
+__global__ void __launch_bounds__(1024) krylov_orthonormalize(const double* __restrict__ src,
+                                                              double* __restrict__ V, int n2,
+                                                              KrylovState* st) {
+  orth_dev(src, V, n2, st);
+}
+
 // O = F~^T F~, rhs = F~^T f~, Cholesky O = L L^T, c = O^-1 rhs, x = V c, and the
 // projected residual ||F~ c - f~|| / ||f~|| formed explicitly. On a non-positive
 // pivot x = 0 and status = -5. With stop_tol > 0 a residual <= stop_tol ends the
 // expansion (used by the adaptive-rank call after each direction). One block.
-__global__ void __launch_bounds__(1024) krylov_solve(const double* __restrict__ V,
-                                                     const double* __restrict__ Ft,
-                                                     const double* __restrict__ ftilde, int n2,
-                                                     KrylovState* st, double* __restrict__ x,
-                                                     double stop_tol) {
+__device__ __forceinline__ void solve_dev(const double* __restrict__ V, const double* __restrict__ Ft,
+                                          const double* __restrict__ ftilde, int n2, KrylovState* st,
+                                          double* __restrict__ x, double stop_tol) {
   __shared__ double sh[17];
   __shared__ double O[MAX_RANK][MAX_RANK + 1];
   __shared__ double c[MAX_RANK];
@@ -441,6 +461,14 @@ __global__ void __launch_bounds__(1024) krylov_solve(const double* __restrict__ 
     st->ls_residual = res;
     if (stop_tol > 0.0 && ok && res <= stop_tol) st->stop = 1;
   }
+}
+
+__global__ void __launch_bounds__(1024) krylov_solve(const double* __restrict__ V,
+                                                     const double* __restrict__ Ft,
+                                                     const double* __restrict__ ftilde, int n2,
+                                                     KrylovState* st, double* __restrict__ x,
+                                                     double stop_tol) {
+  solve_dev(V, Ft, ftilde, n2, st, x, stop_tol);
 }
 
 // (q, m) Mulliken vector of per-spin atom populations: out = (p_up + p_dn - ref, p_up - p_dn),

@@ -40,6 +40,11 @@ SIGNATURES = {
     "kk_ground_state_charges": (_I, [_P, _P, _P]),
     "kk_xlbomd_update": (_I, [_P, _P, _I, _P, _D, _D, _P, _P]),
     "kk_last_error": (ctypes.c_char_p, []),
+    "kk_batch_create": (_I, [ctypes.POINTER(_P), _P]),
+    "kk_batch_destroy": (_I, [_P]),
+    "kk_batch_prepare": (_I, [_P, _I, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _I]),
+    "krylov_kernel_apply_batch": (_I, [_P, _P, _I, _P, _P]),
+    "kk_batch_tuning": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_D)]),
     "kk_profile_enable": (_I, [_P, _I]),
     "kk_profile_reset": (_I, [_P]),
     "kk_profile_read": (_I, [_P, _I, ctypes.POINTER(_D), ctypes.POINTER(_I)]),
@@ -226,3 +231,68 @@ class Handle:
         ms, cnt = ctypes.c_double(), ctypes.c_int()
         _check(LIB.kk_profile_read(self._h, kernel_id, ctypes.byref(ms), ctypes.byref(cnt)), "kk_profile_read")
         return ms.value, cnt.value
+
+
+class Batch:
+    """Many independent systems updated together (krylov_kernel_apply_batch)."""
+
+    def __init__(self, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        self._b = ctypes.c_void_p()
+        _check(LIB.kk_batch_create(ctypes.byref(self._b), ctypes.c_void_p(stream.cuda_stream)), "kk_batch_create")
+        self.n_atoms = []
+        self._keep = []
+
+    def close(self):
+        if self._b:
+            _check(LIB.kk_batch_destroy(self._b), "kk_batch_destroy")
+            self._b = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def prepare(self, systems, precision: int = KK_FP64):
+        """systems: list of dicts with offsets (host ints), S, Z, Q_up, Q_dn, eps_up, eps_dn,
+        gamma (device float64 tensors), W, kT, n_electrons."""
+        ns = len(systems)
+        offs = [np.ascontiguousarray(np.asarray(s["offsets"], dtype=np.int32)) for s in systems]
+        n_atoms = (ctypes.c_int * ns)(*[len(o) - 1 for o in offs])
+        off_ptrs = (ctypes.c_void_p * ns)(*[o.ctypes.data for o in offs])
+
+        def table(key):
+            return (ctypes.c_void_p * ns)(*[_dev(s[key], key).value for s in systems])
+
+        def vals(key):
+            return (ctypes.c_double * ns)(*[float(s[key]) for s in systems])
+
+        tabs = [table(k) for k in ("S", "Z", "Q_up", "Q_dn", "eps_up", "eps_dn", "gamma")]
+        _check(LIB.kk_batch_prepare(self._b, ns, n_atoms, off_ptrs, *tabs, vals("W"), vals("kT"),
+                                    vals("n_electrons"), int(precision)), "kk_batch_prepare")
+        self.n_atoms = [len(o) - 1 for o in offs]
+        return self
+
+    def krylov_kernel_apply(self, deltas, m: int, outs=None, info: bool = True):
+        import torch
+        ns = len(self.n_atoms)
+        if outs is None:
+            outs = [torch.empty_like(d) for d in deltas]
+        dt = (ctypes.c_void_p * ns)(*[_dev(d, "delta", 2 * n).value for d, n in zip(deltas, self.n_atoms)])
+        ot = (ctypes.c_void_p * ns)(*[_dev(o, "Kdelta", 2 * n).value for o, n in zip(outs, self.n_atoms)])
+        if info:
+            inf = (KKInfo * ns)()
+            _check(LIB.krylov_kernel_apply_batch(self._b, dt, int(m), ot, inf), "krylov_kernel_apply_batch",
+                   ok=(KK_OK, KK_BREAKDOWN, KK_ESINGULAR))
+            return outs, [KrylovInfo(x.rank_used, x.status, x.min_pivot, x.max_pivot, x.ls_residual) for x in inf]
+        _check(LIB.krylov_kernel_apply_batch(self._b, dt, int(m), ot, None), "krylov_kernel_apply_batch")
+        return outs, None
+
+    def tuning(self):
+        a, g, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        _check(LIB.kk_batch_tuning(self._b, ctypes.byref(a), ctypes.byref(g), ctypes.byref(ms)), "kk_batch_tuning")
+        return dict(small_np_max=a.value, workgroups_per_cu=g.value, update_ms=ms.value)

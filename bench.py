@@ -42,18 +42,22 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
                     help="transform arithmetic: FP64 MFMA, or FP16 x 3 split products")
-    ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "traffic_fp64_1024.json"))
-    ap.add_argument("--workload", choices=["fe1024", "clusters64"], default="fe1024",
+    ap.add_argument("--traffic-file", default=None,
+                    help="HBM traffic summary of the dominant kernel (default: profiles/traffic_<precision>_1024.json)")
+    ap.add_argument("--workload", choices=["fe1024", "clusters64", "fe1024grad"], default="fe1024",
                     help="fe1024: one 1024-atom bcc cell (headline); clusters64: 64 uneven open clusters, "
-                         "16-250 atoms, rank 6, batched in one graph launch")
+                         "16-250 atoms, rank 6, batched in one graph launch; fe1024grad: K delta and its "
+                         "reverse pass (gradients of ||K delta||^2) on the 1024-atom cell")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB elementwise copy kernel 3 times (scales HBM counters)")
     return ap.parse_args()
 
 
-def gemm_source_digest() -> str:
+def gemm_source_digest(precision: str = "fp64") -> str:
+    """First 16 hex of the sha256 of the header holding the transform kernels."""
     import hashlib
-    src = os.path.join(ROOT, "paper_2303_03529_amd", "csrc", "kk_gemm.hpp")
+    name = "kk_gemm.hpp" if precision == "fp64" else "kk_gemm_mixed.hpp"
+    src = os.path.join(ROOT, "paper_2303_03529_amd", "csrc", name)
     return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
 
 
@@ -144,6 +148,76 @@ def bench_clusters(args):
     print(json.dumps(res), flush=True)
 
 
+def bench_grad(args):
+    """Differentiation form: one step = krylov_kernel_apply plus krylov_kernel_adjoint (reusing
+    the expansion) for L = ||K delta||^2 on the prepared 1024-atom system, FP64."""
+    import torch
+
+    from paper_2303_03529_amd import krylov
+    from paper_2303_03529_amd.caller_setup import expansion_point_device
+    from synth import make_system
+
+    dev = "cuda:0"
+    t_setup = time.perf_counter()
+    sysd = make_system(args.cells, seed=args.seed)
+    N, nb, m = sysd["n_atoms"], sysd["n_basis"], args.rank
+    e = expansion_point_device(sysd, dev)
+    h = krylov.Handle()
+    h.prepare(sysd["offsets"], e["S"], e["Z"], e["Q_up"], e["Q_dn"], e["eps_up"], e["eps_dn"],
+              e["gamma"], sysd["W"], sysd["kT"], sysd["n_electrons"], krylov.KK_FP64)
+    del e
+    torch.cuda.empty_cache()
+    delta = torch.as_tensor(sysd["delta"], dtype=torch.float64, device=dev)
+    out = torch.empty_like(delta)
+    print(f"# setup {time.perf_counter() - t_setup:.1f} s (N={N}, Nb={nb}, m={m})", file=sys.stderr, flush=True)
+
+    def step():
+        x, _ = h.krylov_kernel_apply(delta, m, out=out, info=False)
+        return h.krylov_kernel_adjoint(delta, m, 2.0 * x, reuse_forward=True)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    h.profile_enable(True)
+    h.profile_reset()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g = step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    names = {0: "forward_fermi", 1: "back_mulliken", 2: "reverse_forward_xy", 3: "reverse_accumulate"}
+    flops_launch = {0: 4.0 * nb ** 3, 1: 4.0 * nb ** 3, 2: 8.0 * nb ** 3, 3: 8.0 * nb ** 3}
+    kern = {}
+    for kid, name in names.items():
+        ms, n = h.profile_read(kid)
+        kern[name] = (ms / max(n, 1), n, flops_launch[kid])
+    h.profile_enable(False)
+    h.close()
+    dom = max(kern, key=lambda k: kern[k][0] * kern[k][1])
+    avg_ms, _, fl = kern[dom]
+    achieved = fl / (avg_ms * 1e-3) / 1e12
+    # forward 8 m Nb^3; reverse per direction: X,Y of four items (8), Mulliken of two (4),
+    # accumulation (8); final C E' C^T (8 Nb^3)
+    step_flops = 8.0 * m * nb ** 3 + 20.0 * m * nb ** 3 + 8.0 * nb ** 3
+    res = {
+        "metric": "Krylov kernel gradient evaluations/sec (K delta and dL/d(delta, gamma, W, H^sigma), "
+                  "L = ||K delta||^2) at 1024-atom Fe",
+        "value": args.steps / elapsed, "unit": "gradient evaluations/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"bcc Fe {N} atoms ({args.cells}^3 cells), Nb={nb}, rank m={m}, FP64, "
+                               "forward + reverse pass, K0=-I", "n_atoms": N, "n_basis": nb, "rank": m},
+        "step_tflops": step_flops / (elapsed / args.steps) / 1e12,
+        "mfma_util_step": step_flops / (elapsed / args.steps) / 1e12 / FP64_MFMA_PEAK_TFLOPS,
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_MFMA_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / FP64_MFMA_PEAK_TFLOPS, 4), "traffic": None,
+                     "kernel": dom, "avg_launch_ms": round(avg_ms, 4), "flops_per_launch": fl,
+                     "other_kernel_avg_ms": {k: round(v[0], 4) for k, v in kern.items() if k != dom}},
+        "grad_norms": {"delta": float(g["delta"].norm()), "H_up": float(g["H_up"].norm())},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -164,6 +238,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "clusters64":
         return bench_clusters(args)
+    if args.workload == "fe1024grad":
+        return bench_grad(args)
     t_setup = time.perf_counter()
     sysd = make_system(args.cells, seed=args.seed)
     N, nb, m = sysd["n_atoms"], sysd["n_basis"], args.rank
@@ -228,10 +304,11 @@ def main():
     avg_ms = kernels[dom][0]
     achieved = flops_launch / (avg_ms * 1e-3) / 1e12
     traffic = None
-    if prec == krylov.KK_FP64 and os.path.exists(args.traffic_file):
-        tr = json.load(open(args.traffic_file))
+    traffic_file = args.traffic_file or os.path.join(ROOT, "profiles", f"traffic_{args.precision}_1024.json")
+    if os.path.exists(traffic_file):
+        tr = json.load(open(traffic_file))
         if (tr.get("kernel") == dom and tr.get("n_basis") == nb
-                and tr.get("source_digest") == gemm_source_digest()):
+                and tr.get("source_digest") == gemm_source_digest(args.precision)):
             traffic = tr.get("bytes_per_launch")
     peak = FP64_MFMA_PEAK_TFLOPS if prec == krylov.KK_FP64 else FP16_MFMA_PEAK_TFLOPS / 3.0
     roofline = {

@@ -178,6 +178,46 @@ kk_status kk_xlbomd_update(kk_handle h, const double *n_hist, int k_max, const d
                            double alpha, const double *c, double *n_new);
 
 /*
+ * krylov_kernel_adjoint -- reverse-mode derivative of the rank-m kernel result
+ * x = K delta of krylov_kernel_apply (Sec. II.G), for a scalar L(x) whose
+ * gradient x_bar = dL/dx the caller supplies (2 x for L = ||K delta||^2).
+ *   delta, m, K0   as for krylov_kernel_apply (K0 NULL means -I)
+ *   Kdelta_bar     device 2N: x_bar
+ *   reuse_forward  0: run the Krylov expansion again first (and write x to
+ *                  Kdelta if it is not NULL); 1: use the expansion the last
+ *                  krylov_kernel_apply(_adaptive) on this handle left, which
+ *                  must have had the same delta, m and K0 (m and K0 are
+ *                  checked, KK_EINVAL otherwise; any kk_prepare invalidates it)
+ * Outputs (device, caller-owned, overwritten):
+ *   delta_bar      2N: dL/d delta
+ *   gamma_bar      N x N: dL/d gamma_IJ through the response potentials
+ *                  u = gamma v_q +/- W v_m only (not symmetrized: dL = sum_IJ
+ *                  gamma_bar_IJ d gamma_IJ)
+ *   W_bar          1 double: dL/dW through the response potentials only
+ *   H_bar_up, H_bar_dn  Nb x Nb each: dL/dH^sigma with respect to the spin
+ *                  Hamiltonians of the prepared expansion point (the H whose
+ *                  Z^T H Z has the eigenpairs given to kk_prepare), through the
+ *                  levels, the eigenvectors, the occupations and the shared mu
+ *                  (Sec. II.C). Symmetric: dL = sum_ij H_bar_ij dH_ij for every
+ *                  symmetric dH. A caller that builds gamma, W and H^sigma from
+ *                  other parameters (U, W, H0, n) chains through its own
+ *                  construction; the expansion-point dependence on gamma and W
+ *                  (through H^sigma) is left to that chain.
+ * The per-direction response matrices are recomputed in the reverse sweep,
+ * never stored: the workspace is 12 padded Nb^2 FP64 matrices plus O(N m),
+ * allocated on first use and kept by the handle. Levels closer than 1e-3 kT
+ * (exact degeneracies included) are handled through second divided
+ * differences of the Fermi function. With a breakdown (rank r < m) the rank-r
+ * expansion is differentiated and KK_BREAKDOWN is returned. KK_FP64 handles
+ * only (KK_EINVAL otherwise). Synchronizes once (to read the rank) and again
+ * if info is not NULL.
+ */
+kk_status krylov_kernel_adjoint(kk_handle h, const double *delta, int m, const double *K0,
+                                const double *Kdelta_bar, int reuse_forward, double *Kdelta,
+                                double *delta_bar, double *gamma_bar, double *W_bar,
+                                double *H_bar_up, double *H_bar_dn, kk_info *info);
+
+/*
  * Batched form: many independent systems (e.g. uneven Fe clusters) updated
  * together. Every step of the Krylov loop is one launch for all systems (the
  * two transforms are persistent kernels over a global tile list sorted by
@@ -232,7 +272,9 @@ const char *kk_last_error(void);
  * Kernel timing for measurement. When enabled, the library records HIP events
  * on its stream around each launch of its two dense transform kernels
  * (kernel_id 0: forward eigenbasis transform with the Fermi Hadamard product;
- * 1: back-transform with the Mulliken projection). kk_profile_read
+ * 1: back-transform with the Mulliken projection; 2: the forward transform of
+ * the reverse pass, which also writes X; 3: the reverse pass's accumulation of
+ * Y0_b Xa + Y0_a Xb). kk_profile_read
  * synchronizes and returns the summed milliseconds and launch count since the
  * last reset. At most 8192 launches are recorded between resets.
  */

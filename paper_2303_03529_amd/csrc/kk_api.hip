@@ -28,6 +28,7 @@
 #include "kk_gemm.hpp"
 #include "kk_kernels.hpp"
 #include "kk_gemm_mixed.hpp"
+#include "kk_adjoint.hpp"
 
 namespace {
 
@@ -106,6 +107,37 @@ struct kk_handle_s {
 
   std::vector<void*> ws_owned;  // response workspace, replaced when it grows
 
+  // last Krylov expansion left in V / Ft / ftilde (for a reverse pass that reuses it)
+  bool fwd_valid = false;
+  int fwd_m = 0;
+  const double* fwd_K0 = nullptr;
+  long prepare_gen = 0;  // bumped by every successful kk_prepare
+
+  // reverse-pass workspace (krylov_kernel_adjoint), allocated on first use
+  std::vector<void*> adj_owned;
+  double *aX = nullptr, *aY = nullptr, *aK = nullptr, *aD = nullptr;  // 4, 4, 2, 2 padded matrices
+  double *au = nullptr, *axdiag = nullptr, *apart = nullptr, *agdiag = nullptr;
+  double *admu = nullptr, *agtot = nullptr, *ag = nullptr, *ay = nullptr, *alam = nullptr;
+  double *aVbar = nullptr, *aFbar = nullptr, *abbar = nullptr, *aKd = nullptr;
+  std::vector<void*> pair_owned;
+  int2* apairs = nullptr;
+  double* apk = nullptr;
+  int pair_cap = 0, an0 = 0, an1 = 0;
+  long pairs_gen = -1;
+
+  void free_adjoint() {
+    for (void* p : adj_owned) (void)hipFree(p);
+    for (void* p : pair_owned) (void)hipFree(p);
+    adj_owned.clear();
+    pair_owned.clear();
+    aX = aY = aK = aD = au = axdiag = apart = agdiag = nullptr;
+    admu = agtot = ag = ay = alam = aVbar = aFbar = abbar = aKd = nullptr;
+    apairs = nullptr;
+    apk = nullptr;
+    pair_cap = an0 = an1 = 0;
+    pairs_gen = -1;
+  }
+
   void free_workspace() {
     for (void* p : ws_owned) (void)hipFree(p);
     ws_owned.clear();
@@ -116,12 +148,14 @@ struct kk_handle_s {
   }
 
   void release() {
-    if (owned.empty() && ws_owned.empty()) {
+    if (owned.empty() && ws_owned.empty() && adj_owned.empty()) {
       prepared = false;
       return;
     }
     (void)hipStreamSynchronize(stream);
     free_workspace();
+    free_adjoint();
+    fwd_valid = false;
     for (void* p : owned) (void)hipFree(p);
     owned.clear();
     prepared = false;
@@ -206,6 +240,12 @@ kk_status launch_gemm(kk_handle h, int epi, kk::GemmArgs& a) {
   } else if (epi == kk::EPI_FERMI) {
     ProfileScope ps(h, 0);
     kk::gemm_f64<kk::EPI_FERMI, kk::FwdCfg><<<grid, kk::FwdCfg::THREADS, 0, h->stream>>>(a);
+  } else if (epi == kk::EPI_FERMI_XY) {
+    ProfileScope ps(h, 2);
+    kk::gemm_f64<kk::EPI_FERMI_XY, kk::FwdCfg><<<grid, kk::FwdCfg::THREADS, 0, h->stream>>>(a);
+  } else if (epi == kk::EPI_ACCUM) {
+    ProfileScope ps(h, 3);
+    kk::gemm_f64<kk::EPI_ACCUM, kk::BackCfg><<<grid, kk::BackCfg::THREADS, 0, h->stream>>>(a);
   } else {
     ProfileScope ps(h, 1);
     kk::gemm_f64<kk::EPI_MULLIKEN, kk::BackCfg><<<grid, kk::BackCfg::THREADS, 0, h->stream>>>(a);
@@ -510,6 +550,7 @@ kk_status kk_prepare(kk_handle h, int n_atoms, const int* atom_offsets, int n_ba
   // Re-preparing the same shape (an SCF or MD loop) reuses every buffer.
   const bool reuse = h->prepared && h->natoms == n_atoms && h->nb == nb && h->precision == precision;
   h->prepared = false;
+  h->fwd_valid = false;
   kk_status st;
   if (!reuse) {
     h->release();
@@ -571,6 +612,7 @@ kk_status kk_prepare(kk_handle h, int n_atoms, const int* atom_offsets, int n_ba
   if (mixed && (st = prepare_mixed(h))) return st;
   HIP_OR_FAIL(hipStreamSynchronize(h->stream));
   h->prepared = true;
+  ++h->prepare_gen;
   g_err.clear();
   return KK_OK;
 }
@@ -650,6 +692,9 @@ kk_status krylov_run(kk_handle h, const char* who, const double* delta, int m, d
   }
   kk::krylov_solve<<<1, 1024, 0, h->stream>>>(h->V, h->Ft, h->ftilde, n2, h->kst, Kdelta, 0.0);
   LAUNCH_CHECK("krylov_solve");
+  h->fwd_valid = true;
+  h->fwd_m = m;
+  h->fwd_K0 = K0;
   if (info) {
     kk::KrylovState hs;
     HIP_OR_FAIL(hipMemcpyAsync(&hs, h->kst, sizeof hs, hipMemcpyDeviceToHost, h->stream));
@@ -744,6 +789,282 @@ kk_status kk_profile_read(kk_handle h, int kernel_id, double* total_ms, int* lau
   *total_ms = tot;
   *launches = cnt;
   return KK_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Reverse pass (differentiation form): kernels in kk_adjoint.hpp.
+
+namespace {
+
+kk_status ensure_adjoint(kk_handle h) {
+  if (!h->adj_owned.empty()) return KK_OK;
+  const size_t np = h->np, np2 = np * np, n2 = 2 * (size_t)h->natoms;
+  kk_status st;
+  auto get = [&](double** p, size_t count) -> kk_status {
+    void* q = nullptr;
+    kk_status e = dalloc(h->adj_owned, &q, count * sizeof(double));
+    *p = static_cast<double*>(q);
+    return e;
+  };
+  if ((st = get(&h->aX, 4 * np2))) return st;
+  if ((st = get(&h->aY, 4 * np2))) return st;
+  if ((st = get(&h->aK, 2 * np2))) return st;
+  if ((st = get(&h->aD, 2 * np2))) return st;
+  if ((st = get(&h->au, 4 * np))) return st;
+  if ((st = get(&h->axdiag, 4 * np))) return st;
+  if ((st = get(&h->apart, 2 * (size_t)h->nparts * np))) return st;
+  if ((st = get(&h->agdiag, 2 * np))) return st;
+  if ((st = get(&h->admu, 2))) return st;
+  if ((st = get(&h->agtot, 1))) return st;
+  if ((st = get(&h->ag, n2))) return st;
+  if ((st = get(&h->ay, n2))) return st;
+  if ((st = get(&h->alam, n2))) return st;
+  if ((st = get(&h->abbar, n2))) return st;
+  if ((st = get(&h->aKd, n2))) return st;
+  if ((st = get(&h->aVbar, kk::MAX_RANK * n2))) return st;
+  if ((st = get(&h->aFbar, kk::MAX_RANK * n2))) return st;
+  return KK_OK;
+}
+
+// Level pairs (i < j) of each spin closer than tau, from the prepared levels.
+kk_status ensure_pairs(kk_handle h, double tau) {
+  if (h->pairs_gen == h->prepare_gen) return KK_OK;
+  const int nb = h->nb;
+  std::vector<double> e(2 * (size_t)nb);
+  HIP_OR_FAIL(hipMemcpyAsync(e.data(), h->eps[0], sizeof(double) * nb, hipMemcpyDeviceToHost, h->stream));
+  HIP_OR_FAIL(hipMemcpyAsync(e.data() + nb, h->eps[1], sizeof(double) * nb, hipMemcpyDeviceToHost, h->stream));
+  HIP_OR_FAIL(hipStreamSynchronize(h->stream));
+  std::vector<int2> pairs;
+  int counts[2] = {0, 0};
+  constexpr size_t MAX_PAIRS = size_t(1) << 24;
+  for (int s = 0; s < 2; ++s) {
+    const double* es = e.data() + (size_t)s * nb;
+    std::vector<int> idx(nb);
+    for (int i = 0; i < nb; ++i) idx[i] = i;
+    std::sort(idx.begin(), idx.end(), [&](int a, int b) { return es[a] < es[b] || (es[a] == es[b] && a < b); });
+    for (int p = 0; p < nb; ++p)
+      for (int q = p + 1; q < nb && es[idx[q]] - es[idx[p]] < tau; ++q) {
+        const int i = std::min(idx[p], idx[q]), j = std::max(idx[p], idx[q]);
+        pairs.push_back(make_int2(i, j));
+        ++counts[s];
+        if (pairs.size() > MAX_PAIRS)
+          return fail(KK_EINVAL, "krylov_kernel_adjoint: more than %zu near-degenerate level pairs", MAX_PAIRS);
+      }
+  }
+  const int np_ = (int)pairs.size();
+  if (np_ > h->pair_cap) {
+    for (void* p : h->pair_owned) (void)hipFree(p);
+    h->pair_owned.clear();
+    h->apairs = nullptr;
+    h->apk = nullptr;
+    h->pair_cap = 0;
+    void* q = nullptr;
+    kk_status st;
+    if ((st = dalloc(h->pair_owned, &q, sizeof(int2) * (size_t)np_))) return st;
+    h->apairs = static_cast<int2*>(q);
+    if ((st = dalloc(h->pair_owned, &q, sizeof(double) * (size_t)np_))) return st;
+    h->apk = static_cast<double*>(q);
+    h->pair_cap = np_;
+  }
+  if (np_ > 0) {
+    HIP_OR_FAIL(hipMemcpyAsync(h->apairs, pairs.data(), sizeof(int2) * pairs.size(), hipMemcpyHostToDevice,
+                               h->stream));
+    HIP_OR_FAIL(hipStreamSynchronize(h->stream));  // the host vector must outlive the copy
+  }
+  h->an0 = counts[0];
+  h->an1 = counts[1];
+  h->pairs_gen = h->prepare_gen;
+  return KK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+kk_status krylov_kernel_adjoint(kk_handle h, const double* delta, int m, const double* K0, const double* Kdelta_bar,
+                                int reuse_forward, double* Kdelta, double* delta_bar, double* gamma_bar,
+                                double* W_bar, double* H_bar_up, double* H_bar_dn, kk_info* info) {
+  static const char* who = "krylov_kernel_adjoint";
+  kk_status st = check_handle(h);
+  if (st) return st;
+  if (h->precision != KK_FP64) return fail(KK_EINVAL, "%s: the reverse pass needs a KK_FP64 handle", who);
+  if (!delta || !Kdelta_bar || !delta_bar || !gamma_bar || !W_bar || !H_bar_up || !H_bar_dn)
+    return fail(KK_EINVAL, "%s: NULL array argument", who);
+  const int N = h->natoms, n2 = 2 * N, np = h->np, nb = h->nb;
+  const size_t np2 = (size_t)np * np;
+  if (m < 1 || m > std::min(n2, kk::MAX_RANK))
+    return fail(KK_EINVAL, "%s: need 1 <= m <= min(2N, %d), got %d", who, kk::MAX_RANK, m);
+  const double tau = 1e-3 * h->kT;
+
+  if ((st = ensure_adjoint(h))) return st;
+  // forward expansion: recomputed, or the one the last kernel call left
+  if (reuse_forward) {
+    if (!h->fwd_valid || h->fwd_m != m || h->fwd_K0 != K0)
+      return fail(KK_EINVAL, "%s: reuse_forward needs the last kernel call on this handle to have used the same "
+                             "m and K0", who);
+  } else {
+    kk_info fi;
+    if ((st = krylov_run(h, who, delta, m, 0.0, K0, Kdelta ? Kdelta : h->aKd, &fi)) < 0) return st;
+  }
+  kk::KrylovState hs;
+  HIP_OR_FAIL(hipMemcpyAsync(&hs, h->kst, sizeof hs, hipMemcpyDeviceToHost, h->stream));
+  HIP_OR_FAIL(hipStreamSynchronize(h->stream));
+  if (hs.status == KK_ESINGULAR) return fail(KK_ESINGULAR, "%s: Gram matrix not positive definite", who);
+  if ((st = ensure_pairs(h, tau))) return st;
+  const int r = hs.rank;
+  const int npairs = h->an0 + h->an1;
+
+  if ((st = zero(h, h->aK, 2 * np2))) return st;
+  if ((st = zero(h, h->aD, 2 * np2))) return st;
+  if ((st = zero(h, h->agdiag, 2 * (size_t)np))) return st;
+  if ((st = zero(h, gamma_bar, (size_t)N * N))) return st;
+  if ((st = zero(h, W_bar, 1))) return st;
+  if (npairs > 0 && (st = zero(h, h->apk, npairs))) return st;
+
+  kk::adj_init<<<1, 1024, 0, h->stream>>>(h->V, h->Ft, h->ftilde, n2, h->kst, Kdelta_bar, h->aVbar, h->aFbar,
+                                          h->abbar);
+  LAUNCH_CHECK("adj_init");
+
+  kk::AdjSpins sp{};
+  for (int s = 0; s < 2; ++s) {
+    sp.s[s].Xa = h->aX + (size_t)s * np2;
+    sp.s[s].Xb = h->aX + (size_t)(2 + s) * np2;
+    sp.s[s].eps = h->eps[s]; sp.s[s].f = h->f[s]; sp.s[s].fc = h->fc[s]; sp.s[s].w = h->w[s];
+    sp.s[s].D = h->aD + (size_t)s * np2;
+    sp.s[s].gdiag = h->agdiag + (size_t)s * np;
+  }
+  const int wave_blocks = (N * kk::WAVE + 255) / 256;
+  for (int k = r - 1; k >= 0; --k) {
+    const double* vk = h->V + (size_t)k * n2;
+    // lambda_k and y_k = K0^T lambda_k
+    kk::adj_gs<<<1, 1024, 0, h->stream>>>(h->V, h->Ft, n2, k, k == r - 1, h->aVbar, h->aFbar,
+                                          K0 ? h->alam : h->ay, K0 ? 0 : 1);
+    LAUNCH_CHECK("adj_gs");
+    if (K0) {
+      kk::gemv_t<<<(n2 + 255) / 256, 256, 0, h->stream>>>(K0, h->alam, n2, h->ay);
+      LAUNCH_CHECK("gemv_t");
+    }
+    // potentials: a = M y (identity coupling), b = M Gamma v_k
+    kk::potentials<<<wave_blocks, 256, 0, h->stream>>>(nullptr, N, 1.0, h->ay, 1, h->offsets, np, h->au, nullptr);
+    kk::potentials<<<wave_blocks, 256, 0, h->stream>>>(h->gamma, N, h->W, vk, 1, h->offsets, np, h->au + 2 * np,
+                                                        nullptr);
+    LAUNCH_CHECK("potentials");
+    // X and Y0 of the four items (a up, a dn, b up, b dn)
+    kk::GemmArgs fa{};
+    fa.n = np; fa.k_half = np; fa.two_halves = 1; fa.ntiles = h->n_upper; fa.nitems = 4;
+    fa.tiles = h->tiles_upper; fa.beta = h->beta;
+    for (int z = 0; z < 4; ++z) {
+      const int s = z & 1;
+      kk::GemmItem& it = fa.item[z];
+      it.a0 = h->C[s]; it.b0 = h->G[s]; it.a1 = h->G[s]; it.b1 = h->C[s];
+      it.scale = h->au + (size_t)z * np; it.out = h->aY + (size_t)z * np2; it.xout = h->aX + (size_t)z * np2;
+      it.eps = h->eps[s]; it.f = h->f[s]; it.fc = h->fc[s]; it.w = h->w[s];
+      it.xdiag = h->axdiag + (size_t)z * np;
+    }
+    if ((st = launch_gemm(h, kk::EPI_FERMI_XY, fa))) return st;
+    // g = M chi M y: back-transform and Mulliken sums of the a items
+    kk::GemmArgs ba{};
+    ba.n = np; ba.k_half = np; ba.two_halves = 0; ba.ntiles = h->n_full; ba.nitems = 2;
+    ba.tiles = h->tiles_full; ba.beta = h->beta;
+    for (int s = 0; s < 2; ++s) {
+      kk::GemmItem& it = ba.item[s];
+      it.a0 = h->CT[s]; it.b0 = h->aY + (size_t)s * np2; it.g = h->G[s];
+      it.part = h->apart + (size_t)s * h->nparts * np;
+    }
+    if ((st = launch_gemm(h, kk::EPI_MULLIKEN, ba))) return st;
+    {
+      dim3 grid((N + 255) / 256, 1);
+      kk::combine<<<grid, 256, 0, h->stream>>>(h->axdiag, h->apart, h->nparts, h->w[0], h->w[1], h->wsum, h->t,
+                                                nb, np, h->offsets, N, h->ag, nullptr);
+      LAUNCH_CHECK("combine");
+    }
+    kk::adj_dmu<<<2, 1024, 0, h->stream>>>(h->axdiag, nb, np, h->w[0], h->w[1], h->wsum, h->admu);
+    LAUNCH_CHECK("adj_dmu");
+    // K += Y0_b Xa + Y0_a Xb per spin
+    kk::GemmArgs ka{};
+    ka.n = np; ka.k_half = np; ka.two_halves = 1; ka.ntiles = h->n_full; ka.nitems = 2;
+    ka.tiles = h->tiles_full; ka.beta = h->beta;
+    for (int s = 0; s < 2; ++s) {
+      kk::GemmItem& it = ka.item[s];
+      it.a0 = h->aY + (size_t)(2 + s) * np2; it.b0 = h->aX + (size_t)s * np2;
+      it.a1 = h->aY + (size_t)s * np2; it.b1 = h->aX + (size_t)(2 + s) * np2;
+      it.out = h->aK + (size_t)s * np2;
+    }
+    if ((st = launch_gemm(h, kk::EPI_ACCUM, ka))) return st;
+    {
+      dim3 grid(nb, 2);
+      kk::adj_rows<<<grid, 256, 0, h->stream>>>(sp, nb, np, h->admu, h->mu, h->beta, tau);
+      LAUNCH_CHECK("adj_rows");
+    }
+    if (npairs > 0) {
+      kk::adj_pairs<<<npairs, 256, 0, h->stream>>>(sp, h->apairs, h->an0, nb, np, h->mu, h->beta, tau, h->apk);
+      LAUNCH_CHECK("adj_pairs");
+    }
+    kk::adj_apply<<<wave_blocks, 256, 0, h->stream>>>(h->gamma, N, h->W, h->ag, h->ay, vk,
+                                                       h->aVbar + (size_t)k * n2, gamma_bar);
+    LAUNCH_CHECK("adj_apply");
+    kk::adj_wbar<<<1, 256, 0, h->stream>>>(h->ag, vk, N, W_bar);
+    LAUNCH_CHECK("adj_wbar");
+  }
+  // dL/d delta
+  if (r > 0) {
+    kk::adj_finish<<<1, 1024, 0, h->stream>>>(h->V, h->aVbar, h->ftilde, n2, h->abbar, K0 ? h->alam : delta_bar,
+                                              K0 ? 0 : 1);
+    LAUNCH_CHECK("adj_finish");
+    if (K0) {
+      kk::gemv_t<<<(n2 + 255) / 256, 256, 0, h->stream>>>(K0, h->alam, n2, delta_bar);
+      LAUNCH_CHECK("gemv_t");
+    }
+  } else if ((st = zero(h, delta_bar, n2))) {
+    return st;
+  }
+  // dL/dH^sigma = C E'_bar C^T
+  kk::sum_two<<<1, 1024, 0, h->stream>>>(h->agdiag, h->agdiag + np, np, h->agtot);
+  LAUNCH_CHECK("sum_two");
+  double* Ep[2] = {h->aX, h->aX + np2};
+  for (int s = 0; s < 2; ++s) {
+    dim3 grid(np / 32, np / 32);
+    kk::adj_final<<<grid, 256, 0, h->stream>>>(h->aK + (size_t)s * np2, h->aD + (size_t)s * np2, h->eps[s],
+                                                h->w[s], h->agdiag + (size_t)s * np, h->agtot, h->wsum, nb, np, tau,
+                                                Ep[s]);
+    LAUNCH_CHECK("adj_final");
+  }
+  if (npairs > 0) {
+    kk::adj_pair_final<<<(npairs + 255) / 256, 256, 0, h->stream>>>(h->apairs, h->an0, npairs, h->apk, h->aD,
+                                                                     h->aD + np2, h->eps[0], h->eps[1], h->mu,
+                                                                     h->beta, np, Ep[0], Ep[1]);
+    LAUNCH_CHECK("adj_pair_final");
+  }
+  kk::GemmArgs a{};
+  a.n = np; a.k_half = np; a.two_halves = 0; a.ntiles = h->n_store; a.tiles = h->tiles_store; a.nitems = 2;
+  for (int s = 0; s < 2; ++s) {  // U1 = E'_bar C^T
+    a.item[s] = kk::GemmItem{};
+    a.item[s].a0 = Ep[s]; a.item[s].b0 = h->CT[s]; a.item[s].out = h->aY + (size_t)s * np2;
+  }
+  if ((st = launch_gemm(h, kk::EPI_STORE, a))) return st;
+  for (int s = 0; s < 2; ++s) {  // C U1
+    a.item[s] = kk::GemmItem{};
+    a.item[s].a0 = h->CT[s]; a.item[s].b0 = h->aY + (size_t)s * np2; a.item[s].out = h->aY + (size_t)(2 + s) * np2;
+  }
+  if ((st = launch_gemm(h, kk::EPI_STORE, a))) return st;
+  double* Hb[2] = {H_bar_up, H_bar_dn};
+  for (int s = 0; s < 2; ++s) {
+    const int blocks = (int)std::min<size_t>(((size_t)nb * nb + 255) / 256, 65536);
+    kk::unpad_copy<<<blocks, 256, 0, h->stream>>>(h->aY + (size_t)(2 + s) * np2, np, Hb[s], nb);
+    LAUNCH_CHECK("unpad_copy");
+  }
+  if (info) {
+    HIP_OR_FAIL(hipStreamSynchronize(h->stream));
+    info->rank_used = hs.rank;
+    info->status = hs.status;
+    info->min_pivot = hs.min_pivot;
+    info->max_pivot = hs.max_pivot;
+    info->ls_residual = hs.ls_residual;
+  }
+  g_err.clear();
+  return hs.status == 1 ? KK_BREAKDOWN : KK_OK;
 }
 
 }  // extern "C"

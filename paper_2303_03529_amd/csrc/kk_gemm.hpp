@@ -23,6 +23,9 @@
 //               elements below it are skipped.
 //   EPI_MULLIKEN  Sec. III.A Mulliken rows: part[p][m] = sum over the wave's
 //               columns n of acc[m][n] * G[m][n]; the caller sums the parts.
+//   EPI_FERMI_XY  EPI_FERMI that also writes X itself (both triangles) to xout,
+//               for the reverse pass, which needs X and Y of each direction.
+//   EPI_ACCUM   out[m][n] += acc                                (adjoint sums)
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -35,7 +38,7 @@ typedef double d2 __attribute__((ext_vector_type(2)));
 constexpr int PAD = 128;    // every padded dimension is a multiple of this
 constexpr int MAX_GEMM_BATCH = 16;
 
-enum { EPI_STORE = 0, EPI_FERMI = 1, EPI_MULLIKEN = 2 };
+enum { EPI_STORE = 0, EPI_FERMI = 1, EPI_MULLIKEN = 2, EPI_FERMI_XY = 3, EPI_ACCUM = 4 };
 
 struct GemmItem {
   const double* a0;   // first K half: A operand, [K][n] row-major
@@ -51,6 +54,7 @@ struct GemmItem {
   const double* w;      // beta f (1 - f)
   double* xdiag;        // EPI_FERMI: diag X
   double* part;         // EPI_MULLIKEN: [parts][n]
+  double* xout;         // EPI_FERMI_XY: X
 };
 
 struct GemmArgs {
@@ -148,7 +152,7 @@ __device__ __forceinline__ void f64_tile(const GemmItem& it, const int n, const 
       const int idx = tid + p * Cfg::THREADS;                                               \
       const int row = idx / APR, col = (idx % APR) * 2;                                     \
       ra[p] = *reinterpret_cast<const d2*>(A + (size_t)(k0 + row) * n + m0 + col);     \
-      if constexpr (EPI == EPI_FERMI) {                                                     \
+      if constexpr (EPI == EPI_FERMI || EPI == EPI_FERMI_XY) {                              \
         const double s = it.scale[k0 + row];                                                \
         ra[p] *= s;                                                                         \
       }                                                                                     \
@@ -202,15 +206,18 @@ __device__ __forceinline__ void f64_tile(const GemmItem& it, const int n, const 
   //   m = m0 + wm*(BM/WAVES_M) + i*16 + lr + 4r,  n = n0 + wn*(BN/WAVES_N) + j*16 + lc.
   const int mw = m0 + wm * (BM / Cfg::WAVES_M) + lr;
   const int nw = n0 + wn * (BN / Cfg::WAVES_N) + lc;
-  if constexpr (EPI == EPI_STORE) {
+  if constexpr (EPI == EPI_STORE || EPI == EPI_ACCUM) {
 #pragma unroll
     for (int i = 0; i < WTM; ++i)
 #pragma unroll
       for (int j = 0; j < WTN; ++j)
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-          it.out[(size_t)(mw + i * 16 + 4 * r) * n + nw + j * 16] = acc[i][j][r];
-  } else if constexpr (EPI == EPI_FERMI) {
+        for (int r = 0; r < 4; ++r) {
+          double* o = it.out + (size_t)(mw + i * 16 + 4 * r) * n + nw + j * 16;
+          if constexpr (EPI == EPI_ACCUM) *o += acc[i][j][r];
+          else *o = acc[i][j][r];
+        }
+  } else if constexpr (EPI == EPI_FERMI || EPI == EPI_FERMI_XY) {
     const double beta = beta_arg;
     double en[WTN], fn[WTN], fcn[WTN];
 #pragma unroll
@@ -229,6 +236,10 @@ __device__ __forceinline__ void f64_tile(const GemmItem& it, const int n, const 
           const int c = nw + j * 16;
           if (m > c) continue;
           const double x = 0.5 * acc[i][j][r];
+          if constexpr (EPI == EPI_FERMI_XY) {
+            it.xout[(size_t)m * n + c] = x;
+            it.xout[(size_t)c * n + m] = x;
+          }
           if (m == c) {
             it.xdiag[m] = x;
             it.out[(size_t)m * n + m] = -it.w[m] * x;

@@ -196,7 +196,9 @@ __global__ void mulliken_rows(const double* __restrict__ dup, const double* __re
 
 // Per-orbital spin potentials for a batch of directions (Sec. III.A):
 // u^s_I = sum_J gamma_IJ v_q[J] + sign_s W v_m[I], written to every orbital of
-// atom I in u[(b*2 + s)*np + i]. One wave per (atom, direction).
+// atom I in u[(b*2 + s)*np + i]. One wave per (atom, direction). With gamma
+// NULL the coupling is the identity, u^s_I = v_q[I] + sign_s W v_m[I] (the
+// reverse pass uses it with W = 1 to apply the transposed response).
 __device__ __forceinline__ void potentials_dev(const double* __restrict__ gamma, int natoms, double W,
                                                const double* __restrict__ v, int batch,
                                                const int* __restrict__ offsets, int np, double* __restrict__ u,
@@ -207,10 +209,14 @@ __device__ __forceinline__ void potentials_dev(const double* __restrict__ gamma,
   if (wid >= natoms * batch) return;
   const int b = wid / natoms, a = wid - b * natoms;
   const double* vb = v + (size_t)b * 2 * natoms;
-  const double* g = gamma + (size_t)a * natoms;
   double s = 0.0;
-  for (int j = lane; j < natoms; j += WAVE) s += g[j] * vb[j];
-  s = wave_sum(s);
+  if (gamma != nullptr) {
+    const double* g = gamma + (size_t)a * natoms;
+    for (int j = lane; j < natoms; j += WAVE) s += g[j] * vb[j];
+    s = wave_sum(s);
+  } else {
+    s = vb[a];
+  }
   const double up = s + W * vb[natoms + a];
   const double dn = s - W * vb[natoms + a];
   for (int i = offsets[a] + lane; i < offsets[a + 1]; i += WAVE) {

@@ -39,6 +39,7 @@ SIGNATURES = {
     "krylov_kernel_apply_adaptive": (_I, [_P, _P, _I, _D, _P, _P, _P]),
     "kk_ground_state_charges": (_I, [_P, _P, _P]),
     "kk_xlbomd_update": (_I, [_P, _P, _I, _P, _D, _D, _P, _P]),
+    "krylov_kernel_adjoint": (_I, [_P, _P, _I, _P, _P, _I, _P, _P, _P, _P, _P, _P, _P]),
     "kk_last_error": (ctypes.c_char_p, []),
     "kk_batch_create": (_I, [ctypes.POINTER(_P), _P]),
     "kk_batch_destroy": (_I, [_P]),
@@ -198,6 +199,35 @@ class Handle:
                                                 _dev(out, "Kdelta", n2), ctypes.byref(inf)),
                "krylov_kernel_apply_adaptive", ok=(KK_OK, KK_BREAKDOWN, KK_ESINGULAR))
         return out, KrylovInfo(inf.rank_used, inf.status, inf.min_pivot, inf.max_pivot, inf.ls_residual)
+
+    def krylov_kernel_adjoint(self, delta, m: int, Kdelta_bar, K0=None, reuse_forward: bool = False,
+                              want_Kdelta: bool = False):
+        """Reverse pass of K delta for x_bar = Kdelta_bar. Synchronizes.
+
+        Returns dict(delta, gamma, W, H_up, H_dn, Kdelta (or None), info): the
+        gradients of the caller's L with respect to delta, gamma (through the
+        response potentials), W (likewise, a 0-d tensor) and the expansion-point
+        spin Hamiltonians (n_basis x n_basis each).
+        """
+        import torch
+        n, nb = self.n_atoms, self.n_basis
+        n2 = 2 * n
+        dev = delta.device
+        kw = dict(dtype=torch.float64, device=dev)
+        out = dict(delta=torch.empty(n2, **kw), gamma=torch.empty(n, n, **kw), W=torch.empty((), **kw),
+                   H_up=torch.empty(nb, nb, **kw), H_dn=torch.empty(nb, nb, **kw),
+                   Kdelta=torch.empty(n2, **kw) if want_Kdelta and not reuse_forward else None)
+        k0p = _dev(K0, "K0", n2 * n2) if K0 is not None else ctypes.c_void_p()
+        kdp = _dev(out["Kdelta"], "Kdelta", n2) if out["Kdelta"] is not None else ctypes.c_void_p()
+        inf = KKInfo()
+        _check(LIB.krylov_kernel_adjoint(
+            self._h, _dev(delta, "delta", n2), int(m), k0p, _dev(Kdelta_bar, "Kdelta_bar", n2),
+            1 if reuse_forward else 0, kdp, _dev(out["delta"], "delta_bar", n2),
+            _dev(out["gamma"], "gamma_bar", n * n), _dev(out["W"], "W_bar", 1),
+            _dev(out["H_up"], "H_bar_up", nb * nb), _dev(out["H_dn"], "H_bar_dn", nb * nb), ctypes.byref(inf)),
+            "krylov_kernel_adjoint", ok=(KK_OK, KK_BREAKDOWN))
+        out["info"] = KrylovInfo(inf.rank_used, inf.status, inf.min_pivot, inf.max_pivot, inf.ls_residual)
+        return out
 
     def ground_state_charges(self, reference=None, out=None):
         """q[n] at the prepared point; reference (device, N) = neutral-atom populations."""

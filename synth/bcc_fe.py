@@ -119,7 +119,9 @@ def make_system(n_cells: int | None = None, *, n_atoms: int | None = None, seed:
     (open cluster). Returns a dict of float64 numpy arrays and scalars:
       H0 (Nb,Nb), S (Nb,Nb), gamma (N,N), W, kT, n_electrons, valence (N,)
       (neutral-atom electron counts, the Mulliken reference), offsets (N+1,),
-      positions (N,3), delta (2N,), n_ref (2N,), box (L or None).
+      positions (N,3), delta (2N,), n_ref (2N,), box (L or None),
+      r2_bohr (N,N) squared minimum-image distances in Bohr^2 (zero diagonal),
+      U (eV) and hartree_ev, with which gamma can be rebuilt at another U.
     uniform_moment=True replaces n_ref by (0, 2.2) for every atom.
     """
     if (n_cells is None) == (n_atoms is None):
@@ -181,6 +183,7 @@ def make_system(n_cells: int | None = None, *, n_atoms: int | None = None, seed:
     rb2 = rmin2 / BOHR_ANG ** 2
     gamma = HARTREE_EV / np.sqrt(rb2 + 1.0 / U_HARTREE ** 2)
     np.fill_diagonal(gamma, U_HARTREE * HARTREE_EV)
+    np.fill_diagonal(rb2, 0.0)
 
     return dict(
         H0=H0, S=S, gamma=gamma, W=W_HARTREE * HARTREE_EV, kT=KT_EV,
@@ -189,6 +192,7 @@ def make_system(n_cells: int | None = None, *, n_atoms: int | None = None, seed:
         offsets=np.arange(0, nb + 1, ORBITALS_PER_ATOM, dtype=np.int32),
         positions=pos, delta=delta, n_ref=np.concatenate([n_q, n_m]),
         box=box, n_atoms=n, n_basis=nb, seed=seed,
+        r2_bohr=rb2, U=U_HARTREE * HARTREE_EV, hartree_ev=HARTREE_EV,
     )
 
 

@@ -4,7 +4,7 @@ m = 12), in the launch configuration bench.py times.
 The library is prepared from the device eigensolve (caller_setup), the same
 inputs bench.py uses, so it is independent of the oracle's eigenvectors; only
 basis-invariant outputs are compared with the oracle's stored values
-(tests/golden/fe1024_oracle.json, written by make_fe1024_golden.py, which
+(tests/golden/fe1024_oracle.json, written by make_oracle_golden.py, which
 calls only the oracle). Properties that hold at any size are checked too.
 """
 

@@ -47,6 +47,11 @@ def test_argument_validation_without_device():
         assert L.krylov_kernel_apply(h, ctypes.c_void_p(8), 4, None, ctypes.c_void_p(8), None) \
             == krylov.KK_ENOTPREPARED
         assert "kk_prepare" in krylov.last_error()
+        assert L.krylov_kernel_adjoint(h, p8 := ctypes.c_void_p(8), 4, None, p8, 0, None, p8, p8, p8, p8, p8,
+                                       None) == krylov.KK_ENOTPREPARED
+        assert L.krylov_kernel_apply_adaptive(h, p8, 4, 0.1, None, p8, None) == krylov.KK_ENOTPREPARED
+        assert L.kk_ground_state_charges(h, None, p8) == krylov.KK_ENOTPREPARED
+        assert L.kk_xlbomd_update(h, p8, 1, p8, 1.0, 0.0, p8, p8) == krylov.KK_ENOTPREPARED
         off = np.array([0, 9, 18], dtype=np.int32)
         p = ctypes.c_void_p(8)
         args = [p] * 6

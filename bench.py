@@ -163,12 +163,23 @@ def bench_grad(args):
     N, nb, m = sysd["n_atoms"], sysd["n_basis"], args.rank
     e = expansion_point_device(sysd, dev)
     h = krylov.Handle()
+    prec = krylov.KK_FP64 if args.precision == "fp64" else krylov.KK_MIXED_F16
     h.prepare(sysd["offsets"], e["S"], e["Z"], e["Q_up"], e["Q_dn"], e["eps_up"], e["eps_dn"],
-              e["gamma"], sysd["W"], sysd["kT"], sysd["n_electrons"], krylov.KK_FP64)
-    del e
-    torch.cuda.empty_cache()
+              e["gamma"], sysd["W"], sysd["kT"], sysd["n_electrons"], prec)
     delta = torch.as_tensor(sysd["delta"], dtype=torch.float64, device=dev)
     out = torch.empty_like(delta)
+    ref = None
+    if prec != krylov.KK_FP64:  # FP64 gradient on the same inputs, for the error of the split forward
+        h64 = krylov.Handle()
+        h64.prepare(sysd["offsets"], e["S"], e["Z"], e["Q_up"], e["Q_dn"], e["eps_up"], e["eps_dn"],
+                    e["gamma"], sysd["W"], sysd["kT"], sysd["n_electrons"], krylov.KK_FP64)
+        x64, _ = h64.krylov_kernel_apply(delta, m)
+        ref = h64.krylov_kernel_adjoint(delta, m, 2.0 * x64, reuse_forward=True)
+        ref = {k: ref[k].cpu() for k in ("delta", "H_up", "H_dn")}
+        h64.close()
+        del h64
+    del e
+    torch.cuda.empty_cache()
     print(f"# setup {time.perf_counter() - t_setup:.1f} s (N={N}, Nb={nb}, m={m})", file=sys.stderr, flush=True)
 
     def step():
@@ -192,9 +203,14 @@ def bench_grad(args):
         kern[name] = (ms / max(n, 1), n, flops_launch[kid])
     h.profile_enable(False)
     h.close()
+    err = None
+    if ref is not None:
+        err = {k: float((g[k].cpu() - ref[k]).norm() / ref[k].norm()) for k in ref}
+    fwd_peak = FP64_MFMA_PEAK_TFLOPS if prec == krylov.KK_FP64 else FP16_MFMA_PEAK_TFLOPS / 3.0
     dom = max(kern, key=lambda k: kern[k][0] * kern[k][1])
     avg_ms, _, fl = kern[dom]
     achieved = fl / (avg_ms * 1e-3) / 1e12
+    dom_peak = fwd_peak if dom in ("forward_fermi", "back_mulliken") else FP64_MFMA_PEAK_TFLOPS
     # forward 8 m Nb^3; reverse per direction: X,Y of four items (8), Mulliken of two (4),
     # accumulation (8); final C E' C^T (8 Nb^3)
     step_flops = 8.0 * m * nb ** 3 + 20.0 * m * nb ** 3 + 8.0 * nb ** 3
@@ -203,13 +219,15 @@ def bench_grad(args):
                   "L = ||K delta||^2) at 1024-atom Fe",
         "value": args.steps / elapsed, "unit": "gradient evaluations/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"bcc Fe {N} atoms ({args.cells}^3 cells), Nb={nb}, rank m={m}, FP64, "
-                               "forward + reverse pass, K0=-I", "n_atoms": N, "n_basis": nb, "rank": m},
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prec == krylov.KK_FP64 else "f16x3+f64 forward, f64 reverse", "data": "synthetic",
+        "config": {"workload": f"bcc Fe {N} atoms ({args.cells}^3 cells), Nb={nb}, rank m={m}, "
+                               f"{'FP64' if prec == krylov.KK_FP64 else 'split FP16x3'} forward + FP64 reverse "
+                               "pass, K0=-I", "n_atoms": N, "n_basis": nb, "rank": m},
         "step_tflops": step_flops / (elapsed / args.steps) / 1e12,
-        "mfma_util_step": step_flops / (elapsed / args.steps) / 1e12 / FP64_MFMA_PEAK_TFLOPS,
-        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_MFMA_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(achieved / FP64_MFMA_PEAK_TFLOPS, 4), "traffic": None,
+        "grad_err_vs_fp64": err,
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": round(dom_peak, 2),
+                     "unit": "TFLOP/s", "frac": round(achieved / dom_peak, 4), "traffic": None,
                      "kernel": dom, "avg_launch_ms": round(avg_ms, 4), "flops_per_launch": fl,
                      "other_kernel_avg_ms": {k: round(v[0], 4) for k, v in kern.items() if k != dom}},
         "grad_norms": {"delta": float(g["delta"].norm()), "H_up": float(g["H_up"].norm())},

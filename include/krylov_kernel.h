@@ -208,9 +208,11 @@ kk_status kk_xlbomd_update(kk_handle h, const double *n_hist, int k_max, const d
  * allocated on first use and kept by the handle. Levels closer than 1e-3 kT
  * (exact degeneracies included) are handled through second divided
  * differences of the Fermi function. With a breakdown (rank r < m) the rank-r
- * expansion is differentiated and KK_BREAKDOWN is returned. KK_FP64 handles
- * only (KK_EINVAL otherwise). Synchronizes once (to read the rank) and again
- * if info is not NULL.
+ * expansion is differentiated and KK_BREAKDOWN is returned. The forward
+ * expansion runs in the handle's precision; the reverse sweep always runs in
+ * FP64 (on a KK_MIXED_F16 handle it differentiates the split-precision
+ * forward, with ~1e-7 relative error from it). Synchronizes once (to read the
+ * rank) and again if info is not NULL.
  */
 kk_status krylov_kernel_adjoint(kk_handle h, const double *delta, int m, const double *K0,
                                 const double *Kdelta_bar, int reuse_forward, double *Kdelta,

@@ -18,6 +18,8 @@ returns dL/dU, dL/dW and dL/dH0 as well:
 
 Energies are in eV. The forward's eigensolve of Z^T H^sigma Z (Z = S^-1/2)
 is caller-side setup too (torch.linalg.eigh), as for kk_prepare in general.
+With precision KK_MIXED_F16 the forward expansion runs on the split FP16
+transforms and the reverse sweep in FP64.
 """
 
 from __future__ import annotations
@@ -31,9 +33,10 @@ from . import krylov
 class KernelSystem:
     """Fixed data of one system (S, Z, offsets, distances, n) and its library handle."""
 
-    def __init__(self, sysd: dict, n=None, device: str = "cuda"):
+    def __init__(self, sysd: dict, n=None, device: str = "cuda", precision: int = krylov.KK_FP64):
         dt = torch.float64
         self.device = device
+        self.precision = precision
         self.offsets = np.asarray(sysd["offsets"], dtype=np.int32)
         self.N = len(self.offsets) - 1
         self.counts = torch.as_tensor(np.diff(self.offsets).astype(np.int64), device=device)
@@ -74,7 +77,7 @@ class KernelSystem:
             eig += [e.contiguous(), Q.contiguous()]
         e_up, Q_up, e_dn, Q_dn = eig
         self.handle.prepare(self.offsets, self.S, self.Z, Q_up, Q_dn, e_up, e_dn, gamma.contiguous(), W,
-                            self.kT, self.n_electrons, krylov.KK_FP64)
+                            self.kT, self.n_electrons, self.precision)
         self.token += 1
         return eig
 
@@ -100,7 +103,7 @@ class KrylovKernel(torch.autograd.Function):
         reuse = system.token == ctx.token
         if not reuse:  # the handle moved on: prepare this expansion point again
             system.handle.prepare(system.offsets, system.S, system.Z, Q_up, Q_dn, e_up, e_dn, gamma, ctx.W,
-                                  system.kT, system.n_electrons, krylov.KK_FP64)
+                                  system.kT, system.n_electrons, system.precision)
         g = system.handle.krylov_kernel_adjoint(delta, ctx.m, x_bar.contiguous(), reuse_forward=reuse)
         system.token += 1
         return g["delta"], g["gamma"], g["W"], g["H_up"], g["H_dn"], None, None

@@ -798,6 +798,9 @@ kk_status kk_profile_read(kk_handle h, int kernel_id, double* total_ms, int* lau
 
 namespace {
 
+// Mulliken partial rows per spin written by the FP64 back-transform of the reverse pass.
+int adj_nparts(kk_handle h) { return (h->np / kk::BackCfg::BN) * kk::BackCfg::WAVES_N; }
+
 kk_status ensure_adjoint(kk_handle h) {
   if (!h->adj_owned.empty()) return KK_OK;
   const size_t np = h->np, np2 = np * np, n2 = 2 * (size_t)h->natoms;
@@ -814,7 +817,7 @@ kk_status ensure_adjoint(kk_handle h) {
   if ((st = get(&h->aD, 2 * np2))) return st;
   if ((st = get(&h->au, 4 * np))) return st;
   if ((st = get(&h->axdiag, 4 * np))) return st;
-  if ((st = get(&h->apart, 2 * (size_t)h->nparts * np))) return st;
+  if ((st = get(&h->apart, 2 * (size_t)adj_nparts(h) * np))) return st;
   if ((st = get(&h->agdiag, 2 * np))) return st;
   if ((st = get(&h->admu, 2))) return st;
   if ((st = get(&h->agtot, 1))) return st;
@@ -889,7 +892,6 @@ kk_status krylov_kernel_adjoint(kk_handle h, const double* delta, int m, const d
   static const char* who = "krylov_kernel_adjoint";
   kk_status st = check_handle(h);
   if (st) return st;
-  if (h->precision != KK_FP64) return fail(KK_EINVAL, "%s: the reverse pass needs a KK_FP64 handle", who);
   if (!delta || !Kdelta_bar || !delta_bar || !gamma_bar || !W_bar || !H_bar_up || !H_bar_dn)
     return fail(KK_EINVAL, "%s: NULL array argument", who);
   const int N = h->natoms, n2 = 2 * N, np = h->np, nb = h->nb;
@@ -971,12 +973,12 @@ kk_status krylov_kernel_adjoint(kk_handle h, const double* delta, int m, const d
     for (int s = 0; s < 2; ++s) {
       kk::GemmItem& it = ba.item[s];
       it.a0 = h->CT[s]; it.b0 = h->aY + (size_t)s * np2; it.g = h->G[s];
-      it.part = h->apart + (size_t)s * h->nparts * np;
+      it.part = h->apart + (size_t)s * adj_nparts(h) * np;
     }
     if ((st = launch_gemm(h, kk::EPI_MULLIKEN, ba))) return st;
     {
       dim3 grid((N + 255) / 256, 1);
-      kk::combine<<<grid, 256, 0, h->stream>>>(h->axdiag, h->apart, h->nparts, h->w[0], h->w[1], h->wsum, h->t,
+      kk::combine<<<grid, 256, 0, h->stream>>>(h->axdiag, h->apart, adj_nparts(h), h->w[0], h->w[1], h->wsum, h->t,
                                                 nb, np, h->offsets, N, h->ag, nullptr);
       LAUNCH_CHECK("combine");
     }

@@ -308,12 +308,23 @@ using MCfg256x256 = MixedCfg<256, 256, 32, 2, 4, 1>;
 using MCfg256x256f8 = MixedCfg<256, 256, 32, 2, 4, 1, 8>;
 using MCfg128x256 = MixedCfg<128, 256, 32, 2, 4, 1>;
 using MCfg64x64f8 = MixedCfg<64, 64, 32, 2, 2, 4, 8>;  // small systems of a batch
+using MCfg128x128k16f16 = MixedCfg<128, 128, 16, 2, 2, 3, 16>;
+using MCfg128x128k16f16b2 = MixedCfg<128, 128, 16, 2, 2, 2, 16>;
+using MCfg128x256f8 = MixedCfg<128, 256, 32, 2, 2, 1, 8>;
+using MCfg256x128w8f8 = MixedCfg<256, 128, 32, 4, 2, 1, 8>;
+using MCfg128x128k64f4 = MixedCfg<128, 128, 64, 2, 2, 1, 4>;
+using MCfg128x128w8f8 = MixedCfg<128, 128, 32, 4, 2, 2, 8>;
 
+// Default: 128 x 128 tiles of 8 waves (32 x 64 each), K stage 32, flush every 8 stages, two
+// workgroups (16 waves) per CU. At Nb = 9216 it beat the 4-wave 64 x 64 shape by 2-3 %, and
+// shorter K stages (16), longer ones (64, one workgroup per CU) and wider tiles (128 x 256,
+// 256 x 128) by 5-25 %: the kernel is bound by exposed load latency, not by LDS bandwidth
+// (no bank conflicts; LDS busy ~27 %, MFMA busy ~40 % of cycles).
 #ifndef KK_MFWD_CFG
-#define KK_MFWD_CFG MCfg128x128f8
+#define KK_MFWD_CFG MCfg128x128w8f8
 #endif
 #ifndef KK_MBACK_CFG
-#define KK_MBACK_CFG MCfg128x128f8
+#define KK_MBACK_CFG MCfg128x128w8f8
 #endif
 using MFwdCfg = KK_MFWD_CFG;
 using MBackCfg = KK_MBACK_CFG;

@@ -25,9 +25,9 @@ from synth import make_system  # noqa: E402
 TOL = 1e-10
 
 
-def gpu_gradients(sysd, m, K0=None):
+def gpu_gradients(sysd, m, K0=None, precision=0):
     """L and dL/d(delta, U, W, H0) through KrylovKernel on the device."""
-    ks = KernelSystem(sysd, device=DEV)
+    ks = KernelSystem(sysd, device=DEV, precision=precision)
     try:
         d = t(sysd["delta"]).requires_grad_(True)
         U = torch.tensor(sysd["U"], dtype=torch.float64, device=DEV, requires_grad=True)
@@ -65,6 +65,13 @@ def test_adjoint_fe16_matches_oracle_gradient(m):
 def test_adjoint_fe128_matches_oracle_gradient():
     sysd = make_system(4, seed=128)
     compare(gpu_gradients(sysd, 8), gradients(sysd, 8))
+
+
+def test_adjoint_split_forward_fe128():
+    """Split-precision forward (KK_MIXED_F16), FP64 reverse sweep: the gradient of the
+    split forward map, within the split form's 1e-6 of the oracle gradient."""
+    sysd = make_system(4, seed=128)
+    compare(gpu_gradients(sysd, 8, precision=1), gradients(sysd, 8), tol=1e-6)
 
 
 def test_adjoint_ragged_cluster_matches_oracle_gradient():

@@ -351,6 +351,8 @@ kk_status response_chunk_mixed(kk_handle h, int batch, const double* v, double* 
                                                        h->u, stop);
     LAUNCH_CHECK("potentials");
   }
+  kk::center_potentials<<<batch, 1024, 0, h->stream>>>(h->u, np, h->nb, h->w[0], h->w[1], stop);
+  LAUNCH_CHECK("center_potentials");
   kk::mixed_scales<<<2 * batch, 1024, 0, h->stream>>>(h->u, np, h->mconst, h->beta, h->msc, stop);
   LAUNCH_CHECK("mixed_scales");
   for (int z = 0; z < 2 * batch; ++z) {
@@ -1236,6 +1238,8 @@ kk_status enqueue_update(kk_batch b, int m) {
     kk::b_potentials<<<dim3((b->maxN * kk::WAVE + 255) / 256, ns), 256, 0, b->stream>>>(b->d_sys, k);
     LAUNCH_CHECK("b_potentials");
     if (mixed) {
+      kk::b_center<<<ns, 1024, 0, b->stream>>>(b->d_sys);
+      LAUNCH_CHECK("b_center");
       kk::b_mixed_scales<<<dim3(2, ns), 1024, 0, b->stream>>>(b->d_sys);
       LAUNCH_CHECK("b_mixed_scales");
       const size_t np2 = (size_t)b->max_np * b->max_np;

@@ -80,6 +80,11 @@ __global__ void b_potentials(const SysDesc* __restrict__ d, int k) {
                  blockIdx.x);
 }
 
+__global__ void b_center(const SysDesc* __restrict__ d) {
+  const SysDesc& s = d[blockIdx.x];
+  center_potentials_dev(s.u, s.np, s.nb, s.w0, s.w1, &s.kst->stop, 0);
+}
+
 __global__ void b_mixed_scales(const SysDesc* __restrict__ d) {
   const SysDesc& s = d[blockIdx.y];
   mixed_scales_dev(s.u, s.np, s.mconst, s.beta, s.msc, &s.kst->stop, blockIdx.x);

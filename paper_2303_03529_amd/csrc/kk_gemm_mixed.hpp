@@ -60,11 +60,33 @@ struct MixedCfg {
   static constexpr int WTM = BM / WAVES_M / 32;
   static constexpr int WTN = BN / WAVES_N / 32;
   static constexpr int MIN_BLOCKS = MINB_;
+  static constexpr bool DL = false;
   static constexpr int KP = BK + 8;                 // padded LDS row (halves)
   static_assert((KP / 8) % 2 == 1, "LDS row stride must be an odd number of 16-byte slots");
   static_assert(64 % (BK / 8) == 0 && 16 % (BK / 8) == 0, "piece mapping");
   static_assert(BM % (32 * WAVES_M) == 0 && BN % (32 * WAVES_N) == 0, "wave tiling");
   static_assert(BK % 16 == 0, "BK");
+  static_assert(MIXED_PAD % BM == 0 && MIXED_PAD % BN == 0, "tile must divide the padding");
+};
+
+// Configuration of the direct-to-LDS main loop: BM x BN tile, K stage 32, a ring
+// of NS stages in LDS, one workgroup per CU.
+template <int BM_, int BN_, int WAVES_M_, int WAVES_N_, int NS_, int FLUSH_>
+struct MixedDlCfg {
+  static constexpr bool DL = true;
+  static constexpr int BM = BM_, BN = BN_, BK = 32, NS = NS_, FLUSH = FLUSH_;
+  static constexpr int WAVES_M = WAVES_M_, WAVES_N = WAVES_N_, WAVES = WAVES_M * WAVES_N;
+  static constexpr int THREADS = 64 * WAVES;
+  static constexpr int WTM = BM / WAVES_M / 32, WTN = BN / WAVES_N / 32;
+  static constexpr int MIN_BLOCKS = 1;
+  static constexpr int A_BLK = BM / 16, B_BLK = BN / 16;     // 1 KB blocks of 16 rows
+  static constexpr int STAGE_BLK = 2 * (A_BLK + B_BLK);        // hi and lo of A and B
+  static constexpr int PER_WAVE = STAGE_BLK / WAVES;
+  static constexpr int STAGE_BYTES = STAGE_BLK * 1024;
+  static_assert(STAGE_BLK % WAVES == 0, "DMA blocks per wave");
+  static_assert(BM % (32 * WAVES_M) == 0 && BN % (32 * WAVES_N) == 0, "wave tiling");
+  static_assert(NS >= 2 && NS <= 5, "ring depth");
+  static_assert(NS * STAGE_BYTES <= 160 * 1024, "LDS");
   static_assert(MIXED_PAD % BM == 0 && MIXED_PAD % BN == 0, "tile must divide the padding");
 };
 
@@ -74,14 +96,15 @@ __device__ __forceinline__ void split_store(double v, _Float16* hi, _Float16* lo
   *lo = (_Float16)(float)(v - (double)h);
 }
 
-// One output tile (see f64_tile); ends with a barrier.
-template <int EPI, class Cfg>
-__device__ __forceinline__ void mixed_tile(const MixedItem& it, const int n, const int k_half, const bool two_halves,
-                                           const int2 tile, const double beta_arg) {
+// Main loop with register staging: global -> registers -> LDS (double buffer).
+// Leaves the FP32 sums in acc; ends with a barrier.
+template <class Cfg>
+__device__ __forceinline__ void mixed_mainloop_lds(const MixedItem& it, const int n, const int k_half,
+                                                   const bool two_halves, const int m0, const int n0,
+                                                   f16x (&acc)[Cfg::WTM][Cfg::WTN]) {
   constexpr int BM = Cfg::BM, BN = Cfg::BN, BK = Cfg::BK, KP = Cfg::KP;
   constexpr int WTM = Cfg::WTM, WTN = Cfg::WTN;
   constexpr int CPR = BK / 8;  // 16-byte chunks per row per matrix
-  const int m0 = tile.x * BM, n0 = tile.y * BN;
 
   // [buf][hi/lo][row][k]
   __shared__ __attribute__((aligned(16))) _Float16 As[2][2][BM][KP];
@@ -93,7 +116,6 @@ __device__ __forceinline__ void mixed_tile(const MixedItem& it, const int n, con
   const int wm = wave / Cfg::WAVES_N, wn = wave % Cfg::WAVES_N;
   const int l32 = lane & 31, lh = lane >> 5;
 
-  f16x acc[WTM][WTN];
   f16x tot[Cfg::FLUSH > 0 ? WTM : 1][Cfg::FLUSH > 0 ? WTN : 1];
 #pragma unroll
   for (int i = 0; i < WTM; ++i)
@@ -234,7 +256,18 @@ __device__ __forceinline__ void mixed_tile(const MixedItem& it, const int n, con
 #pragma unroll
       for (int j = 0; j < WTN; ++j) acc[i][j] = tot[i][j];
   }
+}
 
+// Epilogue of a split-precision tile (both forms of the main loop).
+template <int EPI, class Cfg>
+__device__ __forceinline__ void mixed_epilogue(const MixedItem& it, const int n, const int2 tile, const double beta_arg,
+                                               const f16x (&acc)[Cfg::WTM][Cfg::WTN]) {
+  constexpr int BM = Cfg::BM, BN = Cfg::BN;
+  constexpr int WTM = Cfg::WTM, WTN = Cfg::WTN;
+  const int m0 = tile.x * BM, n0 = tile.y * BN;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wm = wave / Cfg::WAVES_N, wn = wave % Cfg::WAVES_N;
+  const int l32 = lane & 31, lh = lane >> 5;
   // Accumulator element (i, j, r) of this lane:
   //   m = m0 + wm*(BM/WAVES_M) + i*32 + 8*(r/4) + 4*lh + r%4,  n = n0 + wn*(BN/WAVES_N) + j*32 + l32.
   const double inv = it.sc[0];
@@ -290,6 +323,173 @@ __device__ __forceinline__ void mixed_tile(const MixedItem& it, const int n, con
   }
 }
 
+// Wait until at most N vector-memory operations of this wave are outstanding
+// (vmcnt = N; expcnt and lgkmcnt left at their maxima, i.e. not waited on).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+
+// Main loop with direct-to-LDS loads (gfx950 LDS DMA). Each wave instruction
+// global_load_lds_dwordx4 copies 16 bytes per lane into 1 KB of LDS at lane
+// order, i.e. 16 rows x 32 halves of one operand; a stage (K = 32) of A_hi,
+// A_lo, B_hi, B_lo is 2 (BM + BN) / 16 such blocks, shared out over the waves.
+// Stages go into a ring of NS slots and are issued NS - 1 stages ahead, with no
+// staging registers. Within a block, row r (0..15) holds its four 16-byte
+// k-chunks c at slot 4 r + (c ^ f(r)), f(r) = (((r >> 1) ^ (r >> 3)) & 1) |
+// (((r >> 2) & 1) << 1), so that the 16 (or 8) lanes of one LDS read pass,
+// which read 16 consecutive rows at one chunk, fall in distinct banks. Each
+// lane loads the global chunk that belongs at its slot. Leaves the FP32 sums
+// in acc; ends with a barrier.
+template <class Cfg>
+__device__ __forceinline__ void mixed_mainloop_dl(const MixedItem& it, const int n, const int k_half,
+                                                  const bool two_halves, const int m0, const int n0,
+                                                  f16x (&acc)[Cfg::WTM][Cfg::WTN]) {
+  constexpr int BM = Cfg::BM, BN = Cfg::BN, BK = 32, NS = Cfg::NS, PW = Cfg::PER_WAVE;
+  constexpr int WTM = Cfg::WTM, WTN = Cfg::WTN;
+  constexpr int A_BLK = Cfg::A_BLK, B_BLK = Cfg::B_BLK, SB = Cfg::STAGE_BYTES;
+  __shared__ __attribute__((aligned(1024))) unsigned char ring[NS * SB];
+
+  const int tid = threadIdx.x;
+  const int nk = (two_halves ? 2 * k_half : k_half) / BK;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wm = wave / Cfg::WAVES_N, wn = wave % Cfg::WAVES_N;
+  const int l32 = lane & 31, lh = lane >> 5;
+  // this lane's row and chunk inside a 16-row block
+  const int rr = lane >> 2;
+  const int fr = (((rr >> 1) ^ (rr >> 3)) & 1) | (((rr >> 2) & 1) << 1);
+  const int gch = (lane & 3) ^ fr;
+
+  f16x tot[Cfg::FLUSH > 0 ? WTM : 1][Cfg::FLUSH > 0 ? WTN : 1];
+#pragma unroll
+  for (int i = 0; i < WTM; ++i)
+#pragma unroll
+    for (int j = 0; j < WTN; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+  if constexpr (Cfg::FLUSH > 0) {
+#pragma unroll
+    for (int i = 0; i < WTM; ++i)
+#pragma unroll
+      for (int j = 0; j < WTN; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) tot[i][j][r] = 0.f;
+  }
+
+  auto issue = [&](int kt) __attribute__((always_inline)) {
+    int k0 = kt * BK;
+    const _Float16 *ah = it.a0h, *al = it.a0l, *bh = it.b0h, *bl = it.b0l;
+    if (two_halves && k0 >= k_half) {
+      ah = it.a1h; al = it.a1l; bh = it.b1h; bl = it.b1l; k0 -= k_half;
+    }
+    unsigned char* slot = ring + (kt % NS) * SB;
+#pragma unroll
+    for (int j = 0; j < PW; ++j) {
+      const int blk = wave * PW + j;  // wave-uniform
+      const _Float16* src;
+      int row0;
+      if (blk < A_BLK) { src = ah; row0 = m0 + blk * 16; }
+      else if (blk < 2 * A_BLK) { src = al; row0 = m0 + (blk - A_BLK) * 16; }
+      else if (blk < 2 * A_BLK + B_BLK) { src = bh; row0 = n0 + (blk - 2 * A_BLK) * 16; }
+      else { src = bl; row0 = n0 + (blk - 2 * A_BLK - B_BLK) * 16; }
+      const _Float16* g = src + (size_t)(row0 + rr) * n + k0 + gch * 8;
+      __builtin_amdgcn_global_load_lds((const void*)g,
+                                       (void __attribute__((address_space(3)))*)(slot + blk * 1024), 16, 0, 0);
+    }
+  };
+
+#pragma unroll
+  for (int s = 0; s < NS - 1; ++s)
+    if (s < nk) issue(s);
+
+  for (int kt = 0; kt < nk; ++kt) {
+    // this wave's loads of stage kt are done once at most min(NS-2, nk-1-kt) later stages remain
+    const int ahead = min(NS - 2, nk - 1 - kt);
+    if constexpr (NS >= 5) { if (ahead >= 3) wait_vmcnt<3 * PW>(); }
+    if constexpr (NS >= 4) { if (ahead == 2) wait_vmcnt<2 * PW>(); }
+    if constexpr (NS >= 3) { if (ahead == 1) wait_vmcnt<PW>(); }
+    if (ahead <= 0) wait_vmcnt<0>();
+    __builtin_amdgcn_s_barrier();  // every wave's part of stage kt is in LDS; slot (kt-1) % NS is free
+    if (kt + NS - 1 < nk) issue(kt + NS - 1);
+    const unsigned char* slot = ring + (kt % NS) * SB;
+    const unsigned char* Ah = slot;
+    const unsigned char* Al = slot + A_BLK * 1024;
+    const unsigned char* Bh = slot + 2 * A_BLK * 1024;
+    const unsigned char* Bl = Bh + B_BLK * 1024;
+#pragma unroll
+    for (int ks = 0; ks < BK / 16; ++ks) {
+      h8 ah[WTM], al[WTM], bh[WTN], bl[WTN];
+      const int c = ks * 2 + lh;
+#pragma unroll
+      for (int i = 0; i < WTM; ++i) {
+        const int r = wm * (BM / Cfg::WAVES_M) + i * 32 + l32;
+        const int rb = r & 15;
+        const int f = (((rb >> 1) ^ (rb >> 3)) & 1) | (((rb >> 2) & 1) << 1);
+        const int off = r * 64 + ((c ^ f) << 4);
+        ah[i] = *reinterpret_cast<const h8*>(Ah + off);
+        al[i] = *reinterpret_cast<const h8*>(Al + off);
+      }
+#pragma unroll
+      for (int j = 0; j < WTN; ++j) {
+        const int r = wn * (BN / Cfg::WAVES_N) + j * 32 + l32;
+        const int rb = r & 15;
+        const int f = (((rb >> 1) ^ (rb >> 3)) & 1) | (((rb >> 2) & 1) << 1);
+        const int off = r * 64 + ((c ^ f) << 4);
+        bh[j] = *reinterpret_cast<const h8*>(Bh + off);
+        bl[j] = *reinterpret_cast<const h8*>(Bl + off);
+      }
+#pragma unroll
+      for (int i = 0; i < WTM; ++i)
+#pragma unroll
+        for (int j = 0; j < WTN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(al[i], bh[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < WTM; ++i)
+#pragma unroll
+        for (int j = 0; j < WTN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < WTM; ++i)
+#pragma unroll
+        for (int j = 0; j < WTN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+    }
+    if constexpr (Cfg::FLUSH > 0) {
+      if ((kt + 1) % Cfg::FLUSH == 0 || kt + 1 == nk) {
+#pragma unroll
+        for (int i = 0; i < WTM; ++i)
+#pragma unroll
+          for (int j = 0; j < WTN; ++j) {
+            tot[i][j] += acc[i][j];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+          }
+      }
+    }
+  }
+  __syncthreads();  // all reads of the ring done before a persistent workgroup's next tile
+  if constexpr (Cfg::FLUSH > 0) {
+#pragma unroll
+    for (int i = 0; i < WTM; ++i)
+#pragma unroll
+      for (int j = 0; j < WTN; ++j) acc[i][j] = tot[i][j];
+  }
+}
+
+// One output tile (see f64_tile); ends with a barrier.
+template <int EPI, class Cfg>
+__device__ __forceinline__ void mixed_tile(const MixedItem& it, const int n, const int k_half, const bool two_halves,
+                                           const int2 tile, const double beta_arg) {
+  const int m0 = tile.x * Cfg::BM, n0 = tile.y * Cfg::BN;
+  f16x acc[Cfg::WTM][Cfg::WTN];
+  if constexpr (Cfg::DL)
+    mixed_mainloop_dl<Cfg>(it, n, k_half, two_halves, m0, n0, acc);
+  else
+    mixed_mainloop_lds<Cfg>(it, n, k_half, two_halves, m0, n0, acc);
+  mixed_epilogue<EPI, Cfg>(it, n, tile, beta_arg, acc);
+}
+
 template <int EPI, class Cfg>
 __global__ __launch_bounds__(Cfg::THREADS, Cfg::MIN_BLOCKS) void gemm_mixed(const MixedArgs args) {
   if (args.stop != nullptr && *args.stop != 0) return;
@@ -314,6 +514,10 @@ using MCfg128x256f8 = MixedCfg<128, 256, 32, 2, 2, 1, 8>;
 using MCfg256x128w8f8 = MixedCfg<256, 128, 32, 4, 2, 1, 8>;
 using MCfg128x128k64f4 = MixedCfg<128, 128, 64, 2, 2, 1, 4>;
 using MCfg128x128w8f8 = MixedCfg<128, 128, 32, 4, 2, 2, 8>;
+using MDl128x128n3 = MixedDlCfg<128, 128, 4, 2, 3, 8>;
+using MDl128x128n4 = MixedDlCfg<128, 128, 4, 2, 4, 8>;
+using MDl128x128n5 = MixedDlCfg<128, 128, 4, 2, 5, 8>;
+using MDl256x128n3 = MixedDlCfg<256, 128, 4, 2, 3, 8>;
 
 // Default: 128 x 128 tiles of 8 waves (32 x 64 each), K stage 32, flush every 8 stages, two
 // workgroups (16 waves) per CU. At Nb = 9216 it beat the 4-wave 64 x 64 shape by 2-3 %, and
@@ -430,6 +634,54 @@ __global__ void const_scales(const double* __restrict__ cmax, const double* __re
     out[2] = sqrt(sm[2][0]);
     out[3] = sqrt(sm[3][0]);
   }
+}
+
+// Gauge centring of direction b's potentials before they are split: a potential
+// shift c common to both spins and all orbitals changes H1 by c S, so X by c I,
+// and leaves the response exactly zero (the shared chemical potential moves by c).
+// Subtracting c keeps the response and removes what would otherwise cancel only
+// after the low-precision products: with c the w-weighted mean of u~ over both
+// spins (w = beta f (1 - f), the weights of the chemical-potential shift), the
+// large common part of gamma v_q and the part the chemical-potential shift takes
+// back are both gone. Falls back to the midrange of u~ when sum w = 0.
+// One block of 1024 threads per direction.
+__device__ __forceinline__ void center_potentials_dev(double* __restrict__ u, int np, int nb,
+                                                      const double* __restrict__ w0, const double* __restrict__ w1,
+                                                      const int* __restrict__ stop, int b) {
+  if (stop != nullptr && *stop != 0) return;
+  __shared__ double sh[17];
+  __shared__ double smin[1024], smax[1024];
+  double* u0 = u + (size_t)(2 * b) * np;
+  double* u1 = u0 + np;
+  double lo = 1e300, hi = -1e300, su = 0.0, sw = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+    lo = fmin(lo, fmin(u0[i], u1[i]));
+    hi = fmax(hi, fmax(u0[i], u1[i]));
+    su += w0[i] * u0[i] + w1[i] * u1[i];
+    sw += w0[i] + w1[i];
+  }
+  su = block_sum(su, sh);
+  sw = block_sum(sw, sh);
+  smin[threadIdx.x] = lo;
+  smax[threadIdx.x] = hi;
+  __syncthreads();
+  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) {
+      smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + st]);
+      smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + st]);
+    }
+    __syncthreads();
+  }
+  const double c = sw > 0.0 ? su / sw : 0.5 * (smin[0] + smax[0]);
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+    u0[i] -= c;
+    u1[i] -= c;
+  }
+}
+
+__global__ void center_potentials(double* __restrict__ u, int np, int nb, const double* __restrict__ w0,
+                                  const double* __restrict__ w1, const int* __restrict__ stop) {
+  center_potentials_dev(u, np, nb, w0, w1, stop, blockIdx.x);
 }
 
 // Per response item z = 2 b + s: scales of the split operands. With

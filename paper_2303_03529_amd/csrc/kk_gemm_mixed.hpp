@@ -85,7 +85,7 @@ struct MixedDlCfg {
   static constexpr int STAGE_BYTES = STAGE_BLK * 1024;
   static_assert(STAGE_BLK % WAVES == 0, "DMA blocks per wave");
   static_assert(BM % (32 * WAVES_M) == 0 && BN % (32 * WAVES_N) == 0, "wave tiling");
-  static_assert(NS >= 2 && NS <= 5, "ring depth");
+  static_assert(NS >= 3 && NS <= 5, "ring depth");
   static_assert(NS * STAGE_BYTES <= 160 * 1024, "LDS");
   static_assert(MIXED_PAD % BM == 0 && MIXED_PAD % BN == 0, "tile must divide the padding");
 };
@@ -339,16 +339,24 @@ __device__ __forceinline__ void wait_vmcnt() {
 // staging registers. Within a block, row r (0..15) holds its four 16-byte
 // k-chunks c at slot 4 r + (c ^ f(r)), f(r) = (((r >> 1) ^ (r >> 3)) & 1) |
 // (((r >> 2) & 1) << 1), so that the 16 (or 8) lanes of one LDS read pass,
-// which read 16 consecutive rows at one chunk, fall in distinct banks. Each
-// lane loads the global chunk that belongs at its slot. Leaves the FP32 sums
-// in acc; ends with a barrier.
+// which read 16 consecutive rows at one chunk, fall in distinct banks; each
+// lane loads the global chunk that belongs at its slot.
+//
+// The LDS -> register fragment reads are software pipelined: the fragments of the next 16-wide K step (the second half of this
+// stage, or the first half of the next stage after its barrier) are read while
+// the MFMAs of the current step run, so a wave no longer stalls on each LDS read
+// before its products. Two fragment register sets alternate. The barrier before
+// a stage waits for every wave's DMA of that stage and also for
+// this wave's reads of the previous stage (lgkmcnt 0), so its slot can be refilled.
+// Leaves the FP32 sums in acc; ends with a barrier.
 template <class Cfg>
 __device__ __forceinline__ void mixed_mainloop_dl(const MixedItem& it, const int n, const int k_half,
-                                                  const bool two_halves, const int m0, const int n0,
-                                                  f16x (&acc)[Cfg::WTM][Cfg::WTN]) {
+                                                       const bool two_halves, const int m0, const int n0,
+                                                       f16x (&acc)[Cfg::WTM][Cfg::WTN]) {
   constexpr int BM = Cfg::BM, BN = Cfg::BN, BK = 32, NS = Cfg::NS, PW = Cfg::PER_WAVE;
   constexpr int WTM = Cfg::WTM, WTN = Cfg::WTN;
   constexpr int A_BLK = Cfg::A_BLK, B_BLK = Cfg::B_BLK, SB = Cfg::STAGE_BYTES;
+  static_assert(NS >= 3, "the pipelined loop refills a slot one stage after reading it");
   __shared__ __attribute__((aligned(1024))) unsigned char ring[NS * SB];
 
   const int tid = threadIdx.x;
@@ -356,10 +364,24 @@ __device__ __forceinline__ void mixed_mainloop_dl(const MixedItem& it, const int
   const int wave = tid >> 6, lane = tid & 63;
   const int wm = wave / Cfg::WAVES_N, wn = wave % Cfg::WAVES_N;
   const int l32 = lane & 31, lh = lane >> 5;
-  // this lane's row and chunk inside a 16-row block
   const int rr = lane >> 2;
   const int fr = (((rr >> 1) ^ (rr >> 3)) & 1) | (((rr >> 2) & 1) << 1);
   const int gch = (lane & 3) ^ fr;
+
+  // per-lane LDS byte offsets of the fragment rows (chunk swizzle applied per K step)
+  int aoff[WTM], boff[WTN], af[WTM], bf[WTN];
+#pragma unroll
+  for (int i = 0; i < WTM; ++i) {
+    const int r = wm * (BM / Cfg::WAVES_M) + i * 32 + l32, rb = r & 15;
+    aoff[i] = r * 64;
+    af[i] = (((rb >> 1) ^ (rb >> 3)) & 1) | (((rb >> 2) & 1) << 1);
+  }
+#pragma unroll
+  for (int j = 0; j < WTN; ++j) {
+    const int r = wn * (BN / Cfg::WAVES_N) + j * 32 + l32, rb = r & 15;
+    boff[j] = r * 64;
+    bf[j] = (((rb >> 1) ^ (rb >> 3)) & 1) | (((rb >> 2) & 1) << 1);
+  }
 
   f16x tot[Cfg::FLUSH > 0 ? WTM : 1][Cfg::FLUSH > 0 ? WTN : 1];
 #pragma unroll
@@ -377,11 +399,15 @@ __device__ __forceinline__ void mixed_mainloop_dl(const MixedItem& it, const int
         for (int r = 0; r < 16; ++r) tot[i][j][r] = 0.f;
   }
 
+  // operand pointers read from the kernel arguments once (scalar loads inside the loop
+  // would force lgkmcnt(0) waits and serialize the pipelined LDS reads)
+  const _Float16 *const p0[4] = {it.a0h, it.a0l, it.b0h, it.b0l};
+  const _Float16 *const p1[4] = {it.a1h, it.a1l, it.b1h, it.b1l};
   auto issue = [&](int kt) __attribute__((always_inline)) {
     int k0 = kt * BK;
-    const _Float16 *ah = it.a0h, *al = it.a0l, *bh = it.b0h, *bl = it.b0l;
+    const _Float16 *ah = p0[0], *al = p0[1], *bh = p0[2], *bl = p0[3];
     if (two_halves && k0 >= k_half) {
-      ah = it.a1h; al = it.a1l; bh = it.b1h; bl = it.b1l; k0 -= k_half;
+      ah = p1[0]; al = p1[1]; bh = p1[2]; bl = p1[3]; k0 -= k_half;
     }
     unsigned char* slot = ring + (kt % NS) * SB;
 #pragma unroll
@@ -398,76 +424,83 @@ __device__ __forceinline__ void mixed_mainloop_dl(const MixedItem& it, const int
                                        (void __attribute__((address_space(3)))*)(slot + blk * 1024), 16, 0, 0);
     }
   };
+  // stage s landed for every wave; s - 1's slot free; refill it with stage s + NS - 1
+  auto enter_stage = [&](int s) __attribute__((always_inline)) {
+    const int ahead = min(NS - 2, nk - 1 - s);
+    if constexpr (NS >= 5) { if (ahead >= 3) wait_vmcnt<3 * PW>(); }
+    if constexpr (NS >= 4) { if (ahead == 2) wait_vmcnt<2 * PW>(); }
+    if (ahead == 1) wait_vmcnt<PW>();
+    if (ahead <= 0) wait_vmcnt<0>();
+    __builtin_amdgcn_s_waitcnt(15 | (7 << 4) | (3 << 14));  // lgkmcnt(0): this wave's reads of stage s-1 done
+    __builtin_amdgcn_s_barrier();
+    if (s + NS - 1 < nk) issue(s + NS - 1);
+  };
+  auto load = [&](h8 (&xa)[WTM][2], h8 (&xb)[WTN][2], int s, int ks) __attribute__((always_inline)) {
+    const unsigned char* slot = ring + (s % NS) * SB;
+    const int c = ks * 2 + lh;
+#pragma unroll
+    for (int i = 0; i < WTM; ++i) {
+      const int off = aoff[i] + ((c ^ af[i]) << 4);
+      xa[i][0] = *reinterpret_cast<const h8*>(slot + off);
+      xa[i][1] = *reinterpret_cast<const h8*>(slot + A_BLK * 1024 + off);
+    }
+#pragma unroll
+    for (int j = 0; j < WTN; ++j) {
+      const int off = boff[j] + ((c ^ bf[j]) << 4);
+      xb[j][0] = *reinterpret_cast<const h8*>(slot + 2 * A_BLK * 1024 + off);
+      xb[j][1] = *reinterpret_cast<const h8*>(slot + (2 * A_BLK + B_BLK) * 1024 + off);
+    }
+  };
+  auto mfma = [&](const h8 (&xa)[WTM][2], const h8 (&xb)[WTN][2]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int i = 0; i < WTM; ++i)
+#pragma unroll
+      for (int j = 0; j < WTN; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(xa[i][1], xb[j][0], acc[i][j], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < WTM; ++i)
+#pragma unroll
+      for (int j = 0; j < WTN; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(xa[i][0], xb[j][1], acc[i][j], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < WTM; ++i)
+#pragma unroll
+      for (int j = 0; j < WTN; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(xa[i][0], xb[j][0], acc[i][j], 0, 0, 0);
+  };
 
+  h8 pa[WTM][2], pb[WTN][2], qa[WTM][2], qb[WTN][2];
 #pragma unroll
   for (int s = 0; s < NS - 1; ++s)
     if (s < nk) issue(s);
-
-  for (int kt = 0; kt < nk; ++kt) {
-    // this wave's loads of stage kt are done once at most min(NS-2, nk-1-kt) later stages remain
-    const int ahead = min(NS - 2, nk - 1 - kt);
-    if constexpr (NS >= 5) { if (ahead >= 3) wait_vmcnt<3 * PW>(); }
-    if constexpr (NS >= 4) { if (ahead == 2) wait_vmcnt<2 * PW>(); }
-    if constexpr (NS >= 3) { if (ahead == 1) wait_vmcnt<PW>(); }
-    if (ahead <= 0) wait_vmcnt<0>();
-    __builtin_amdgcn_s_barrier();  // every wave's part of stage kt is in LDS; slot (kt-1) % NS is free
-    if (kt + NS - 1 < nk) issue(kt + NS - 1);
-    const unsigned char* slot = ring + (kt % NS) * SB;
-    const unsigned char* Ah = slot;
-    const unsigned char* Al = slot + A_BLK * 1024;
-    const unsigned char* Bh = slot + 2 * A_BLK * 1024;
-    const unsigned char* Bl = Bh + B_BLK * 1024;
-#pragma unroll
-    for (int ks = 0; ks < BK / 16; ++ks) {
-      h8 ah[WTM], al[WTM], bh[WTN], bl[WTN];
-      const int c = ks * 2 + lh;
-#pragma unroll
-      for (int i = 0; i < WTM; ++i) {
-        const int r = wm * (BM / Cfg::WAVES_M) + i * 32 + l32;
-        const int rb = r & 15;
-        const int f = (((rb >> 1) ^ (rb >> 3)) & 1) | (((rb >> 2) & 1) << 1);
-        const int off = r * 64 + ((c ^ f) << 4);
-        ah[i] = *reinterpret_cast<const h8*>(Ah + off);
-        al[i] = *reinterpret_cast<const h8*>(Al + off);
-      }
-#pragma unroll
-      for (int j = 0; j < WTN; ++j) {
-        const int r = wn * (BN / Cfg::WAVES_N) + j * 32 + l32;
-        const int rb = r & 15;
-        const int f = (((rb >> 1) ^ (rb >> 3)) & 1) | (((rb >> 2) & 1) << 1);
-        const int off = r * 64 + ((c ^ f) << 4);
-        bh[j] = *reinterpret_cast<const h8*>(Bh + off);
-        bl[j] = *reinterpret_cast<const h8*>(Bl + off);
-      }
-#pragma unroll
-      for (int i = 0; i < WTM; ++i)
-#pragma unroll
-        for (int j = 0; j < WTN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(al[i], bh[j], acc[i][j], 0, 0, 0);
-#pragma unroll
-      for (int i = 0; i < WTM; ++i)
-#pragma unroll
-        for (int j = 0; j < WTN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[i], bl[j], acc[i][j], 0, 0, 0);
-#pragma unroll
-      for (int i = 0; i < WTM; ++i)
-#pragma unroll
-        for (int j = 0; j < WTN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[i], bh[j], acc[i][j], 0, 0, 0);
-    }
+  auto flush = [&]() __attribute__((always_inline)) {
     if constexpr (Cfg::FLUSH > 0) {
-      if ((kt + 1) % Cfg::FLUSH == 0 || kt + 1 == nk) {
 #pragma unroll
-        for (int i = 0; i < WTM; ++i)
+      for (int i = 0; i < WTM; ++i)
 #pragma unroll
-          for (int j = 0; j < WTN; ++j) {
-            tot[i][j] += acc[i][j];
+        for (int j = 0; j < WTN; ++j) {
+          tot[i][j] += acc[i][j];
 #pragma unroll
-            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
-          }
-      }
+          for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+        }
     }
+  };
+  enter_stage(0);
+  load(pa, pb, 0, 0);
+  // the last stage is peeled off so that no branch sits between a fragment read and
+  // its use (a join would make the LDS wait count conservative, i.e. wait for all)
+  for (int kt = 0; kt < nk - 1; ++kt) {
+    load(qa, qb, kt, 1);  // second half of this stage, read during the first half's products
+    mfma(pa, pb);
+    enter_stage(kt + 1);
+    load(pa, pb, kt + 1, 0);  // first half of the next stage, read during this stage's second half
+    mfma(qa, qb);
+    if ((kt + 1) % (Cfg::FLUSH > 0 ? Cfg::FLUSH : 1) == 0) flush();
   }
+  load(qa, qb, nk - 1, 1);
+  mfma(pa, pb);
+  mfma(qa, qb);
+  flush();
   __syncthreads();  // all reads of the ring done before a persistent workgroup's next tile
   if constexpr (Cfg::FLUSH > 0) {
 #pragma unroll
@@ -508,22 +541,24 @@ using MCfg256x256 = MixedCfg<256, 256, 32, 2, 4, 1>;
 using MCfg256x256f8 = MixedCfg<256, 256, 32, 2, 4, 1, 8>;
 using MCfg128x256 = MixedCfg<128, 256, 32, 2, 4, 1>;
 using MCfg64x64f8 = MixedCfg<64, 64, 32, 2, 2, 4, 8>;  // small systems of a batch
-using MCfg128x128k16f16 = MixedCfg<128, 128, 16, 2, 2, 3, 16>;
 using MCfg128x128k16f16b2 = MixedCfg<128, 128, 16, 2, 2, 2, 16>;
 using MCfg128x256f8 = MixedCfg<128, 256, 32, 2, 2, 1, 8>;
 using MCfg256x128w8f8 = MixedCfg<256, 128, 32, 4, 2, 1, 8>;
 using MCfg128x128k64f4 = MixedCfg<128, 128, 64, 2, 2, 1, 4>;
 using MCfg128x128w8f8 = MixedCfg<128, 128, 32, 4, 2, 2, 8>;
+// Direct-to-LDS shapes (one workgroup per CU). At Nb = 9216: 256 x 128 with a
+// 3-stage ring 254 / 295 TFLOP/s (forward / back, algorithmic), 128 x 128 with 3
+// stages 245 / 267, against 253 / 289 for the register-staged default.
 using MDl128x128n3 = MixedDlCfg<128, 128, 4, 2, 3, 8>;
 using MDl128x128n4 = MixedDlCfg<128, 128, 4, 2, 4, 8>;
-using MDl128x128n5 = MixedDlCfg<128, 128, 4, 2, 5, 8>;
 using MDl256x128n3 = MixedDlCfg<256, 128, 4, 2, 3, 8>;
 
 // Default: 128 x 128 tiles of 8 waves (32 x 64 each), K stage 32, flush every 8 stages, two
 // workgroups (16 waves) per CU. At Nb = 9216 it beat the 4-wave 64 x 64 shape by 2-3 %, and
 // shorter K stages (16), longer ones (64, one workgroup per CU) and wider tiles (128 x 256,
-// 256 x 128) by 5-25 %: the kernel is bound by exposed load latency, not by LDS bandwidth
-// (no bank conflicts; LDS busy ~27 %, MFMA busy ~40 % of cycles).
+// 256 x 128) by 5-25 %; the direct-to-LDS shapes above come within 2 % of it. Counters: no
+// LDS bank conflicts, LDS busy ~27 % and MFMA busy ~40 % of cycles, while the chip clock drops
+// to ~1.7 GHz during these kernels (2.4 GHz during the FP64 ones).
 #ifndef KK_MFWD_CFG
 #define KK_MFWD_CFG MCfg128x128w8f8
 #endif

@@ -194,7 +194,7 @@ kk_status kk_xlbomd_update(kk_handle h, const double *n_hist, int k_max, const d
  *                  u = gamma v_q +/- W v_m only (not symmetrized: dL = sum_IJ
  *                  gamma_bar_IJ d gamma_IJ)
  *   W_bar          1 double: dL/dW through the response potentials only
- *   H_bar_up, H_bar_dn  Nb x Nb each: dL/dH^sigma with respect to the spin
+ *   H_bar_up, H_bar_dn  Nb x Nb each, or both NULL: dL/dH^sigma with respect to the spin
  *                  Hamiltonians of the prepared expansion point (the H whose
  *                  Z^T H Z has the eigenpairs given to kk_prepare), through the
  *                  levels, the eigenvectors, the occupations and the shared mu
@@ -204,15 +204,21 @@ kk_status kk_xlbomd_update(kk_handle h, const double *n_hist, int k_max, const d
  *                  construction; the expansion-point dependence on gamma and W
  *                  (through H^sigma) is left to that chain.
  * The per-direction response matrices are recomputed in the reverse sweep,
- * never stored: the workspace is 12 padded Nb^2 FP64 matrices plus O(N m),
- * allocated on first use and kept by the handle. Levels closer than 1e-3 kT
- * (exact degeneracies included) are handled through second divided
- * differences of the Fermi function. With a breakdown (rank r < m) the rank-r
- * expansion is differentiated and KK_BREAKDOWN is returned. The forward
- * expansion runs in the handle's precision; the reverse sweep always runs in
- * FP64 (on a KK_MIXED_F16 handle it differentiates the split-precision
- * forward, with ~1e-7 relative error from it). Synchronizes once (to read the
- * rank) and again if info is not NULL.
+ * never stored. Levels closer than 1e-3 kT (exact degeneracies included) are
+ * handled through second divided differences of the Fermi function. With a
+ * breakdown (rank r < m) the rank-r expansion is differentiated and
+ * KK_BREAKDOWN is returned.
+ * Cost and precision. With H_bar_up = H_bar_dn = NULL only delta_bar,
+ * gamma_bar and W_bar are formed: one transposed response per direction (m
+ * responses, like the forward), in the handle's precision, no workspace beyond
+ * O(N m). With the H gradients the reverse sweep runs its transforms in FP64
+ * on any handle (about 2.5x the forward's FP64 work; 12 padded Nb^2 FP64
+ * matrices of workspace, allocated on first use and kept by the handle): the
+ * expansion-point derivative divides commutators of products by level gaps,
+ * which turns the ~1e-7 error of split-precision products into ~1e-4. On a
+ * KK_MIXED_F16 handle the forward expansion (when recomputed) is split
+ * precision, so the gradient is that of the split forward map (~1e-7 from the
+ * FP64 one). Synchronizes once (to read the rank) and again if info is not NULL.
  */
 kk_status krylov_kernel_adjoint(kk_handle h, const double *delta, int m, const double *K0,
                                 const double *Kdelta_bar, int reuse_forward, double *Kdelta,

@@ -83,15 +83,19 @@ def _fermi_parts(eps, mu, beta):
     return f, fc, F
 
 
-def kernel_loss(sysd: dict, delta, U, W, H0, m: int, K0=None, return_parts: bool = False):
-    """L = ||K delta||^2 as a torch scalar (all arguments torch tensors on the CPU)."""
+def kernel_loss(sysd: dict, delta, U, W, H0, m: int, K0=None, return_parts: bool = False, gamma=None):
+    """L = ||K delta||^2 as a torch scalar (all arguments torch tensors on the CPU).
+
+    gamma, if given, is used instead of gamma(U) (to differentiate with respect to
+    its entries)."""
     S = torch.as_tensor(sysd["S"], dtype=DT)
     offsets = sysd["offsets"]
     N = sysd["gamma"].shape[0]
     beta = 1.0 / sysd["kT"]
     Z = torch.as_tensor(congruence_lowdin(sysd["S"]), dtype=DT)
     n_ref = torch.as_tensor(sysd["n_ref"], dtype=DT)
-    gamma = gamma_of_U(sysd["r2_bohr"], U, sysd["hartree_ev"])
+    if gamma is None:
+        gamma = gamma_of_U(sysd["r2_bohr"], U, sysd["hartree_ev"])
     Hs = 0.5 * (H0 + H0.T)
 
     # expansion point
@@ -170,3 +174,27 @@ def gradients(sysd: dict, m: int, delta=None, U=None, W=None, H0=None, K0=None) 
     gd, gu, gw, gh = torch.autograd.grad(L, [d, u, wv, h0])
     return dict(L=float(L.detach()), delta=gd.numpy(), U=float(gu), W=float(gw), H0=gh.numpy(),
                 Kdelta=parts["x"].detach().numpy(), rank=parts["rank"])
+
+
+def U_gradient_terms(sysd: dict, m: int) -> np.ndarray:
+    """The N x N terms dL/dgamma_IJ dgamma_IJ/dU whose sum is dL/dU (chain rule through gamma)."""
+    d = torch.tensor(sysd["delta"], dtype=DT)
+    u = torch.tensor(sysd["U"], dtype=DT)
+    wv = torch.tensor(sysd["W"], dtype=DT)
+    h0 = torch.tensor(sysd["H0"], dtype=DT)
+    g = gamma_of_U(sysd["r2_bohr"], u, sysd["hartree_ev"]).detach().requires_grad_(True)
+    (gg,) = torch.autograd.grad(kernel_loss(sysd, d, u, wv, h0, m, gamma=g), [g])
+    h = sysd["hartree_ev"]
+    r2 = torch.as_tensor(sysd["r2_bohr"], dtype=DT)
+    dg = h * (h * h / u ** 3) / (r2 + (h / u) ** 2) ** 1.5      # d gamma_IJ / dU off the diagonal
+    dg = torch.where(torch.eye(r2.shape[0], dtype=torch.bool), torch.ones_like(dg), dg)
+    return (gg * dg).detach().numpy()
+
+
+def U_gradient_scale(sysd: dict, m: int) -> float:
+    """sum_IJ |dL/dgamma_IJ dgamma_IJ/dU|: the size of the terms whose sum is dL/dU.
+
+    dL/dU is a strongly cancelling sum (its terms are a few hundred times larger
+    than the result on the bcc-Fe systems), so an error bound for it is stated
+    relative to this scale."""
+    return float(np.abs(U_gradient_terms(sysd, m)).sum())

@@ -19,7 +19,9 @@ returns dL/dU, dL/dW and dL/dH0 as well:
 Energies are in eV. The forward's eigensolve of Z^T H^sigma Z (Z = S^-1/2)
 is caller-side setup too (torch.linalg.eigh), as for kk_prepare in general.
 With precision KK_MIXED_F16 the forward expansion runs on the split FP16
-transforms and the reverse sweep in FP64.
+transforms; the reverse sweep runs split as well when no gradient with respect
+to the spin Hamiltonians (hence U, W through them, H0) is needed, and in FP64
+otherwise.
 """
 
 from __future__ import annotations
@@ -104,7 +106,9 @@ class KrylovKernel(torch.autograd.Function):
         if not reuse:  # the handle moved on: prepare this expansion point again
             system.handle.prepare(system.offsets, system.S, system.Z, Q_up, Q_dn, e_up, e_dn, gamma, ctx.W,
                                   system.kT, system.n_electrons, system.precision)
-        g = system.handle.krylov_kernel_adjoint(delta, ctx.m, x_bar.contiguous(), reuse_forward=reuse)
+        want_H = ctx.needs_input_grad[3] or ctx.needs_input_grad[4]
+        g = system.handle.krylov_kernel_adjoint(delta, ctx.m, x_bar.contiguous(), reuse_forward=reuse,
+                                                want_H=want_H)
         system.token += 1
         return g["delta"], g["gamma"], g["W"], g["H_up"], g["H_dn"], None, None
 

@@ -283,12 +283,16 @@ int max_chunk(kk_handle h) {
 }
 
 // Responses of `batch` directions v (batch x 2N) into q1 (batch x 2N); batch <= chunk_cap.
-kk_status response_chunk(kk_handle h, int batch, const double* v, double* q1, const int* stop) {
+// identity = true: potentials v_q +/- v_m per atom (gamma = I, W = 1), the transposed-response
+// form the reverse pass needs.
+kk_status response_chunk(kk_handle h, int batch, const double* v, double* q1, const int* stop,
+                         bool identity = false) {
   const int N = h->natoms, np = h->np;
   {
     const int waves = N * batch, threads = 256;
     const int blocks = (waves * kk::WAVE + threads - 1) / threads;
-    kk::potentials<<<blocks, threads, 0, h->stream>>>(h->gamma, N, h->W, v, batch, h->offsets, np,
+    kk::potentials<<<blocks, threads, 0, h->stream>>>(identity ? nullptr : h->gamma, N, identity ? 1.0 : h->W, v,
+                                                       batch, h->offsets, np,
                                                        h->u, stop);
     LAUNCH_CHECK("potentials");
   }
@@ -341,13 +345,15 @@ kk_status launch_mixed(kk_handle h, int epi, kk::MixedArgs& a) {
 
 // Split-precision responses: same steps as response_chunk, with the two
 // transforms on FP16 x 3 MFMA products (Y kept as an FP16 split).
-kk_status response_chunk_mixed(kk_handle h, int batch, const double* v, double* q1, const int* stop) {
+kk_status response_chunk_mixed(kk_handle h, int batch, const double* v, double* q1, const int* stop,
+                               bool identity = false) {
   const int N = h->natoms, np = h->np;
   const size_t np2 = (size_t)np * np;
   {
     const int waves = N * batch, threads = 256;
     const int blocks = (waves * kk::WAVE + threads - 1) / threads;
-    kk::potentials<<<blocks, threads, 0, h->stream>>>(h->gamma, N, h->W, v, batch, h->offsets, np,
+    kk::potentials<<<blocks, threads, 0, h->stream>>>(identity ? nullptr : h->gamma, N, identity ? 1.0 : h->W, v,
+                                                       batch, h->offsets, np,
                                                        h->u, stop);
     LAUNCH_CHECK("potentials");
   }
@@ -401,9 +407,10 @@ kk_status response_chunk_mixed(kk_handle h, int batch, const double* v, double* 
   return KK_OK;
 }
 
-kk_status response_any(kk_handle h, int batch, const double* v, double* q1, const int* stop) {
-  return h->precision == KK_FP64 ? response_chunk(h, batch, v, q1, stop)
-                                 : response_chunk_mixed(h, batch, v, q1, stop);
+kk_status response_any(kk_handle h, int batch, const double* v, double* q1, const int* stop,
+                       bool identity = false) {
+  return h->precision == KK_FP64 ? response_chunk(h, batch, v, q1, stop, identity)
+                                 : response_chunk_mixed(h, batch, v, q1, stop, identity);
 }
 
 kk_status check_handle(kk_handle h) {
@@ -803,8 +810,9 @@ namespace {
 // Mulliken partial rows per spin written by the FP64 back-transform of the reverse pass.
 int adj_nparts(kk_handle h) { return (h->np / kk::BackCfg::BN) * kk::BackCfg::WAVES_N; }
 
-kk_status ensure_adjoint(kk_handle h) {
-  if (!h->adj_owned.empty()) return KK_OK;
+// Reverse-pass workspace: the Krylov vectors always; the 12 padded matrices of the
+// expansion-point part only once a call asks for dL/dH.
+kk_status ensure_adjoint(kk_handle h, bool want_H) {
   const size_t np = h->np, np2 = np * np, n2 = 2 * (size_t)h->natoms;
   kk_status st;
   auto get = [&](double** p, size_t count) -> kk_status {
@@ -813,10 +821,13 @@ kk_status ensure_adjoint(kk_handle h) {
     *p = static_cast<double*>(q);
     return e;
   };
-  if ((st = get(&h->aX, 4 * np2))) return st;
-  if ((st = get(&h->aY, 4 * np2))) return st;
-  if ((st = get(&h->aK, 2 * np2))) return st;
-  if ((st = get(&h->aD, 2 * np2))) return st;
+  if (want_H && !h->aX) {
+    if ((st = get(&h->aX, 4 * np2))) return st;
+    if ((st = get(&h->aY, 4 * np2))) return st;
+    if ((st = get(&h->aK, 2 * np2))) return st;
+    if ((st = get(&h->aD, 2 * np2))) return st;
+  }
+  if (h->ag) return KK_OK;
   if ((st = get(&h->au, 4 * np))) return st;
   if ((st = get(&h->axdiag, 4 * np))) return st;
   if ((st = get(&h->apart, 2 * (size_t)adj_nparts(h) * np))) return st;
@@ -894,15 +905,19 @@ kk_status krylov_kernel_adjoint(kk_handle h, const double* delta, int m, const d
   static const char* who = "krylov_kernel_adjoint";
   kk_status st = check_handle(h);
   if (st) return st;
-  if (!delta || !Kdelta_bar || !delta_bar || !gamma_bar || !W_bar || !H_bar_up || !H_bar_dn)
+  if (!delta || !Kdelta_bar || !delta_bar || !gamma_bar || !W_bar)
     return fail(KK_EINVAL, "%s: NULL array argument", who);
+  if ((H_bar_up == nullptr) != (H_bar_dn == nullptr))
+    return fail(KK_EINVAL, "%s: give both H_bar_up and H_bar_dn, or neither", who);
+  const bool want_H = H_bar_up != nullptr;
   const int N = h->natoms, n2 = 2 * N, np = h->np, nb = h->nb;
   const size_t np2 = (size_t)np * np;
   if (m < 1 || m > std::min(n2, kk::MAX_RANK))
     return fail(KK_EINVAL, "%s: need 1 <= m <= min(2N, %d), got %d", who, kk::MAX_RANK, m);
   const double tau = 1e-3 * h->kT;
 
-  if ((st = ensure_adjoint(h))) return st;
+  if ((st = ensure_adjoint(h, want_H))) return st;
+  if ((st = ensure_workspace(h, 1))) return st;
   // forward expansion: recomputed, or the one the last kernel call left
   if (reuse_forward) {
     if (!h->fwd_valid || h->fwd_m != m || h->fwd_K0 != K0)
@@ -916,16 +931,18 @@ kk_status krylov_kernel_adjoint(kk_handle h, const double* delta, int m, const d
   HIP_OR_FAIL(hipMemcpyAsync(&hs, h->kst, sizeof hs, hipMemcpyDeviceToHost, h->stream));
   HIP_OR_FAIL(hipStreamSynchronize(h->stream));
   if (hs.status == KK_ESINGULAR) return fail(KK_ESINGULAR, "%s: Gram matrix not positive definite", who);
-  if ((st = ensure_pairs(h, tau))) return st;
+  if (want_H && (st = ensure_pairs(h, tau))) return st;
   const int r = hs.rank;
-  const int npairs = h->an0 + h->an1;
+  const int npairs = want_H ? h->an0 + h->an1 : 0;
 
-  if ((st = zero(h, h->aK, 2 * np2))) return st;
-  if ((st = zero(h, h->aD, 2 * np2))) return st;
-  if ((st = zero(h, h->agdiag, 2 * (size_t)np))) return st;
+  if (want_H) {
+    if ((st = zero(h, h->aK, 2 * np2))) return st;
+    if ((st = zero(h, h->aD, 2 * np2))) return st;
+    if ((st = zero(h, h->agdiag, 2 * (size_t)np))) return st;
+    if (npairs > 0 && (st = zero(h, h->apk, npairs))) return st;
+  }
   if ((st = zero(h, gamma_bar, (size_t)N * N))) return st;
   if ((st = zero(h, W_bar, 1))) return st;
-  if (npairs > 0 && (st = zero(h, h->apk, npairs))) return st;
 
   kk::adj_init<<<1, 1024, 0, h->stream>>>(h->V, h->Ft, h->ftilde, n2, h->kst, Kdelta_bar, h->aVbar, h->aFbar,
                                           h->abbar);
@@ -949,6 +966,16 @@ kk_status krylov_kernel_adjoint(kk_handle h, const double* delta, int m, const d
     if (K0) {
       kk::gemv_t<<<(n2 + 255) / 256, 256, 0, h->stream>>>(K0, h->alam, n2, h->ay);
       LAUNCH_CHECK("gemv_t");
+    }
+    if (!want_H) {
+      // only g = M chi M y is needed: one response with identity coupling, in the handle's precision
+      if ((st = response_any(h, 1, h->ay, h->ag, nullptr, true))) return st;
+      kk::adj_apply<<<wave_blocks, 256, 0, h->stream>>>(h->gamma, N, h->W, h->ag, h->ay, vk,
+                                                         h->aVbar + (size_t)k * n2, gamma_bar);
+      LAUNCH_CHECK("adj_apply");
+      kk::adj_wbar<<<1, 256, 0, h->stream>>>(h->ag, vk, N, W_bar);
+      LAUNCH_CHECK("adj_wbar");
+      continue;
     }
     // potentials: a = M y (identity coupling), b = M Gamma v_k
     kk::potentials<<<wave_blocks, 256, 0, h->stream>>>(nullptr, N, 1.0, h->ay, 1, h->offsets, np, h->au, nullptr);
@@ -1023,6 +1050,18 @@ kk_status krylov_kernel_adjoint(kk_handle h, const double* delta, int m, const d
     }
   } else if ((st = zero(h, delta_bar, n2))) {
     return st;
+  }
+  if (!want_H) {
+    if (info) {
+      HIP_OR_FAIL(hipStreamSynchronize(h->stream));
+      info->rank_used = hs.rank;
+      info->status = hs.status;
+      info->min_pivot = hs.min_pivot;
+      info->max_pivot = hs.max_pivot;
+      info->ls_residual = hs.ls_residual;
+    }
+    g_err.clear();
+    return hs.status == 1 ? KK_BREAKDOWN : KK_OK;
   }
   // dL/dH^sigma = C E'_bar C^T
   kk::sum_two<<<1, 1024, 0, h->stream>>>(h->agdiag, h->agdiag + np, np, h->agtot);

@@ -201,13 +201,13 @@ class Handle:
         return out, KrylovInfo(inf.rank_used, inf.status, inf.min_pivot, inf.max_pivot, inf.ls_residual)
 
     def krylov_kernel_adjoint(self, delta, m: int, Kdelta_bar, K0=None, reuse_forward: bool = False,
-                              want_Kdelta: bool = False):
+                              want_Kdelta: bool = False, want_H: bool = True):
         """Reverse pass of K delta for x_bar = Kdelta_bar. Synchronizes.
 
         Returns dict(delta, gamma, W, H_up, H_dn, Kdelta (or None), info): the
         gradients of the caller's L with respect to delta, gamma (through the
-        response potentials), W (likewise, a 0-d tensor) and the expansion-point
-        spin Hamiltonians (n_basis x n_basis each).
+        response potentials), W (likewise, a 0-d tensor) and, with want_H, the
+        expansion-point spin Hamiltonians (n_basis x n_basis each; else None).
         """
         import torch
         n, nb = self.n_atoms, self.n_basis
@@ -215,8 +215,11 @@ class Handle:
         dev = delta.device
         kw = dict(dtype=torch.float64, device=dev)
         out = dict(delta=torch.empty(n2, **kw), gamma=torch.empty(n, n, **kw), W=torch.empty((), **kw),
-                   H_up=torch.empty(nb, nb, **kw), H_dn=torch.empty(nb, nb, **kw),
+                   H_up=torch.empty(nb, nb, **kw) if want_H else None,
+                   H_dn=torch.empty(nb, nb, **kw) if want_H else None,
                    Kdelta=torch.empty(n2, **kw) if want_Kdelta and not reuse_forward else None)
+        hup = _dev(out["H_up"], "H_bar_up", nb * nb) if want_H else ctypes.c_void_p()
+        hdn = _dev(out["H_dn"], "H_bar_dn", nb * nb) if want_H else ctypes.c_void_p()
         k0p = _dev(K0, "K0", n2 * n2) if K0 is not None else ctypes.c_void_p()
         kdp = _dev(out["Kdelta"], "Kdelta", n2) if out["Kdelta"] is not None else ctypes.c_void_p()
         inf = KKInfo()
@@ -224,7 +227,7 @@ class Handle:
             self._h, _dev(delta, "delta", n2), int(m), k0p, _dev(Kdelta_bar, "Kdelta_bar", n2),
             1 if reuse_forward else 0, kdp, _dev(out["delta"], "delta_bar", n2),
             _dev(out["gamma"], "gamma_bar", n * n), _dev(out["W"], "W_bar", 1),
-            _dev(out["H_up"], "H_bar_up", nb * nb), _dev(out["H_dn"], "H_bar_dn", nb * nb), ctypes.byref(inf)),
+            hup, hdn, ctypes.byref(inf)),
             "krylov_kernel_adjoint", ok=(KK_OK, KK_BREAKDOWN))
         out["info"] = KrylovInfo(inf.rank_used, inf.status, inf.min_pivot, inf.max_pivot, inf.ls_residual)
         return out

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 import torch
 
-from oracle.adjoint import gamma_of_U, gradients
+from oracle.adjoint import U_gradient_terms, gamma_of_U, gradients
 from oracle.expansion import expansion_point
 from oracle.krylov import jacobian_exact, kernel_apply
 from synth import make_system
@@ -84,3 +84,11 @@ def test_full_rank_delta_gradient_closed_form():
     x = np.linalg.solve(J, sysd["delta"])
     want = 2 * np.linalg.solve(J.T, x)
     assert np.linalg.norm(g["delta"] - want) < 1e-9 * np.linalg.norm(want)
+
+
+def test_U_gradient_terms_sum_to_the_U_gradient(fe16):
+    """The per-entry chain-rule terms through gamma add up to dL/dU (and cancel strongly)."""
+    sysd, g = fe16
+    terms = U_gradient_terms(sysd, 4)
+    assert abs(terms.sum() - g["U"]) < 1e-10 * np.abs(terms).sum()
+    assert np.abs(terms).sum() > 10 * abs(g["U"])

@@ -38,7 +38,7 @@ def gpu_gradients(sysd, m, K0=None, precision=0):
         x = kernel_from_parameters(ks, d, U, W, H0, m)
         L = x @ x
         gd, gu, gw, gh = torch.autograd.grad(L, [d, U, W, H0])
-        return dict(L=float(L), delta=gd.cpu().numpy(), U=float(gu), W=float(gw), H0=gh.cpu().numpy())
+        return dict(L=float(L.detach()), delta=gd.cpu().numpy(), U=float(gu), W=float(gw), H0=gh.cpu().numpy())
     finally:
         ks.close()
 

@@ -75,3 +75,19 @@ def test_xlbomd_electrons_stay_near_ground_state():
     res, n_end = gpu_scf.xlbomd_electrons(sysd, start, steps=12, kappa=1.0, m_max=6, rank_tol=0.05)
     print("XL-BOMD residuals", [f"{r:.1e}" for r in res])
     assert max(res) < 10 * res[0]
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-9), (1, 1e-6)], ids=["fp64", "split"])
+def test_kernel_mixer_scf_fe128_reaches_the_oracle_fixed_point(precision, tol):
+    """128-atom bcc Fe: the GPU SCF with the adaptive-rank kernel mixer converges, and the
+    density it returns is a fixed point of the oracle's own map q[n] (independent
+    diagonalization and Mulliken sums on the CPU)."""
+    from oracle.scf import rms
+    sysd = make_system(4, seed=128)
+    n_gpu, hist = gpu_scf.scf(sysd, sysd["n_ref"], tol=tol, max_iter=60, m_max=8, rank_tol=0.1, switch_at=10.0,
+                              precision=precision)
+    print("GPU SCF fe128", [f"{x['rms']:.1e}/{x['rank']}" for x in hist])
+    assert hist[-1]["mode"] == "done"
+    res = rms(net_q_of_n(sysd, n_gpu) - n_gpu)
+    print(f"oracle residual at the GPU fixed point: {res:.2e}")
+    assert res < 2 * tol

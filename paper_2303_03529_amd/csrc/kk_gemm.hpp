@@ -100,6 +100,9 @@ struct TileCfg {
   static constexpr int WTM = BM / WAVES_M / 16;  // MFMA tiles per wave along m
   static constexpr int WTN = BN / WAVES_N / 16;  // along n
   static constexpr int MIN_BLOCKS = MINB_;
+  // MIN_BLOCKS co-resident workgroups need this many waves per SIMD, which caps
+  // the registers per lane the compiler may use (512 / WAVES_PER_EU).
+  static constexpr int WAVES_PER_EU = (MIN_BLOCKS * THREADS / 64 + 3) / 4;
   // global -> LDS staging: each thread moves double2 pieces
   static constexpr int A_PIECES = BK * BM / 2 / THREADS;
   static constexpr int B_PIECES = BK * BN / 2 / THREADS;
@@ -219,12 +222,8 @@ __device__ __forceinline__ void f64_tile(const GemmItem& it, const int n, const 
         }
   } else if constexpr (EPI == EPI_FERMI || EPI == EPI_FERMI_XY) {
     const double beta = beta_arg;
-    double en[WTN], fn[WTN], fcn[WTN];
-#pragma unroll
-    for (int j = 0; j < WTN; ++j) {
-      const int c = nw + j * 16;
-      en[j] = it.eps[c]; fn[j] = it.f[c]; fcn[j] = it.fc[c];
-    }
+    // Column spectra are re-read per row (cached) rather than held, which keeps the
+    // epilogue inside the main loop's register budget.
 #pragma unroll
     for (int i = 0; i < WTM; ++i)
 #pragma unroll
@@ -235,6 +234,7 @@ __device__ __forceinline__ void f64_tile(const GemmItem& it, const int n, const 
         for (int j = 0; j < WTN; ++j) {
           const int c = nw + j * 16;
           if (m > c) continue;
+          const double en = it.eps[c], fn = it.f[c], fcn = it.fc[c];
           const double x = 0.5 * acc[i][j][r];
           if constexpr (EPI == EPI_FERMI_XY) {
             it.xout[(size_t)m * n + c] = x;
@@ -244,7 +244,7 @@ __device__ __forceinline__ void f64_tile(const GemmItem& it, const int n, const 
             it.xdiag[m] = x;
             it.out[(size_t)m * n + m] = -it.w[m] * x;
           } else {
-            const double y = fermi_divided_difference(em, fm, fcm, en[j], fn[j], fcn[j], beta) * x;
+            const double y = fermi_divided_difference(em, fm, fcm, en, fn, fcn, beta) * x;
             it.out[(size_t)m * n + c] = y;
             it.out[(size_t)c * n + m] = y;
           }

@@ -25,8 +25,6 @@
 
 namespace kk {
 
-constexpr int MIXED_PAD = 256;  // padded dimension of the split-precision path
-
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef float f16x __attribute__((ext_vector_type(16)));
 
@@ -66,7 +64,6 @@ struct MixedCfg {
   static_assert(64 % (BK / 8) == 0 && 16 % (BK / 8) == 0, "piece mapping");
   static_assert(BM % (32 * WAVES_M) == 0 && BN % (32 * WAVES_N) == 0, "wave tiling");
   static_assert(BK % 16 == 0, "BK");
-  static_assert(MIXED_PAD % BM == 0 && MIXED_PAD % BN == 0, "tile must divide the padding");
 };
 
 // Configuration of the direct-to-LDS main loop: BM x BN tile, K stage 32, a ring
@@ -87,7 +84,6 @@ struct MixedDlCfg {
   static_assert(BM % (32 * WAVES_M) == 0 && BN % (32 * WAVES_N) == 0, "wave tiling");
   static_assert(NS >= 3 && NS <= 5, "ring depth");
   static_assert(NS * STAGE_BYTES <= 160 * 1024, "LDS");
-  static_assert(MIXED_PAD % BM == 0 && MIXED_PAD % BN == 0, "tile must divide the padding");
 };
 
 __device__ __forceinline__ void split_store(double v, _Float16* hi, _Float16* lo) {
@@ -567,6 +563,14 @@ using MDl256x128n3 = MixedDlCfg<256, 128, 4, 2, 3, 8>;
 #endif
 using MFwdCfg = KK_MFWD_CFG;
 using MBackCfg = KK_MBACK_CFG;
+
+// Padded dimension of the split-precision path: the largest tile side of the two
+// transforms (128 for the default), so that both tile the padded matrices exactly.
+constexpr int pad_max(int a, int b) { return a > b ? a : b; }
+constexpr int MIXED_PAD = pad_max(pad_max(MFwdCfg::BM, MFwdCfg::BN), pad_max(MBackCfg::BM, MBackCfg::BN));
+static_assert(MIXED_PAD % MFwdCfg::BM == 0 && MIXED_PAD % MFwdCfg::BN == 0 && MIXED_PAD % MBackCfg::BM == 0 &&
+                  MIXED_PAD % MBackCfg::BN == 0,
+              "both transforms' tiles must divide the padding");
 
 // ---------------------------------------------------------------------------
 // Split helpers

@@ -141,49 +141,70 @@ __device__ __forceinline__ void f64_tile(const GemmItem& it, const int n, const 
 #pragma unroll
     for (int j = 0; j < WTN; ++j) acc[i][j] = (d4){0.0, 0.0, 0.0, 0.0};
 
-  // Global -> register -> LDS staging, two stages ahead: stage s is loaded into
-  // register set s % 2 at the start of step s - 2 and written to LDS buffer s % 2 at
-  // the end of step s - 1, so each load has two steps of products to arrive.
-  d2 ra[2][AP], rb[2][BP];
-  auto gload = [&](const int kt, d2 (&xa)[AP], d2 (&xb)[BP]) __attribute__((always_inline)) {
+  // Global -> register -> LDS staging, one stage ahead: the loads of stage kt + 1 are
+  // issued at the start of step kt and written to LDS at its end. The forward
+  // transform's row scale is applied at that write, not at the load, so that no
+  // instruction in the step waits for the loads; and the loads are unconditional (the
+  // last step reloads the last stage, written to the idle buffer and never read), so
+  // that the wait before the write is the only one.
+  constexpr bool SCALED = EPI == EPI_FERMI || EPI == EPI_FERMI_XY;
+  d2 ra[AP], rb[BP];
+  double rs[AP];
+  // Byte offsets of this thread's staging pieces within a K stage (loop invariant, a
+  // few hundred KB at most); the stage's uniform part goes into the base pointers.
+  unsigned aoff[AP], soff[AP], boff[BP];
+#pragma unroll
+  for (int p = 0; p < AP; ++p) {
+    const int idx = tid + p * Cfg::THREADS;
+    const int row = idx / APR, col = (idx % APR) * 2;
+    aoff[p] = (unsigned)(row * n + col) * 8u;
+    soff[p] = (unsigned)row * 8u;
+  }
+#pragma unroll
+  for (int p = 0; p < BP; ++p) {
+    const int idx = tid + p * Cfg::THREADS;
+    const int row = idx / BPR, col = (idx % BPR) * 2;
+    boff[p] = (unsigned)(row * n + col) * 8u;
+  }
+  auto gload = [&](const int kt) __attribute__((always_inline)) {
     int k0 = kt * BK;
     const double* A = it.a0;
     const double* B = it.b0;
     if (two_halves && k0 >= k_half) {
       A = it.a1; B = it.b1; k0 -= k_half;
     }
+    const char* Ab = reinterpret_cast<const char*>(A + (size_t)k0 * n + m0);
+    const char* Bb = reinterpret_cast<const char*>(B + (size_t)k0 * n + n0);
+#pragma unroll
+    for (int p = 0; p < AP; ++p) {
+      ra[p] = *reinterpret_cast<const d2*>(Ab + aoff[p]);
+      if constexpr (SCALED)
+        rs[p] = *reinterpret_cast<const double*>(reinterpret_cast<const char*>(it.scale + k0) + soff[p]);
+    }
+#pragma unroll
+    for (int p = 0; p < BP; ++p) rb[p] = *reinterpret_cast<const d2*>(Bb + boff[p]);
+  };
+  auto lstore = [&](const int buf) __attribute__((always_inline)) {
 #pragma unroll
     for (int p = 0; p < AP; ++p) {
       const int idx = tid + p * Cfg::THREADS;
-      const int row = idx / APR, col = (idx % APR) * 2;
-      xa[p] = *reinterpret_cast<const d2*>(A + (size_t)(k0 + row) * n + m0 + col);
-      if constexpr (EPI == EPI_FERMI || EPI == EPI_FERMI_XY) xa[p] *= it.scale[k0 + row];
+      d2 v = ra[p];
+      if constexpr (SCALED) v *= rs[p];
+      *reinterpret_cast<d2*>(&As[buf][idx / APR][(idx % APR) * 2]) = v;
     }
 #pragma unroll
     for (int p = 0; p < BP; ++p) {
       const int idx = tid + p * Cfg::THREADS;
-      const int row = idx / BPR, col = (idx % BPR) * 2;
-      xb[p] = *reinterpret_cast<const d2*>(B + (size_t)(k0 + row) * n + n0 + col);
+      *reinterpret_cast<d2*>(&Bs[buf][idx / BPR][(idx % BPR) * 2]) = rb[p];
     }
   };
-  auto lstore = [&](const int buf, const d2 (&xa)[AP], const d2 (&xb)[BP]) __attribute__((always_inline)) {
-#pragma unroll
-    for (int p = 0; p < AP; ++p) {
-      const int idx = tid + p * Cfg::THREADS;
-      *reinterpret_cast<d2*>(&As[buf][idx / APR][(idx % APR) * 2]) = xa[p];
-    }
-#pragma unroll
-    for (int p = 0; p < BP; ++p) {
-      const int idx = tid + p * Cfg::THREADS;
-      *reinterpret_cast<d2*>(&Bs[buf][idx / BPR][(idx % BPR) * 2]) = xb[p];
-    }
-  };
-  // step kt: products of stage kt (LDS buffer kt % 2); x = register set of stage kt,
-  // refilled with stage kt + 2; y = register set of stage kt + 1, written to LDS
-  auto step = [&](const int kt, d2 (&xa)[AP], d2 (&xb)[BP], const d2 (&ya)[AP], const d2 (&yb)[BP])
-                  __attribute__((always_inline)) {
+
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
     const int buf = kt & 1;
-    if (kt + 2 < nk) gload(kt + 2, xa, xb);
+    gload(min(kt + 1, nk - 1));
 #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
       double a[WTM], b[WTN];
@@ -197,20 +218,9 @@ __device__ __forceinline__ void f64_tile(const GemmItem& it, const int n, const 
         for (int j = 0; j < WTN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
-    if (kt + 1 < nk) lstore(buf ^ 1, ya, yb);
+    lstore(buf ^ 1);
     __syncthreads();
-  };
-
-  gload(0, ra[0], rb[0]);
-  if (nk > 1) gload(1, ra[1], rb[1]);
-  lstore(0, ra[0], rb[0]);
-  __syncthreads();
-  int kt = 0;
-  for (; kt + 1 < nk; kt += 2) {
-    step(kt, ra[0], rb[0], ra[1], rb[1]);
-    step(kt + 1, ra[1], rb[1], ra[0], rb[0]);
   }
-  if (kt < nk) step(kt, ra[0], rb[0], ra[1], rb[1]);
 
   // Accumulator element (i, j, r) of this lane sits at
   //   m = m0 + wm*(BM/WAVES_M) + i*16 + lr + 4r,  n = n0 + wn*(BN/WAVES_N) + j*16 + lc.

@@ -75,11 +75,11 @@ kk_status kk_destroy(kk_handle h);
 
 /*
  * kk_prepare -- expansion-point setup, once per MD step (Sec. II.C).
- *   n_atoms        N >= 1
+ *   n_atoms        1 <= N <= 4096
  *   atom_offsets   HOST array of N+1 ints: orbitals of atom I are
  *                  [atom_offsets[I], atom_offsets[I+1]); offsets[0] = 0,
  *                  strictly increasing, offsets[N] = n_basis.
- *   n_basis        Nb >= 1
+ *   n_basis        1 <= Nb <= 65536 (KK_EINVAL outside these ranges)
  *   S              Nb x Nb overlap matrix (symmetric positive definite)
  *   Z              Nb x Nb congruence factor with Z^T S Z = I
  *   Q_up, Q_dn     Nb x Nb orthonormal eigenvectors (columns) of Z^T H^sigma Z

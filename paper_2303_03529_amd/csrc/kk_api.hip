@@ -319,9 +319,8 @@ kk_status response_chunk(kk_handle h, int batch, const double* v, double* q1, co
   if ((st = launch_gemm(h, kk::EPI_FERMI, fa))) return st;
   if ((st = launch_gemm(h, kk::EPI_MULLIKEN, ba))) return st;
   {
-    const int threads = 256;
-    dim3 grid((N + threads - 1) / threads, batch);
-    kk::combine<<<grid, threads, 0, h->stream>>>(h->xdiag, h->part, h->nparts, h->w[0], h->w[1],
+    dim3 grid((N + kk::COMBINE_ATOMS - 1) / kk::COMBINE_ATOMS, batch);
+    kk::combine<<<grid, kk::COMBINE_THREADS, 0, h->stream>>>(h->xdiag, h->part, h->nparts, h->w[0], h->w[1],
                                                   h->wsum, h->t, h->nb, np, h->offsets, N, q1, stop);
     LAUNCH_CHECK("combine");
   }
@@ -363,7 +362,7 @@ kk_status response_chunk_mixed(kk_handle h, int batch, const double* v, double* 
   LAUNCH_CHECK("mixed_scales");
   for (int z = 0; z < 2 * batch; ++z) {
     const int s = z & 1;
-    const int blocks = (int)std::min<size_t>((np2 + 255) / 256, 16384);
+    const int blocks = (int)std::min<size_t>((np2 / 8 + 255) / 256, 16384);
     kk::split_scaled_columns<<<blocks, 256, 0, h->stream>>>(h->CT[s], np, h->u + (size_t)z * np,
                                                              h->msc + z * 8 + 3, h->uct_h + z * np2,
                                                              h->uct_l + z * np2, stop);
@@ -398,9 +397,8 @@ kk_status response_chunk_mixed(kk_handle h, int batch, const double* v, double* 
   if ((st = launch_mixed(h, kk::EPI_FERMI, fa))) return st;
   if ((st = launch_mixed(h, kk::EPI_MULLIKEN, ba))) return st;
   {
-    const int threads = 256;
-    dim3 grid((N + threads - 1) / threads, batch);
-    kk::combine<<<grid, threads, 0, h->stream>>>(h->xdiag, h->part, h->nparts, h->w[0], h->w[1],
+    dim3 grid((N + kk::COMBINE_ATOMS - 1) / kk::COMBINE_ATOMS, batch);
+    kk::combine<<<grid, kk::COMBINE_THREADS, 0, h->stream>>>(h->xdiag, h->part, h->nparts, h->w[0], h->w[1],
                                                   h->wsum, h->t, h->nb, np, h->offsets, N, q1, stop);
     LAUNCH_CHECK("combine");
   }
@@ -540,6 +538,7 @@ kk_status kk_prepare(kk_handle h, int n_atoms, const int* atom_offsets, int n_ba
   if (!h) return fail(KK_EINVAL, "kk_prepare: handle is NULL");
   if (n_atoms < 1 || n_basis < 1) return fail(KK_EINVAL, "kk_prepare: n_atoms and n_basis must be >= 1");
   if (2 * n_atoms > 8 * 1024) return fail(KK_EINVAL, "kk_prepare: at most 4096 atoms are supported");
+  if (n_basis > 65536) return fail(KK_EINVAL, "kk_prepare: at most 65536 basis functions are supported");
   if (!atom_offsets || !S || !Z || !Q_up || !Q_dn || !eps_up || !eps_dn || !gamma)
     return fail(KK_EINVAL, "kk_prepare: NULL array argument");
   if (!(kT > 0.0)) return fail(KK_EINVAL, "kk_prepare: kT must be > 0");
@@ -1006,8 +1005,9 @@ kk_status krylov_kernel_adjoint(kk_handle h, const double* delta, int m, const d
     }
     if ((st = launch_gemm(h, kk::EPI_MULLIKEN, ba))) return st;
     {
-      dim3 grid((N + 255) / 256, 1);
-      kk::combine<<<grid, 256, 0, h->stream>>>(h->axdiag, h->apart, adj_nparts(h), h->w[0], h->w[1], h->wsum, h->t,
+      dim3 grid((N + kk::COMBINE_ATOMS - 1) / kk::COMBINE_ATOMS, 1);
+      kk::combine<<<grid, kk::COMBINE_THREADS, 0, h->stream>>>(h->axdiag, h->apart, adj_nparts(h), h->w[0], h->w[1],
+                                                              h->wsum, h->t,
                                                 nb, np, h->offsets, N, h->ag, nullptr);
       LAUNCH_CHECK("combine");
     }
@@ -1303,7 +1303,8 @@ kk_status enqueue_update(kk_batch b, int m) {
       if ((st = launch_persistent<kk::EPI_MULLIKEN, BSmallF64>(b, bi, b->cls[1].back, b->cls[1].nback, 0)))
         return st;
     }
-    kk::b_combine<<<dim3((b->maxN + 255) / 256, ns), 256, 0, b->stream>>>(b->d_sys);
+    kk::b_combine<<<dim3((b->maxN + kk::COMBINE_ATOMS - 1) / kk::COMBINE_ATOMS, ns), kk::COMBINE_THREADS, 0,
+                    b->stream>>>(b->d_sys);
     LAUNCH_CHECK("b_combine");
     kk::b_precond<<<dim3(bx_vec, ns), 256, 0, b->stream>>>(b->d_sys, k);
     LAUNCH_CHECK("b_precond");

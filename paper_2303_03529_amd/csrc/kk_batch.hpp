@@ -104,7 +104,7 @@ __global__ void b_split(const SysDesc* __restrict__ d) {
 
 __global__ void b_combine(const SysDesc* __restrict__ d) {
   const SysDesc& s = d[blockIdx.y];
-  if ((int)(blockIdx.x * blockDim.x) >= s.natoms) return;
+  if ((int)(blockIdx.x * (blockDim.x / WAVE)) >= s.natoms) return;
   combine_dev(s.xdiag, s.part, s.nparts, s.part_stride, s.w0, s.w1, s.wsum, s.t, s.nb, s.np, s.offsets, s.natoms, s.q1,
               &s.kst->stop, blockIdx.x, 0);
 }

@@ -606,10 +606,28 @@ __device__ __forceinline__ void split_scaled_columns_dev(const double* __restric
                                                          int bx, int gdx) {
   if (stop != nullptr && *stop != 0) return;
   const double s = *sc_p;
-  const size_t total = (size_t)np * np;
-  for (size_t i = (size_t)bx * blockDim.x + threadIdx.x; i < total; i += (size_t)gdx * blockDim.x) {
-    const int c = (int)(i % np);
-    split_store(s * u[c] * src[i], hi + i, lo + i);
+  // 8 consecutive columns of one row per thread and step (np is a multiple of 128 and
+  // at most 65536, so the group count fits 32 bits): 16-byte loads and stores only.
+  const unsigned per_row = (unsigned)np / 8u, total = per_row * (unsigned)np;
+  for (unsigned g = (unsigned)bx * blockDim.x + threadIdx.x; g < total; g += (unsigned)gdx * blockDim.x) {
+    const unsigned r = g / per_row, c0 = (g - r * per_row) * 8u;
+    const size_t base = (size_t)r * np + c0;
+    const d2* sv = reinterpret_cast<const d2*>(src + base);
+    const d2* uv = reinterpret_cast<const d2*>(u + c0);
+    h8 vh, vl;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const d2 v = sv[q], w = uv[q];
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const double x = s * w[e] * v[e];
+        const _Float16 h = (_Float16)(float)x;
+        vh[2 * q + e] = h;
+        vl[2 * q + e] = (_Float16)(float)(x - (double)h);
+      }
+    }
+    *reinterpret_cast<h8*>(hi + base) = vh;
+    *reinterpret_cast<h8*>(lo + base) = vl;
   }
 }
 

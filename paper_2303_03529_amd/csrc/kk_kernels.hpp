@@ -236,7 +236,9 @@ __global__ void potentials(const double* __restrict__ gamma, int natoms, double 
 //   xdiag[(b*2+s)*np + i], part[(b*2+s)][p][np], t[s*natoms + I] = sum_{i in I}
 //   sum_k C_ik w_k G_ik (the response to a unit chemical-potential shift),
 //   wsum = sum_s sum_i w_i.
-// Grid: (ceil(natoms / blockDim), batch).
+// One wave per atom: its lanes split the partial rows, each adds the atom's
+// orbitals of its rows, and the wave reduces. Grid: (ceil(natoms / waves per
+// block), batch); every block also reduces dmu over all orbitals (cached reads).
 __device__ __forceinline__ void combine_dev(const double* __restrict__ xdiag, const double* __restrict__ part,
                                             int nparts, int part_stride, const double* __restrict__ w_up,
                                             const double* __restrict__ w_dn, const double* __restrict__ wsum_p,
@@ -253,19 +255,27 @@ __device__ __forceinline__ void combine_dev(const double* __restrict__ xdiag, co
   s = block_sum(s, sh);
   const double wsum = *wsum_p;
   const double dmu = wsum > 0.0 ? s / wsum : 0.0;
-  const int a = bx * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int a = bx * (blockDim.x / WAVE) + (int)(threadIdx.x / WAVE);
   if (a >= natoms) return;
+  const int i0 = offsets[a], i1 = offsets[a + 1];
   double dn[2];
   for (int sp = 0; sp < 2; ++sp) {
     const double* pp = part + ((size_t)b * 2 + sp) * part_stride * np;
     double acc = 0.0;
-    for (int i = offsets[a]; i < offsets[a + 1]; ++i)
-      for (int p = 0; p < nparts; ++p) acc += pp[(size_t)p * np + i];
-    dn[sp] = acc + dmu * t[sp * natoms + a];
+    for (int p = lane; p < nparts; p += WAVE)
+      for (int i = i0; i < i1; ++i) acc += pp[(size_t)p * np + i];
+    dn[sp] = wave_sum(acc) + dmu * t[sp * natoms + a];
   }
-  q1[(size_t)b * 2 * natoms + a] = dn[0] + dn[1];
-  q1[(size_t)b * 2 * natoms + natoms + a] = dn[0] - dn[1];
+  if (lane == 0) {
+    q1[(size_t)b * 2 * natoms + a] = dn[0] + dn[1];
+    q1[(size_t)b * 2 * natoms + natoms + a] = dn[0] - dn[1];
+  }
 }
+
+// Blocks of the combine kernels: COMBINE_THREADS threads, one wave per atom.
+constexpr int COMBINE_THREADS = 256;
+constexpr int COMBINE_ATOMS = COMBINE_THREADS / WAVE;
 
 __global__ void combine(const double* __restrict__ xdiag, const double* __restrict__ part, int nparts,
                         const double* __restrict__ w_up, const double* __restrict__ w_dn,

@@ -1,6 +1,6 @@
 """Edge cases of the HIP path against the oracle: the smallest system (one
 atom), atoms with different orbital counts, the largest rank, a batch of one,
-and the reverse pass after a breakdown."""
+the reverse pass after a breakdown, and sizes beyond the supported range."""
 
 import numpy as np
 import pytest
@@ -125,5 +125,30 @@ def test_adjoint_after_breakdown():
         assert g["info"].rank_used == 2
         ref = gradients(sysd, 2, delta=delta)
         assert rel(g["delta"].cpu().numpy(), ref["delta"]) < 1e-8
+    finally:
+        h.close()
+
+
+def test_prepare_rejects_out_of_range_sizes():
+    """kk_prepare checks the sizes before touching any array: more than 65536 basis
+    functions or 4096 atoms is KK_EINVAL with a message, and the same handle then
+    prepares a valid system and matches the oracle."""
+    import ctypes
+    dummy = torch.zeros(1, dtype=torch.float64, device="cuda")
+    p = ctypes.c_void_p(dummy.data_ptr())
+    h = krylov.Handle()
+    try:
+        for n_atoms, nb in ((1, 70000), (4097, 4097 * 9)):
+            off = np.linspace(0, nb, n_atoms + 1).astype(np.int32)
+            rc = krylov.LIB.kk_prepare(h._h, n_atoms, off.ctypes.data_as(ctypes.c_void_p), nb, p, p, p, p, p, p, p,
+                                       -0.4, 0.25, 8.0, krylov.KK_FP64)
+            assert rc == krylov.KK_EINVAL
+            assert ("65536" if nb == 70000 else "4096") in krylov.last_error()
+        sysd = make_system(2, seed=16)
+        ep = expansion_point(sysd)
+        h.prepare(sysd["offsets"], t(sysd["S"]), t(ep["Z"]), t(ep["Q"][0]), t(ep["Q"][1]), t(ep["eps"][0]),
+                  t(ep["eps"][1]), t(sysd["gamma"]), sysd["W"], sysd["kT"], sysd["n_electrons"], krylov.KK_FP64)
+        x, _ = h.krylov_kernel_apply(t(sysd["delta"]), 4)
+        assert rel(x.cpu().numpy(), kernel_apply(sysd, ep, sysd["delta"], 4)) < 1e-10
     finally:
         h.close()

@@ -61,6 +61,10 @@ struct MixedCfg {
   static constexpr bool DL = false;
   static constexpr int KP = BK + 8;                 // padded LDS row (halves)
   static_assert((KP / 8) % 2 == 1, "LDS row stride must be an odd number of 16-byte slots");
+  static constexpr int YP = BN + 8;                 // padded row of a Y staging tile (halves)
+  static constexpr int MAIN_BYTES = 2 * 2 * (BM + BN) * KP * 2;
+  static constexpr int EPI_BYTES = 2 * BM * YP * 2;  // the staged mirror tile, hi and lo
+  static constexpr int SMEM_BYTES = MAIN_BYTES > EPI_BYTES ? MAIN_BYTES : EPI_BYTES;
   static_assert(64 % (BK / 8) == 0 && 16 % (BK / 8) == 0, "piece mapping");
   static_assert(BM % (32 * WAVES_M) == 0 && BN % (32 * WAVES_N) == 0, "wave tiling");
   static_assert(BK % 16 == 0, "BK");
@@ -80,11 +84,22 @@ struct MixedDlCfg {
   static constexpr int STAGE_BLK = 2 * (A_BLK + B_BLK);        // hi and lo of A and B
   static constexpr int PER_WAVE = STAGE_BLK / WAVES;
   static constexpr int STAGE_BYTES = STAGE_BLK * 1024;
+  static constexpr int YP = BN + 8;
+  static constexpr int EPI_BYTES = 2 * BM * YP * 2;
+  static constexpr int SMEM_BYTES = NS * STAGE_BYTES > EPI_BYTES ? NS * STAGE_BYTES : EPI_BYTES;
   static_assert(STAGE_BLK % WAVES == 0, "DMA blocks per wave");
   static_assert(BM % (32 * WAVES_M) == 0 && BN % (32 * WAVES_N) == 0, "wave tiling");
   static_assert(NS >= 3 && NS <= 5, "ring depth");
   static_assert(NS * STAGE_BYTES <= 160 * 1024, "LDS");
 };
+
+// LDS of one split-precision tile, shared by its main loop and its epilogue (one
+// static buffer per configuration): the K-stage buffers, then the Y staging tiles.
+template <class Cfg>
+__device__ __forceinline__ unsigned char* mixed_smem() {
+  __shared__ __attribute__((aligned(1024))) unsigned char smem[Cfg::SMEM_BYTES];
+  return smem;
+}
 
 __device__ __forceinline__ void split_store(double v, _Float16* hi, _Float16* lo) {
   const _Float16 h = (_Float16)(float)v;
@@ -103,8 +118,8 @@ __device__ __forceinline__ void mixed_mainloop_lds(const MixedItem& it, const in
   constexpr int CPR = BK / 8;  // 16-byte chunks per row per matrix
 
   // [buf][hi/lo][row][k]
-  __shared__ __attribute__((aligned(16))) _Float16 As[2][2][BM][KP];
-  __shared__ __attribute__((aligned(16))) _Float16 Bs[2][2][BN][KP];
+  auto As = reinterpret_cast<_Float16 (*)[2][BM][KP]>(mixed_smem<Cfg>());
+  auto Bs = reinterpret_cast<_Float16 (*)[2][BN][KP]>(mixed_smem<Cfg>() + 2 * 2 * BM * KP * 2);
 
   const int tid = threadIdx.x;
   const int nk = (two_halves ? 2 * k_half : k_half) / BK;
@@ -270,7 +285,18 @@ __device__ __forceinline__ void mixed_epilogue(const MixedItem& it, const int n,
   const int mw = m0 + wm * (BM / Cfg::WAVES_M) + 4 * lh;
   const int nw = n0 + wn * (BN / Cfg::WAVES_N) + l32;
   if constexpr (EPI == EPI_FERMI) {
+    // Y is written twice: the tile itself straight from the accumulator layout (32
+    // consecutive columns per row and instruction, full cache lines per wave), and its
+    // mirror through LDS (hi and lo tiles, transposed there) with 16-byte row stores.
+    // Written straight from the accumulators the mirror's 2-byte stores land in 32 rows
+    // per instruction: 4 % of the forward, and 9 % of the back-transform, which then
+    // reads the partly written lines. A diagonal tile stages its full symmetric block.
+    static_assert(BM == BN, "the staged mirror needs square tiles");
+    constexpr int YP = Cfg::YP, CH = BN / 8;
     const double beta = beta_arg, sy = it.sc[1];
+    const bool diag = tile.x == tile.y;
+    _Float16* const Th = reinterpret_cast<_Float16*>(mixed_smem<Cfg>());  // [BN][YP]: mirror, hi
+    _Float16* const Tl = Th + BN * YP;                                    // [BN][YP]: mirror, lo
     double en[WTN], fn[WTN], fcn[WTN];
 #pragma unroll
     for (int j = 0; j < WTN; ++j) {
@@ -281,23 +307,40 @@ __device__ __forceinline__ void mixed_epilogue(const MixedItem& it, const int n,
     for (int i = 0; i < WTM; ++i)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int m = mw + i * 32 + 8 * (r / 4) + (r % 4);
+        const int ml = mw - m0 + i * 32 + 8 * (r / 4) + (r % 4), m = m0 + ml;
         const double em = it.eps[m], fm = it.f[m], fcm = it.fc[m];
 #pragma unroll
         for (int j = 0; j < WTN; ++j) {
-          const int c = nw + j * 32;
-          if (m > c) continue;
+          const int cl = nw - n0 + j * 32, c = n0 + cl;
+          if (m > c) continue;  // below the diagonal: the mirror of another lane's element
           const double x = 0.5 * inv * (double)acc[i][j][r];
+          double y;
           if (m == c) {
             it.xdiag[m] = x;
-            split_store(-it.w[m] * x * sy, it.yh + (size_t)m * n + m, it.yl + (size_t)m * n + m);
+            y = -it.w[m] * x * sy;
           } else {
-            const double y = fermi_divided_difference(em, fm, fcm, en[j], fn[j], fcn[j], beta) * x * sy;
-            split_store(y, it.yh + (size_t)m * n + c, it.yl + (size_t)m * n + c);
-            split_store(y, it.yh + (size_t)c * n + m, it.yl + (size_t)c * n + m);
+            y = fermi_divided_difference(em, fm, fcm, en[j], fn[j], fcn[j], beta) * x * sy;
+          }
+          const _Float16 h = (_Float16)(float)y, l = (_Float16)(float)(y - (double)h);
+          it.yh[(size_t)m * n + c] = h;
+          it.yl[(size_t)m * n + c] = l;
+          Th[cl * YP + ml] = h;
+          Tl[cl * YP + ml] = l;
+          if (diag) {
+            Th[ml * YP + cl] = h;
+            Tl[ml * YP + cl] = l;
           }
         }
       }
+    __syncthreads();
+    // staged rows: row cl of the mirror is Y row n0 + cl from column m0 on
+    for (int q = threadIdx.x; q < BN * CH; q += Cfg::THREADS) {
+      const int row = q / CH, ch = q % CH;
+      const size_t o = (size_t)(n0 + row) * n + m0 + ch * 8;
+      *reinterpret_cast<h8*>(it.yh + o) = *reinterpret_cast<const h8*>(Th + row * YP + ch * 8);
+      *reinterpret_cast<h8*>(it.yl + o) = *reinterpret_cast<const h8*>(Tl + row * YP + ch * 8);
+    }
+    __syncthreads();
   } else {  // EPI_MULLIKEN
     const int p = tile.y * Cfg::WAVES_N + wn;
 #pragma unroll
@@ -353,7 +396,7 @@ __device__ __forceinline__ void mixed_mainloop_dl(const MixedItem& it, const int
   constexpr int WTM = Cfg::WTM, WTN = Cfg::WTN;
   constexpr int A_BLK = Cfg::A_BLK, B_BLK = Cfg::B_BLK, SB = Cfg::STAGE_BYTES;
   static_assert(NS >= 3, "the pipelined loop refills a slot one stage after reading it");
-  __shared__ __attribute__((aligned(1024))) unsigned char ring[NS * SB];
+  unsigned char* const ring = mixed_smem<Cfg>();
 
   const int tid = threadIdx.x;
   const int nk = (two_halves ? 2 * k_half : k_half) / BK;

@@ -142,23 +142,25 @@ __device__ __forceinline__ void f64_tile(const GemmItem& it, const int n, const 
     for (int j = 0; j < WTN; ++j) acc[i][j] = (d4){0.0, 0.0, 0.0, 0.0};
 
   // Global -> register -> LDS staging, one stage ahead: the loads of stage kt + 1 are
-  // issued at the start of step kt and written to LDS at its end. The forward
-  // transform's row scale is applied at that write, not at the load, so that no
-  // instruction in the step waits for the loads; and the loads are unconditional (the
-  // last step reloads the last stage, written to the idle buffer and never read), so
-  // that the wait before the write is the only one.
+  // issued at the start of step kt and written to LDS at its end, and nothing in
+  // between waits for them; the loads are unconditional (the last step reloads the last
+  // stage, written to the idle buffer and never read), because a conditional load makes
+  // the compiler wait for every load in flight before the write.
+  // The forward transform's row scales go through a 3-slot LDS ring: the BK scales of
+  // stage s are loaded by the first BK threads at the start of step s - 2, put in slot
+  // s % 3 at its end, and multiplied in when stage s is written to LDS (end of step s - 1).
   constexpr bool SCALED = EPI == EPI_FERMI || EPI == EPI_FERMI_XY;
+  __shared__ double Ss[SCALED ? 3 : 1][BK];
   d2 ra[AP], rb[BP];
-  double rs[AP];
+  double sreg = 0.0;
   // Byte offsets of this thread's staging pieces within a K stage (loop invariant, a
   // few hundred KB at most); the stage's uniform part goes into the base pointers.
-  unsigned aoff[AP], soff[AP], boff[BP];
+  unsigned aoff[AP], boff[BP];
 #pragma unroll
   for (int p = 0; p < AP; ++p) {
     const int idx = tid + p * Cfg::THREADS;
     const int row = idx / APR, col = (idx % APR) * 2;
     aoff[p] = (unsigned)(row * n + col) * 8u;
-    soff[p] = (unsigned)row * 8u;
   }
 #pragma unroll
   for (int p = 0; p < BP; ++p) {
@@ -176,20 +178,28 @@ __device__ __forceinline__ void f64_tile(const GemmItem& it, const int n, const 
     const char* Ab = reinterpret_cast<const char*>(A + (size_t)k0 * n + m0);
     const char* Bb = reinterpret_cast<const char*>(B + (size_t)k0 * n + n0);
 #pragma unroll
-    for (int p = 0; p < AP; ++p) {
-      ra[p] = *reinterpret_cast<const d2*>(Ab + aoff[p]);
-      if constexpr (SCALED)
-        rs[p] = *reinterpret_cast<const double*>(reinterpret_cast<const char*>(it.scale + k0) + soff[p]);
-    }
+    for (int p = 0; p < AP; ++p) ra[p] = *reinterpret_cast<const d2*>(Ab + aoff[p]);
 #pragma unroll
     for (int p = 0; p < BP; ++p) rb[p] = *reinterpret_cast<const d2*>(Bb + boff[p]);
   };
-  auto lstore = [&](const int buf) __attribute__((always_inline)) {
+  auto sload = [&](const int kt) __attribute__((always_inline)) {
+    if constexpr (SCALED) {
+      int k0 = kt * BK;
+      if (two_halves && k0 >= k_half) k0 -= k_half;
+      if (tid < BK) sreg = it.scale[k0 + tid];
+    }
+  };
+  auto sstore = [&](const int kt) __attribute__((always_inline)) {
+    if constexpr (SCALED) {
+      if (tid < BK) Ss[kt % 3][tid] = sreg;
+    }
+  };
+  auto lstore = [&](const int buf, const int kt) __attribute__((always_inline)) {
 #pragma unroll
     for (int p = 0; p < AP; ++p) {
       const int idx = tid + p * Cfg::THREADS;
       d2 v = ra[p];
-      if constexpr (SCALED) v *= rs[p];
+      if constexpr (SCALED) v *= Ss[kt % 3][idx / APR];
       *reinterpret_cast<d2*>(&As[buf][idx / APR][(idx % APR) * 2]) = v;
     }
 #pragma unroll
@@ -200,11 +210,17 @@ __device__ __forceinline__ void f64_tile(const GemmItem& it, const int n, const 
   };
 
   gload(0);
-  lstore(0);
+  sload(0);
+  sstore(0);
+  sload(min(1, nk - 1));
+  sstore(1);
+  __syncthreads();
+  lstore(0, 0);
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
     const int buf = kt & 1;
     gload(min(kt + 1, nk - 1));
+    sload(min(kt + 2, nk - 1));
 #pragma unroll
     for (int kk = 0; kk < BK / 4; ++kk) {
       double a[WTM], b[WTN];
@@ -218,7 +234,8 @@ __device__ __forceinline__ void f64_tile(const GemmItem& it, const int n, const 
         for (int j = 0; j < WTN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
-    lstore(buf ^ 1);
+    lstore(buf ^ 1, kt + 1);
+    sstore(kt + 2);
     __syncthreads();
   }
 

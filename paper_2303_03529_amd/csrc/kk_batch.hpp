@@ -148,10 +148,13 @@ __global__ __launch_bounds__(Cfg::THREADS) __attribute__((amdgpu_waves_per_eu(Cf
   }
 }
 
+// Held to MIN_BLOCKS workgroups per CU as well (it then spills a few values outside the K
+// loop): with the staged mirror write of the forward epilogue, left to itself the compiler
+// gives the forward form ~190 registers, one workgroup per CU, and the batch runs 4 % slower.
 template <int EPI, class Cfg>
-__global__ __launch_bounds__(Cfg::THREADS, Cfg::MIN_BLOCKS) void b_gemm_mixed(const BatchItemMixed* __restrict__ items,
-                                                                            const int4* __restrict__ tiles,
-                                                                            int ntiles, int two_halves) {
+__global__ __launch_bounds__(Cfg::THREADS) __attribute__((amdgpu_waves_per_eu((Cfg::MIN_BLOCKS * Cfg::THREADS / 64 + 3) / 4)))
+void b_gemm_mixed(const BatchItemMixed* __restrict__ items, const int4* __restrict__ tiles, int ntiles,
+                  int two_halves) {
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int4 tl = tiles[t];
     const BatchItemMixed& it = items[tl.x];

@@ -56,6 +56,12 @@ kk_status fail(kk_status st, const char* fmt, ...) {
     if (e_ != hipSuccess) return fail(KK_EHIP, "launch %s: %s", what, hipGetErrorString(e_)); \
   } while (0)
 
+// A split-precision handle also runs FP64 GEMMs on its padded size (the
+// setup products and the FP64 reverse sweep), so its padding is a multiple of
+// the tile sides of both kernel families.
+constexpr int SPLIT_PAD = kk::MIXED_PAD > kk::PAD ? kk::MIXED_PAD : kk::PAD;
+static_assert(SPLIT_PAD % kk::MIXED_PAD == 0 && SPLIT_PAD % kk::PAD == 0,
+              "split-precision padding must be a multiple of every tile side");
 constexpr int MAX_CHUNK = kk::MAX_GEMM_BATCH / 2;  // directions per GEMM launch
 constexpr size_t WORKSPACE_BUDGET = size_t(12) << 30;  // bytes of Y workspace per handle
 constexpr int MAX_EVENTS = 8192;
@@ -553,7 +559,7 @@ kk_status kk_prepare(kk_handle h, int n_atoms, const int* atom_offsets, int n_ba
       return fail(KK_EINVAL, "kk_prepare: atom_offsets must be strictly increasing (atom %d)", a);
 
   const bool mixed = precision == KK_MIXED_F16;
-  const int pad = mixed ? kk::MIXED_PAD : kk::PAD;
+  const int pad = mixed ? SPLIT_PAD : kk::PAD;
   const int nb = n_basis, np = (nb + pad - 1) / pad * pad;
   // Re-preparing the same shape (an SCF or MD loop) reuses every buffer.
   const bool reuse = h->prepared && h->natoms == n_atoms && h->nb == nb && h->precision == precision;

@@ -62,6 +62,19 @@ kk_status fail(kk_status st, const char* fmt, ...) {
 constexpr int SPLIT_PAD = kk::MIXED_PAD > kk::PAD ? kk::MIXED_PAD : kk::PAD;
 static_assert(SPLIT_PAD % kk::MIXED_PAD == 0 && SPLIT_PAD % kk::PAD == 0,
               "split-precision padding must be a multiple of every tile side");
+// Small systems fill the chip better with 64 x 64 tiles (a 128-atom system has
+// 45 upper 128 x 128 forward tiles per spin for 256 CUs). Up to these padded
+// sizes the FP64 response transforms (both) and the split forward transform use
+// them; the reverse pass and the setup products keep the large tiles. On MI355X:
+// FP64 forward 0.22 vs 0.34 ms and back 0.144 vs 0.169 ms at Nb = 1152, forward
+// 1.08 vs 1.20 ms and back equal at Nb = 2250, 64 x 64 slower from Nb = 3888;
+// split forward 0.080 vs 0.098 ms at Nb = 1152 and slower at 2250 (its back
+// transform is not faster with them at any size).
+constexpr int SMALL_NP_F64 = 2304;
+constexpr int SMALL_NP_SPLIT = 1152;
+using SmallF64 = kk::Cfg64x64;
+using SmallMx = kk::MCfg64x64f8;
+static_assert(kk::PAD % SmallF64::BM == 0 && SPLIT_PAD % SmallMx::BM == 0, "small tiles must divide the padding");
 constexpr int MAX_CHUNK = kk::MAX_GEMM_BATCH / 2;  // directions per GEMM launch
 constexpr size_t WORKSPACE_BUDGET = size_t(12) << 30;  // bytes of Y workspace per handle
 constexpr int MAX_EVENTS = 8192;
@@ -83,6 +96,11 @@ struct kk_handle_s {
   int* offsets = nullptr;
   int2 *tiles_upper = nullptr, *tiles_full = nullptr, *tiles_store = nullptr;
   int n_upper = 0, n_full = 0, n_store = 0;
+  // small systems: 64 x 64 tiles for the response transforms (FP64 lists here;
+  // the split forward's list is mtiles_upper)
+  bool small_f64 = false, small_mfwd = false;
+  int2 *stiles_upper = nullptr, *stiles_full = nullptr;
+  int n_supper = 0, n_sfull = 0;
 
   // split-precision state (precision == KK_MIXED_F16)
   int precision = KK_FP64;
@@ -237,7 +255,7 @@ struct ProfileScope {
   }
 };
 
-kk_status launch_gemm(kk_handle h, int epi, kk::GemmArgs& a) {
+kk_status launch_gemm(kk_handle h, int epi, kk::GemmArgs& a, bool small = false) {
   const int grid = a.ntiles * a.nitems;
   if (grid <= 0) return KK_OK;
   if (a.nitems > kk::MAX_GEMM_BATCH) return fail(KK_EINVAL, "internal: too many GEMM items");
@@ -245,7 +263,10 @@ kk_status launch_gemm(kk_handle h, int epi, kk::GemmArgs& a) {
     kk::gemm_f64<kk::EPI_STORE, kk::StoreCfg><<<grid, kk::StoreCfg::THREADS, 0, h->stream>>>(a);
   } else if (epi == kk::EPI_FERMI) {
     ProfileScope ps(h, 0);
-    kk::gemm_f64<kk::EPI_FERMI, kk::FwdCfg><<<grid, kk::FwdCfg::THREADS, 0, h->stream>>>(a);
+    if (small)
+      kk::gemm_f64<kk::EPI_FERMI, SmallF64><<<grid, SmallF64::THREADS, 0, h->stream>>>(a);
+    else
+      kk::gemm_f64<kk::EPI_FERMI, kk::FwdCfg><<<grid, kk::FwdCfg::THREADS, 0, h->stream>>>(a);
   } else if (epi == kk::EPI_FERMI_XY) {
     ProfileScope ps(h, 2);
     kk::gemm_f64<kk::EPI_FERMI_XY, kk::FwdCfg><<<grid, kk::FwdCfg::THREADS, 0, h->stream>>>(a);
@@ -254,7 +275,10 @@ kk_status launch_gemm(kk_handle h, int epi, kk::GemmArgs& a) {
     kk::gemm_f64<kk::EPI_ACCUM, kk::BackCfg><<<grid, kk::BackCfg::THREADS, 0, h->stream>>>(a);
   } else {
     ProfileScope ps(h, 1);
-    kk::gemm_f64<kk::EPI_MULLIKEN, kk::BackCfg><<<grid, kk::BackCfg::THREADS, 0, h->stream>>>(a);
+    if (small)
+      kk::gemm_f64<kk::EPI_MULLIKEN, SmallF64><<<grid, SmallF64::THREADS, 0, h->stream>>>(a);
+    else
+      kk::gemm_f64<kk::EPI_MULLIKEN, kk::BackCfg><<<grid, kk::BackCfg::THREADS, 0, h->stream>>>(a);
   }
   LAUNCH_CHECK("gemm_f64");
   return KK_OK;
@@ -302,12 +326,13 @@ kk_status response_chunk(kk_handle h, int batch, const double* v, double* q1, co
                                                        h->u, stop);
     LAUNCH_CHECK("potentials");
   }
+  const bool small = h->small_f64;
   kk::GemmArgs fa{};
-  fa.n = np; fa.k_half = np; fa.two_halves = 1; fa.ntiles = h->n_upper; fa.nitems = 2 * batch;
-  fa.tiles = h->tiles_upper; fa.stop = stop; fa.beta = h->beta;
+  fa.n = np; fa.k_half = np; fa.two_halves = 1; fa.ntiles = small ? h->n_supper : h->n_upper;
+  fa.nitems = 2 * batch; fa.tiles = small ? h->stiles_upper : h->tiles_upper; fa.stop = stop; fa.beta = h->beta;
   kk::GemmArgs ba{};
-  ba.n = np; ba.k_half = np; ba.two_halves = 0; ba.ntiles = h->n_full; ba.nitems = 2 * batch;
-  ba.tiles = h->tiles_full; ba.stop = stop; ba.beta = h->beta;
+  ba.n = np; ba.k_half = np; ba.two_halves = 0; ba.ntiles = small ? h->n_sfull : h->n_full;
+  ba.nitems = 2 * batch; ba.tiles = small ? h->stiles_full : h->tiles_full; ba.stop = stop; ba.beta = h->beta;
   for (int b = 0; b < batch; ++b)
     for (int s = 0; s < 2; ++s) {
       const int z = 2 * b + s;
@@ -322,8 +347,8 @@ kk_status response_chunk(kk_handle h, int batch, const double* v, double* q1, co
       bi.part = h->part + (size_t)z * h->nparts * np;
     }
   kk_status st;
-  if ((st = launch_gemm(h, kk::EPI_FERMI, fa))) return st;
-  if ((st = launch_gemm(h, kk::EPI_MULLIKEN, ba))) return st;
+  if ((st = launch_gemm(h, kk::EPI_FERMI, fa, small))) return st;
+  if ((st = launch_gemm(h, kk::EPI_MULLIKEN, ba, small))) return st;
   {
     dim3 grid((N + kk::COMBINE_ATOMS - 1) / kk::COMBINE_ATOMS, batch);
     kk::combine<<<grid, kk::COMBINE_THREADS, 0, h->stream>>>(h->xdiag, h->part, h->nparts, h->w[0], h->w[1],
@@ -339,7 +364,10 @@ kk_status launch_mixed(kk_handle h, int epi, kk::MixedArgs& a) {
   if (a.nitems > kk::MAX_GEMM_BATCH) return fail(KK_EINVAL, "internal: too many GEMM items");
   if (epi == kk::EPI_FERMI) {
     ProfileScope ps(h, 0);
-    kk::gemm_mixed<kk::EPI_FERMI, kk::MFwdCfg><<<grid, kk::MFwdCfg::THREADS, 0, h->stream>>>(a);
+    if (h->small_mfwd)
+      kk::gemm_mixed<kk::EPI_FERMI, SmallMx><<<grid, SmallMx::THREADS, 0, h->stream>>>(a);
+    else
+      kk::gemm_mixed<kk::EPI_FERMI, kk::MFwdCfg><<<grid, kk::MFwdCfg::THREADS, 0, h->stream>>>(a);
   } else {
     ProfileScope ps(h, 1);
     kk::gemm_mixed<kk::EPI_MULLIKEN, kk::MBackCfg><<<grid, kk::MBackCfg::THREADS, 0, h->stream>>>(a);
@@ -447,6 +475,19 @@ kk_status allocate_prepared(kk_handle h) {
   std::vector<int2> up = tile_order(np, kk::FwdCfg::BM, kk::FwdCfg::BN, true);
   std::vector<int2> full = tile_order(np, kk::BackCfg::BM, kk::BackCfg::BN, false);
   std::vector<int2> stt = tile_order(np, kk::StoreCfg::BM, kk::StoreCfg::BN, false);
+  std::vector<int2> sup, sfull, mup, mfull;
+  if (h->small_f64) {
+    sup = tile_order(np, SmallF64::BM, SmallF64::BN, true);
+    sfull = tile_order(np, SmallF64::BM, SmallF64::BN, false);
+    h->n_supper = (int)sup.size();
+    h->n_sfull = (int)sfull.size();
+    if ((st = dalloc_t(h, &h->stiles_upper, sup.size()))) return st;
+    if ((st = dalloc_t(h, &h->stiles_full, sfull.size()))) return st;
+    HIP_OR_FAIL(hipMemcpyAsync(h->stiles_upper, sup.data(), sizeof(int2) * sup.size(), hipMemcpyHostToDevice,
+                               h->stream));
+    HIP_OR_FAIL(hipMemcpyAsync(h->stiles_full, sfull.data(), sizeof(int2) * sfull.size(), hipMemcpyHostToDevice,
+                               h->stream));
+  }
   h->n_upper = (int)up.size();
   h->n_full = (int)full.size();
   h->n_store = (int)stt.size();
@@ -473,8 +514,9 @@ kk_status allocate_prepared(kk_handle h) {
       for (_Float16** q : {&h->Ch[s], &h->Cl[s], &h->CTh[s], &h->CTl[s], &h->GTh[s], &h->GTl[s]})
         if ((st = dalloc_t(h, q, np2))) return st;
     }
-    std::vector<int2> mup = tile_order(np, kk::MFwdCfg::BM, kk::MFwdCfg::BN, true);
-    std::vector<int2> mfull = tile_order(np, kk::MBackCfg::BM, kk::MBackCfg::BN, false);
+    mup = h->small_mfwd ? tile_order(np, SmallMx::BM, SmallMx::BN, true)
+                        : tile_order(np, kk::MFwdCfg::BM, kk::MFwdCfg::BN, true);
+    mfull = tile_order(np, kk::MBackCfg::BM, kk::MBackCfg::BN, false);
     h->n_mupper = (int)mup.size();
     h->n_mfull = (int)mfull.size();
     if ((st = dalloc_t(h, &h->mtiles_upper, mup.size()))) return st;
@@ -570,8 +612,11 @@ kk_status kk_prepare(kk_handle h, int n_atoms, const int* atom_offsets, int n_ba
     h->release();
     h->precision = precision;
     h->natoms = n_atoms; h->nb = nb; h->np = np;
+    h->small_f64 = !mixed && np <= SMALL_NP_F64;
+    h->small_mfwd = mixed && np <= SMALL_NP_SPLIT;
     h->nparts = mixed ? (np / kk::MBackCfg::BN) * kk::MBackCfg::WAVES_N
-                      : (np / kk::BackCfg::BN) * kk::BackCfg::WAVES_N;
+                      : h->small_f64 ? (np / SmallF64::BN) * SmallF64::WAVES_N
+                                     : (np / kk::BackCfg::BN) * kk::BackCfg::WAVES_N;
     if ((st = allocate_prepared(h))) return st;
   }
   h->W = W; h->kT = kT; h->beta = 1.0 / kT; h->n_e = n_electrons;
@@ -1127,8 +1172,6 @@ namespace {
 
 // Tile configurations a batch chooses between: large systems use the default
 // transforms, systems with np <= small_np_max use 64 x 64 tiles.
-using BSmallF64 = kk::Cfg64x64;
-using BSmallMx = kk::MCfg64x64f8;
 
 struct TileClass {
   int4* fwd = nullptr;
@@ -1216,8 +1259,8 @@ kk_status build_tile_lists(kk_batch b, int small_np_max) {
     const int np = b->np_of[i];
     const int c = np <= small_np_max ? 1 : 0;
     int bm, bn, sbm, sbn;
-    if (mixed) { bm = kk::MFwdCfg::BM; bn = kk::MFwdCfg::BN; sbm = BSmallMx::BM; sbn = BSmallMx::BN; }
-    else { bm = kk::FwdCfg::BM; bn = kk::FwdCfg::BN; sbm = BSmallF64::BM; sbn = BSmallF64::BN; }
+    if (mixed) { bm = kk::MFwdCfg::BM; bn = kk::MFwdCfg::BN; sbm = SmallMx::BM; sbn = SmallMx::BN; }
+    else { bm = kk::FwdCfg::BM; bn = kk::FwdCfg::BN; sbm = SmallF64::BM; sbn = SmallF64::BN; }
     const int tbm = c ? sbm : bm, tbn = c ? sbn : bn;
     for (int s = 0; s < 2; ++s) {
       const int item = 2 * i + s;
@@ -1237,7 +1280,7 @@ kk_status build_tile_lists(kk_batch b, int small_np_max) {
       size_t capf = 0, capb = 0;
       for (int i = 0; i < b->ns; ++i) {
         const int np = b->np_of[i];
-        const int sb = mixed ? BSmallMx::BM : BSmallF64::BM;
+        const int sb = mixed ? SmallMx::BM : SmallF64::BM;
         capf += 2 * (size_t)(np / sb) * (np / sb + 1) / 2 + 2 * (np / sb);
         capb += 2 * (size_t)(np / sb) * (np / sb);
       }
@@ -1294,19 +1337,19 @@ kk_status enqueue_update(kk_batch b, int m) {
       auto* fi = static_cast<const kk::BatchItemMixed*>(b->d_items_fwd);
       auto* bi = static_cast<const kk::BatchItemMixed*>(b->d_items_back);
       if ((st = launch_persistent<kk::EPI_FERMI, kk::MFwdCfg>(b, fi, b->cls[0].fwd, b->cls[0].nfwd, 1))) return st;
-      if ((st = launch_persistent<kk::EPI_FERMI, BSmallMx>(b, fi, b->cls[1].fwd, b->cls[1].nfwd, 1))) return st;
+      if ((st = launch_persistent<kk::EPI_FERMI, SmallMx>(b, fi, b->cls[1].fwd, b->cls[1].nfwd, 1))) return st;
       if ((st = launch_persistent<kk::EPI_MULLIKEN, kk::MBackCfg>(b, bi, b->cls[0].back, b->cls[0].nback, 0)))
         return st;
-      if ((st = launch_persistent<kk::EPI_MULLIKEN, BSmallMx>(b, bi, b->cls[1].back, b->cls[1].nback, 0)))
+      if ((st = launch_persistent<kk::EPI_MULLIKEN, SmallMx>(b, bi, b->cls[1].back, b->cls[1].nback, 0)))
         return st;
     } else {
       auto* fi = static_cast<const kk::BatchItemF64*>(b->d_items_fwd);
       auto* bi = static_cast<const kk::BatchItemF64*>(b->d_items_back);
       if ((st = launch_persistent<kk::EPI_FERMI, kk::FwdCfg>(b, fi, b->cls[0].fwd, b->cls[0].nfwd, 1))) return st;
-      if ((st = launch_persistent<kk::EPI_FERMI, BSmallF64>(b, fi, b->cls[1].fwd, b->cls[1].nfwd, 1))) return st;
+      if ((st = launch_persistent<kk::EPI_FERMI, SmallF64>(b, fi, b->cls[1].fwd, b->cls[1].nfwd, 1))) return st;
       if ((st = launch_persistent<kk::EPI_MULLIKEN, kk::BackCfg>(b, bi, b->cls[0].back, b->cls[0].nback, 0)))
         return st;
-      if ((st = launch_persistent<kk::EPI_MULLIKEN, BSmallF64>(b, bi, b->cls[1].back, b->cls[1].nback, 0)))
+      if ((st = launch_persistent<kk::EPI_MULLIKEN, SmallF64>(b, bi, b->cls[1].back, b->cls[1].nback, 0)))
         return st;
     }
     kk::b_combine<<<dim3((b->maxN + kk::COMBINE_ATOMS - 1) / kk::COMBINE_ATOMS, ns), kk::COMBINE_THREADS, 0,
@@ -1448,8 +1491,8 @@ kk_status kk_batch_prepare(kk_batch b, int n_systems, const int* n_atoms, const 
     // Mulliken partial rows: one per wave column of a tile column, for either tile class
     b->parts_large[i] = mixed ? (h->np / kk::MBackCfg::BN) * kk::MBackCfg::WAVES_N
                               : (h->np / kk::BackCfg::BN) * kk::BackCfg::WAVES_N;
-    b->parts_small[i] = mixed ? (h->np / BSmallMx::BN) * BSmallMx::WAVES_N
-                              : (h->np / BSmallF64::BN) * BSmallF64::WAVES_N;
+    b->parts_small[i] = mixed ? (h->np / SmallMx::BN) * SmallMx::WAVES_N
+                              : (h->np / SmallF64::BN) * SmallF64::WAVES_N;
     const int part_rows = std::max(b->parts_large[i], b->parts_small[i]);
     double* part = nullptr;
     if ((st = balloc(b, &part, (size_t)2 * part_rows * np))) return st;

@@ -75,9 +75,11 @@ def test_mixed_kernel_fe128(fe128m):
     assert info.rank_used == 8 and err < TOL_MIXED
 
 
-def test_mixed_ragged_cluster():
-    sysd, ep, h = _case(n_atoms=37, seed=10_037)
-    v = np.random.default_rng(7).standard_normal(2 * 37)
+@pytest.mark.parametrize("n_atoms", [37, 129])
+def test_mixed_ragged_cluster(n_atoms):
+    """37 atoms: 64 x 64 forward tiles; 129 (padded 1280): the smallest size on 128 x 128."""
+    sysd, ep, h = _case(n_atoms=n_atoms, seed=10_000 + n_atoms)
+    v = np.random.default_rng(7).standard_normal(2 * n_atoms)
     got = h.density_response_batch(t(v)).cpu().numpy()[0]
     assert rel(got, response(sysd, ep, v)) < TOL_MIXED
 

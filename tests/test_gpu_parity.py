@@ -72,9 +72,11 @@ def test_response_is_deterministic(fe128):
     assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("n_atoms", [17, 37, 131])
+@pytest.mark.parametrize("n_atoms", [17, 37, 131, 250, 257])
 def test_response_ragged_clusters(n_atoms):
-    """Open clusters: Nb = 9N not a multiple of the tile (padding path)."""
+    """Open clusters: Nb = 9N not a multiple of the tile (padding path). 250 atoms
+    (padded 2304) is the largest size on 64 x 64 response tiles, 257 (2432) the
+    smallest on 128 x 128."""
     sysd, ep, h = _case(n_atoms=n_atoms, seed=10_000 + n_atoms)
     v = np.random.default_rng(n_atoms).standard_normal(2 * n_atoms)
     got = h.density_response_batch(t(v)).cpu().numpy()[0]

@@ -215,6 +215,23 @@ __global__ void zero_fill(double* p, size_t n) {
     p[i] = 0.0;
 }
 
+// The per-direction split operands of one response chunk in one launch:
+// blockIdx.y = 2 item + which, item z = 2 direction + spin; which 0 splits
+// (U~ C)^T from C^T, which 1 (U~ G)^T from G^T, each at its own scale.
+__global__ void split_operands(const double* __restrict__ CT0, const double* __restrict__ CT1,
+                               const double* __restrict__ GT0, const double* __restrict__ GT1, int np,
+                               const double* __restrict__ u, const double* __restrict__ msc,
+                               _Float16* __restrict__ uct_h, _Float16* __restrict__ uct_l,
+                               _Float16* __restrict__ ugt_h, _Float16* __restrict__ ugt_l,
+                               const int* __restrict__ stop) {
+  const int z = blockIdx.y >> 1, which = blockIdx.y & 1, spin = z & 1;
+  const size_t off = (size_t)z * np * np;
+  const double* src = which ? (spin ? GT1 : GT0) : (spin ? CT1 : CT0);
+  kk::split_scaled_columns_dev(src, np, u + (size_t)z * np, msc + z * 8 + 3 + which,
+                               (which ? ugt_h : uct_h) + off, (which ? ugt_l : uct_l) + off, stop, blockIdx.x,
+                               gridDim.x);
+}
+
 kk_status zero(kk_handle h, double* p, size_t n) {
   const int blocks = (int)std::min<size_t>((n + 255) / 256, 65536);
   zero_fill<<<std::max(blocks, 1), 256, 0, h->stream>>>(p, n);
@@ -394,17 +411,12 @@ kk_status response_chunk_mixed(kk_handle h, int batch, const double* v, double* 
   LAUNCH_CHECK("center_potentials");
   kk::mixed_scales<<<2 * batch, 1024, 0, h->stream>>>(h->u, np, h->mconst, h->beta, h->msc, stop);
   LAUNCH_CHECK("mixed_scales");
-  for (int z = 0; z < 2 * batch; ++z) {
-    const int s = z & 1;
-    const int blocks = (int)std::min<size_t>((np2 / 8 + 255) / 256, 16384);
-    kk::split_scaled_columns<<<blocks, 256, 0, h->stream>>>(h->CT[s], np, h->u + (size_t)z * np,
-                                                             h->msc + z * 8 + 3, h->uct_h + z * np2,
-                                                             h->uct_l + z * np2, stop);
-    LAUNCH_CHECK("split_scaled_columns");
-    kk::split_scaled_columns<<<blocks, 256, 0, h->stream>>>(h->GT[s], np, h->u + (size_t)z * np,
-                                                             h->msc + z * 8 + 4, h->ugt_h + z * np2,
-                                                             h->ugt_l + z * np2, stop);
-    LAUNCH_CHECK("split_scaled_columns");
+  {
+    const int blocks = (int)std::max<size_t>(1, std::min<size_t>((np2 / 8 + 255) / 256, 16384 / (4 * batch)));
+    split_operands<<<dim3(blocks, 4 * batch), 256, 0, h->stream>>>(h->CT[0], h->CT[1], h->GT[0], h->GT[1], np, h->u,
+                                                                    h->msc, h->uct_h, h->uct_l, h->ugt_h, h->ugt_l,
+                                                                    stop);
+    LAUNCH_CHECK("split_operands");
   }
   kk::MixedArgs fa{};
   fa.n = np; fa.k_half = np; fa.two_halves = 1; fa.ntiles = h->n_mupper; fa.nitems = 2 * batch;

@@ -742,6 +742,8 @@ kk_status krylov_run(kk_handle h, const char* who, const double* delta, int m, d
   if ((st = ensure_workspace(h, 1))) return st;
   const int* stop = &h->kst->stop;
   const int gv_threads = 256, gv_blocks = (n2 * kk::WAVE + gv_threads - 1) / gv_threads;
+  // orthonormalization: one block just large enough for 8 entries per thread
+  const int orth_threads = std::max(64, std::min(1024, ((n2 + 7) / 8 + 63) / 64 * 64));
 
   kk::krylov_reset<<<1, 64, 0, h->stream>>>(h->kst);
   LAUNCH_CHECK("krylov_reset");
@@ -749,7 +751,7 @@ kk_status krylov_run(kk_handle h, const char* who, const double* delta, int m, d
   LAUNCH_CHECK("precondition");
   for (int k = 0; k < m; ++k) {
     const double* src = (k == 0) ? h->ftilde : h->Ft + (size_t)(k - 1) * n2;
-    kk::krylov_orthonormalize<<<1, 1024, 0, h->stream>>>(src, h->V, n2, h->kst);
+    kk::krylov_orthonormalize<<<1, orth_threads, 0, h->stream>>>(src, h->V, n2, h->kst);
     LAUNCH_CHECK("krylov_orthonormalize");
     const double* vk = h->V + (size_t)k * n2;
     if ((st = response_any(h, 1, vk, h->q1, stop))) return st;

@@ -337,7 +337,8 @@ __global__ void precondition(const double* __restrict__ K0, const double* __rest
 
 // Orthogonalize src against the accepted directions V[0..rank) with modified
 // Gram-Schmidt, two passes; accept it as V[rank] if its norm kept more than
-// BREAKDOWN_TOL of its starting norm, else stop the expansion. One block.
+// BREAKDOWN_TOL of its starting norm, else stop the expansion. One block of
+// at least n2 / 8 threads.
 __device__ __forceinline__ void orth_dev(const double* __restrict__ src, double* __restrict__ V, int n2,
                                          KrylovState* st) {
   __shared__ double sh[17];
@@ -409,18 +410,31 @@ __device__ __forceinline__ void solve_dev(const double* __restrict__ V, const do
   __shared__ double c[MAX_RANK];
   __shared__ int ok;
   const int r = st->rank;
-  for (int a = 0; a < r; ++a) {
-    for (int b = 0; b <= a; ++b) {
+  // The r (r + 1) / 2 entries of O and the r of the right-hand side, one wave
+  // each (fixed lane order and shuffle tree, so the result is deterministic).
+  {
+    const int lane = threadIdx.x & (WAVE - 1), nw = blockDim.x / WAVE, npairs = r * (r + 1) / 2;
+    for (int p = threadIdx.x / WAVE; p < npairs + r; p += nw) {
+      int a, b = -1;
+      if (p < npairs) {
+        a = 0;
+        while ((a + 1) * (a + 2) / 2 <= p) ++a;
+        b = p - a * (a + 1) / 2;
+      } else {
+        a = p - npairs;
+      }
+      const double* fa = Ft + (size_t)a * n2;
+      const double* y = b >= 0 ? Ft + (size_t)b * n2 : ftilde;
       double d = 0.0;
-      for (int i = threadIdx.x; i < n2; i += blockDim.x) d += Ft[(size_t)a * n2 + i] * Ft[(size_t)b * n2 + i];
-      d = block_sum(d, sh);
-      if (threadIdx.x == 0) { O[a][b] = d; O[b][a] = d; }
+      for (int i = lane; i < n2; i += WAVE) d += fa[i] * y[i];
+      d = wave_sum(d);
+      if (lane == 0) {
+        if (b >= 0) { O[a][b] = d; O[b][a] = d; }
+        else c[a] = d;
+      }
     }
-    double d = 0.0;
-    for (int i = threadIdx.x; i < n2; i += blockDim.x) d += Ft[(size_t)a * n2 + i] * ftilde[i];
-    d = block_sum(d, sh);
-    if (threadIdx.x == 0) c[a] = d;
   }
+  __syncthreads();
   if (threadIdx.x == 0) {
     ok = 1;
     double pmin = 0.0, pmax = 0.0;

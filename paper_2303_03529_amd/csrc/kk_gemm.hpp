@@ -153,8 +153,9 @@ __device__ __forceinline__ void f64_tile(const GemmItem& it, const int n, const 
   __shared__ double Ss[SCALED ? 3 : 1][BK];
   d2 ra[AP], rb[BP];
   double sreg = 0.0;
-  // Byte offsets of this thread's staging pieces within a K stage (loop invariant, a
-  // few hundred KB at most); the stage's uniform part goes into the base pointers.
+  // Byte offsets of this thread's staging pieces within a K stage (loop invariant; BK
+  // rows of n <= 65536 doubles span at most 8 MB, so 32 bits hold them); the stage's
+  // uniform part goes into the base pointers.
   unsigned aoff[AP], boff[BP];
 #pragma unroll
   for (int p = 0; p < AP; ++p) {

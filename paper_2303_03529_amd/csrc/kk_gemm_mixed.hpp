@@ -674,12 +674,6 @@ __device__ __forceinline__ void split_scaled_columns_dev(const double* __restric
   }
 }
 
-__global__ void split_scaled_columns(const double* __restrict__ src, int np, const double* __restrict__ u,
-                                     const double* __restrict__ sc_p, _Float16* __restrict__ hi,
-                                     _Float16* __restrict__ lo, const int* __restrict__ stop) {
-  split_scaled_columns_dev(src, np, u, sc_p, hi, lo, stop, blockIdx.x, gridDim.x);
-}
-
 // Per-row max |x| and sum x^2 of an np x np FP64 matrix (one block per row).
 __global__ void row_stats(const double* __restrict__ m, int np, double* __restrict__ rmax,
                           double* __restrict__ rnorm2) {

@@ -354,21 +354,30 @@ __device__ __forceinline__ void orth_dev(const double* __restrict__ src, double*
     nn += w[e] * w[e];
   }
   const double start = sqrt(block_sum(nn, sh));
-  for (int pass = 0; pass < 2; ++pass) {
-    for (int j = 0; j < rank; ++j) {
-      const double* vj = V + (size_t)j * n2;
-      double d = 0.0;
+  // Two passes of projections against v_0 .. v_{rank-1}, in order; the entries of
+  // the next v_j are loaded before the current projection's reduction, so the
+  // loop waits on reductions, not on loads. Entries past n2 are zero in w and v.
+  auto load_row = [&](int j, double* dst) {
+    const double* vj = V + (size_t)j * n2;
 #pragma unroll
-      for (int e = 0; e < PER; ++e) {
-        const int i = threadIdx.x + e * blockDim.x;
-        if (i < n2) d += vj[i] * w[e];
-      }
-      d = block_sum(d, sh);
+    for (int e = 0; e < PER; ++e) {
+      const int i = threadIdx.x + e * blockDim.x;
+      dst[e] = i < n2 ? vj[i] : 0.0;
+    }
+  };
+  const int steps = 2 * rank;
+  double cur[PER], nxt[PER] = {};
+  if (steps > 0) load_row(0, cur);
+  for (int t = 0; t < steps; ++t) {
+    if (t + 1 < steps) load_row((t + 1) % rank, nxt);
+    double d = 0.0;
 #pragma unroll
-      for (int e = 0; e < PER; ++e) {
-        const int i = threadIdx.x + e * blockDim.x;
-        if (i < n2) w[e] -= d * vj[i];
-      }
+    for (int e = 0; e < PER; ++e) d += cur[e] * w[e];
+    d = block_sum(d, sh);
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      w[e] -= d * cur[e];
+      cur[e] = nxt[e];
     }
   }
   nn = 0.0;

@@ -75,6 +75,15 @@ constexpr int SMALL_NP_SPLIT = 1152;
 using SmallF64 = kk::Cfg64x64;
 using SmallMx = kk::MCfg64x64f8;
 static_assert(kk::PAD % SmallF64::BM == 0 && SPLIT_PAD % SmallMx::BM == 0, "small tiles must divide the padding");
+// Rows nb..np-1 of every operand a response transform or a setup product
+// contracts over are zero (the padded copies of S, Z, Q and the potentials are
+// zero there, hence C, G and Y too), so those contractions stop at nb rounded up
+// to KSTEP, which every K stage divides. The reverse pass keeps the full np.
+constexpr int KSTEP = 32;
+static_assert(KSTEP % kk::FwdCfg::BK == 0 && KSTEP % kk::BackCfg::BK == 0 && KSTEP % kk::StoreCfg::BK == 0 &&
+                  KSTEP % SmallF64::BK == 0 && KSTEP % kk::MFwdCfg::BK == 0 && KSTEP % kk::MBackCfg::BK == 0 &&
+                  KSTEP % SmallMx::BK == 0 && kk::PAD % KSTEP == 0,
+              "KSTEP must be a multiple of every K stage and divide the padding");
 constexpr int MAX_CHUNK = kk::MAX_GEMM_BATCH / 2;  // directions per GEMM launch
 constexpr size_t WORKSPACE_BUDGET = size_t(12) << 30;  // bytes of Y workspace per handle
 constexpr int MAX_EVENTS = 8192;
@@ -85,6 +94,7 @@ struct kk_handle_s {
   hipStream_t stream = nullptr;
   bool prepared = false;
   int natoms = 0, nb = 0, np = 0, nparts = 0;
+  int kc = 0;  // contraction length of the transforms: nb rounded up to KSTEP (<= np)
   double W = 0, kT = 0, beta = 0, n_e = 0;
   std::vector<void*> owned;  // every device allocation of the prepared state
 
@@ -345,10 +355,10 @@ kk_status response_chunk(kk_handle h, int batch, const double* v, double* q1, co
   }
   const bool small = h->small_f64;
   kk::GemmArgs fa{};
-  fa.n = np; fa.k_half = np; fa.two_halves = 1; fa.ntiles = small ? h->n_supper : h->n_upper;
+  fa.n = np; fa.k_half = h->kc; fa.two_halves = 1; fa.ntiles = small ? h->n_supper : h->n_upper;
   fa.nitems = 2 * batch; fa.tiles = small ? h->stiles_upper : h->tiles_upper; fa.stop = stop; fa.beta = h->beta;
   kk::GemmArgs ba{};
-  ba.n = np; ba.k_half = np; ba.two_halves = 0; ba.ntiles = small ? h->n_sfull : h->n_full;
+  ba.n = np; ba.k_half = h->kc; ba.two_halves = 0; ba.ntiles = small ? h->n_sfull : h->n_full;
   ba.nitems = 2 * batch; ba.tiles = small ? h->stiles_full : h->tiles_full; ba.stop = stop; ba.beta = h->beta;
   for (int b = 0; b < batch; ++b)
     for (int s = 0; s < 2; ++s) {
@@ -419,10 +429,10 @@ kk_status response_chunk_mixed(kk_handle h, int batch, const double* v, double* 
     LAUNCH_CHECK("split_operands");
   }
   kk::MixedArgs fa{};
-  fa.n = np; fa.k_half = np; fa.two_halves = 1; fa.ntiles = h->n_mupper; fa.nitems = 2 * batch;
+  fa.n = np; fa.k_half = h->kc; fa.two_halves = 1; fa.ntiles = h->n_mupper; fa.nitems = 2 * batch;
   fa.tiles = h->mtiles_upper; fa.stop = stop; fa.beta = h->beta;
   kk::MixedArgs ba{};
-  ba.n = np; ba.k_half = np; ba.two_halves = 0; ba.ntiles = h->n_mfull; ba.nitems = 2 * batch;
+  ba.n = np; ba.k_half = h->kc; ba.two_halves = 0; ba.ntiles = h->n_mfull; ba.nitems = 2 * batch;
   ba.tiles = h->mtiles_full; ba.stop = stop; ba.beta = h->beta;
   for (int z = 0; z < 2 * batch; ++z) {
     const int s = z & 1;
@@ -624,6 +634,7 @@ kk_status kk_prepare(kk_handle h, int n_atoms, const int* atom_offsets, int n_ba
     h->release();
     h->precision = precision;
     h->natoms = n_atoms; h->nb = nb; h->np = np;
+    h->kc = (nb + KSTEP - 1) / KSTEP * KSTEP;
     h->small_f64 = !mixed && np <= SMALL_NP_F64;
     h->small_mfwd = mixed && np <= SMALL_NP_SPLIT;
     h->nparts = mixed ? (np / kk::MBackCfg::BN) * kk::MBackCfg::WAVES_N
@@ -650,7 +661,7 @@ kk_status kk_prepare(kk_handle h, int n_atoms, const int* atom_offsets, int n_ba
     LAUNCH_CHECK("pad_copy Q");
   }
   kk::GemmArgs a{};
-  a.n = np; a.k_half = np; a.two_halves = 0; a.ntiles = h->n_store; a.tiles = h->tiles_store;
+  a.n = np; a.k_half = h->kc; a.two_halves = 0; a.ntiles = h->n_store; a.tiles = h->tiles_store;
   a.stop = nullptr; a.nitems = 2;
   for (int s = 0; s < 2; ++s) {  // C_s[m][n] = sum_k Z^T[k][m] Q_s[k][n]
     a.item[s] = kk::GemmItem{};
@@ -1522,7 +1533,7 @@ kk_status kk_batch_prepare(kk_batch b, int n_systems, const int* n_atoms, const 
     for (int s = 0; s < 2; ++s) {
       if (mixed) {
         kk::BatchItemMixed fi{}, bi{};
-        fi.n = bi.n = h->np; fi.beta = bi.beta = h->beta; fi.stop = bi.stop = &h->kst->stop;
+        fi.n = bi.n = h->np; fi.k = bi.k = h->kc; fi.beta = bi.beta = h->beta; fi.stop = bi.stop = &h->kst->stop;
         kk::MixedItem& F = fi.g;
         F.a0h = h->uct_h + s * np2; F.a0l = h->uct_l + s * np2; F.b0h = h->GTh[s]; F.b0l = h->GTl[s];
         F.a1h = h->ugt_h + s * np2; F.a1l = h->ugt_l + s * np2; F.b1h = h->CTh[s]; F.b1l = h->CTl[s];
@@ -1536,7 +1547,7 @@ kk_status kk_batch_prepare(kk_batch b, int n_systems, const int* n_atoms, const 
         mxb.push_back(bi);
       } else {
         kk::BatchItemF64 fi{}, bi{};
-        fi.n = bi.n = h->np; fi.beta = bi.beta = h->beta; fi.stop = bi.stop = &h->kst->stop;
+        fi.n = bi.n = h->np; fi.k = bi.k = h->kc; fi.beta = bi.beta = h->beta; fi.stop = bi.stop = &h->kst->stop;
         kk::GemmItem& F = fi.g;
         F.a0 = h->C[s]; F.b0 = h->G[s]; F.a1 = h->G[s]; F.b1 = h->C[s];
         F.scale = h->u + s * np; F.out = h->Y + s * np2;

@@ -37,14 +37,14 @@ struct SysDesc {
 
 struct BatchItemF64 {
   GemmItem g;
-  int n, pad;
+  int n, k;  // padded size; contraction length (rows past the system's nb are zero)
   const int* stop;
   double beta;
 };
 
 struct BatchItemMixed {
   MixedItem g;
-  int n, pad;
+  int n, k;
   const int* stop;
   double beta;
 };
@@ -144,7 +144,7 @@ __global__ __launch_bounds__(Cfg::THREADS) __attribute__((amdgpu_waves_per_eu(Cf
     const int4 tl = tiles[t];
     const BatchItemF64& it = items[tl.x];
     if (*it.stop) continue;
-    f64_tile<EPI, Cfg>(it.g, it.n, it.n, two_halves != 0, make_int2(tl.y, tl.z), it.beta);
+    f64_tile<EPI, Cfg>(it.g, it.n, it.k, two_halves != 0, make_int2(tl.y, tl.z), it.beta);
   }
 }
 
@@ -159,7 +159,7 @@ void b_gemm_mixed(const BatchItemMixed* __restrict__ items, const int4* __restri
     const int4 tl = tiles[t];
     const BatchItemMixed& it = items[tl.x];
     if (*it.stop) continue;
-    mixed_tile<EPI, Cfg>(it.g, it.n, it.n, two_halves != 0, make_int2(tl.y, tl.z), it.beta);
+    mixed_tile<EPI, Cfg>(it.g, it.n, it.k, two_halves != 0, make_int2(tl.y, tl.z), it.beta);
   }
 }
 

@@ -50,6 +50,16 @@ def test_mixed_response_fe16(fe16m):
     assert max(errs) < TOL_MIXED
 
 
+def test_mixed_response_fe16_full_chunks(fe16m):
+    """More directions than one launch takes (several full chunks and a partial one):
+    every direction's operands are split in the chunk's single launch."""
+    sysd, ep, h = fe16m
+    V = np.random.default_rng(11).standard_normal((19, 2 * sysd["n_atoms"]))
+    got = h.density_response_batch(t(V)).cpu().numpy()
+    errs = [rel(got[b], response(sysd, ep, V[b])) for b in range(V.shape[0])]
+    assert max(errs) < TOL_MIXED, errs
+
+
 def test_mixed_response_fe128(fe128m):
     sysd, ep, h = fe128m
     V = np.random.default_rng(2).standard_normal((2, 2 * sysd["n_atoms"]))

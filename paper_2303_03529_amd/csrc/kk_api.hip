@@ -63,15 +63,13 @@ constexpr int SPLIT_PAD = kk::MIXED_PAD > kk::PAD ? kk::MIXED_PAD : kk::PAD;
 static_assert(SPLIT_PAD % kk::MIXED_PAD == 0 && SPLIT_PAD % kk::PAD == 0,
               "split-precision padding must be a multiple of every tile side");
 // Small systems fill the chip better with 64 x 64 tiles (a 128-atom system has
-// 45 upper 128 x 128 forward tiles per spin for 256 CUs). Up to these padded
-// sizes the FP64 response transforms (both) and the split forward transform use
-// them; the reverse pass and the setup products keep the large tiles. On MI355X:
-// FP64 forward 0.22 vs 0.34 ms and back 0.144 vs 0.169 ms at Nb = 1152, forward
-// 1.08 vs 1.20 ms and back equal at Nb = 2250, 64 x 64 slower from Nb = 3888;
-// split forward 0.080 vs 0.098 ms at Nb = 1152 and slower at 2250 (its back
-// transform is not faster with them at any size).
+// 45 upper 128 x 128 forward tiles per spin for 256 CUs). Up to this padded
+// size the FP64 response transforms (both) use them; the reverse pass and the
+// setup products keep the large tiles. On MI355X: FP64 forward 0.22 vs 0.34 ms
+// and back 0.144 vs 0.169 ms at Nb = 1152, forward 1.08 vs 1.20 ms and back
+// equal at Nb = 2250, 64 x 64 slower from Nb = 3888. The batch uses the same
+// shapes for its small-tile class (SmallMx in the split form).
 constexpr int SMALL_NP_F64 = 2304;
-constexpr int SMALL_NP_SPLIT = 1152;
 using SmallF64 = kk::Cfg64x64;
 using SmallMx = kk::MCfg64x64f8;
 static_assert(kk::PAD % SmallF64::BM == 0 && SPLIT_PAD % SmallMx::BM == 0, "small tiles must divide the padding");
@@ -106,9 +104,8 @@ struct kk_handle_s {
   int* offsets = nullptr;
   int2 *tiles_upper = nullptr, *tiles_full = nullptr, *tiles_store = nullptr;
   int n_upper = 0, n_full = 0, n_store = 0;
-  // small systems: 64 x 64 tiles for the response transforms (FP64 lists here;
-  // the split forward's list is mtiles_upper)
-  bool small_f64 = false, small_mfwd = false;
+  // small systems: 64 x 64 tiles for the FP64 response transforms
+  bool small_f64 = false;
   int2 *stiles_upper = nullptr, *stiles_full = nullptr;
   int n_supper = 0, n_sfull = 0;
 
@@ -119,9 +116,11 @@ struct kk_handle_s {
   _Float16 *CTh[2] = {nullptr, nullptr}, *CTl[2] = {nullptr, nullptr};
   _Float16 *GTh[2] = {nullptr, nullptr}, *GTl[2] = {nullptr, nullptr};
   double* mconst = nullptr;  // per spin: s_C, s_G, max column norms of C and G
-  int2 *mtiles_upper = nullptr, *mtiles_full = nullptr;
-  int n_mupper = 0, n_mfull = 0;
+  int2* mtiles_full = nullptr;  // both split transforms of a single system: full tiles
+  int n_mfull = 0;
+  // (U~ C)^T split per direction; (U~ G)^T only for a batch's two-half forward transform
   _Float16 *uct_h = nullptr, *uct_l = nullptr, *ugt_h = nullptr, *ugt_l = nullptr;
+  float* x32 = nullptr;  // split forward: the product C^T U~ G per direction, FP32
   _Float16 *yh = nullptr, *yl = nullptr;
   double* msc = nullptr;
   double* mscratch = nullptr;  // 4 np doubles: row statistics for the split scales
@@ -178,6 +177,7 @@ struct kk_handle_s {
     chunk_cap = 0;
     u = Y = xdiag = part = nullptr;
     uct_h = uct_l = ugt_h = ugt_l = yh = yl = nullptr;
+    x32 = nullptr;
     msc = nullptr;
   }
 
@@ -225,21 +225,16 @@ __global__ void zero_fill(double* p, size_t n) {
     p[i] = 0.0;
 }
 
-// The per-direction split operands of one response chunk in one launch:
-// blockIdx.y = 2 item + which, item z = 2 direction + spin; which 0 splits
-// (U~ C)^T from C^T, which 1 (U~ G)^T from G^T, each at its own scale.
-__global__ void split_operands(const double* __restrict__ CT0, const double* __restrict__ CT1,
-                               const double* __restrict__ GT0, const double* __restrict__ GT1, int np,
+// The per-direction split operand (U~ C)^T of every item of a response chunk in
+// one launch: blockIdx.y = item z = 2 direction + spin, split from C^T at its scale.
+__global__ void split_operands(const double* __restrict__ CT0, const double* __restrict__ CT1, int np,
                                const double* __restrict__ u, const double* __restrict__ msc,
                                _Float16* __restrict__ uct_h, _Float16* __restrict__ uct_l,
-                               _Float16* __restrict__ ugt_h, _Float16* __restrict__ ugt_l,
                                const int* __restrict__ stop) {
-  const int z = blockIdx.y >> 1, which = blockIdx.y & 1, spin = z & 1;
+  const int z = blockIdx.y;
   const size_t off = (size_t)z * np * np;
-  const double* src = which ? (spin ? GT1 : GT0) : (spin ? CT1 : CT0);
-  kk::split_scaled_columns_dev(src, np, u + (size_t)z * np, msc + z * 8 + 3 + which,
-                               (which ? ugt_h : uct_h) + off, (which ? ugt_l : uct_l) + off, stop, blockIdx.x,
-                               gridDim.x);
+  kk::split_scaled_columns_dev((z & 1) ? CT1 : CT0, np, u + (size_t)z * np, msc + z * 8 + 3, uct_h + off,
+                               uct_l + off, stop, blockIdx.x, gridDim.x);
 }
 
 kk_status zero(kk_handle h, double* p, size_t n) {
@@ -323,6 +318,7 @@ kk_status ensure_workspace(kk_handle h, int chunk) {
   } else {
     for (_Float16** q : {&h->uct_h, &h->uct_l, &h->ugt_h, &h->ugt_l, &h->yh, &h->yl})
       if ((st = dalloc_t(h, q, items * np * np, true))) return st;
+    if ((st = dalloc_t(h, &h->x32, items * np * np, true))) return st;
     if ((st = dalloc_t(h, &h->msc, items * 8, true))) return st;
   }
   if ((st = dalloc_t(h, &h->xdiag, items * np, true))) return st;
@@ -333,8 +329,9 @@ kk_status ensure_workspace(kk_handle h, int chunk) {
 }
 
 int max_chunk(kk_handle h) {
-  // FP64: one Y per spin; split path: six FP16 matrices per spin
-  const size_t per_dir = (size_t)2 * h->np * h->np * (h->precision == KK_FP64 ? sizeof(double) : 6 * sizeof(_Float16));
+  // FP64: one Y per spin; split path: six FP16 matrices and one FP32 per spin
+  const size_t per_dir = (size_t)2 * h->np * h->np *
+                         (h->precision == KK_FP64 ? sizeof(double) : 6 * sizeof(_Float16) + sizeof(float));
   size_t c = WORKSPACE_BUDGET / std::max<size_t>(per_dir, 1);
   return (int)std::max<size_t>(1, std::min<size_t>(c, MAX_CHUNK));
 }
@@ -389,12 +386,13 @@ kk_status launch_mixed(kk_handle h, int epi, kk::MixedArgs& a) {
   const int grid = a.ntiles * a.nitems;
   if (grid <= 0) return KK_OK;
   if (a.nitems > kk::MAX_GEMM_BATCH) return fail(KK_EINVAL, "internal: too many GEMM items");
-  if (epi == kk::EPI_FERMI) {
+  if (epi == kk::EPI_FERMI) {  // forward: full-tile product, then symmetrize and split Y
     ProfileScope ps(h, 0);
-    if (h->small_mfwd)
-      kk::gemm_mixed<kk::EPI_FERMI, SmallMx><<<grid, SmallMx::THREADS, 0, h->stream>>>(a);
-    else
-      kk::gemm_mixed<kk::EPI_FERMI, kk::MFwdCfg><<<grid, kk::MFwdCfg::THREADS, 0, h->stream>>>(a);
+    kk::gemm_mixed<kk::EPI_STORE, kk::MBackCfg><<<grid, kk::MBackCfg::THREADS, 0, h->stream>>>(a);
+    LAUNCH_CHECK("gemm_mixed");
+    const int nblk = a.n / kk::SYM_B;
+    kk::fermi_symmetrize<<<dim3(nblk * (nblk + 1) / 2, a.nitems), 256, 0, h->stream>>>(a);
+    LAUNCH_CHECK("fermi_symmetrize");
   } else {
     ProfileScope ps(h, 1);
     kk::gemm_mixed<kk::EPI_MULLIKEN, kk::MBackCfg><<<grid, kk::MBackCfg::THREADS, 0, h->stream>>>(a);
@@ -422,15 +420,15 @@ kk_status response_chunk_mixed(kk_handle h, int batch, const double* v, double* 
   kk::mixed_scales<<<2 * batch, 1024, 0, h->stream>>>(h->u, np, h->mconst, h->beta, h->msc, stop);
   LAUNCH_CHECK("mixed_scales");
   {
-    const int blocks = (int)std::max<size_t>(1, std::min<size_t>((np2 / 8 + 255) / 256, 16384 / (4 * batch)));
-    split_operands<<<dim3(blocks, 4 * batch), 256, 0, h->stream>>>(h->CT[0], h->CT[1], h->GT[0], h->GT[1], np, h->u,
-                                                                    h->msc, h->uct_h, h->uct_l, h->ugt_h, h->ugt_l,
-                                                                    stop);
+    const int blocks = (int)std::max<size_t>(1, std::min<size_t>((np2 / 8 + 255) / 256, 16384 / (2 * batch)));
+    split_operands<<<dim3(blocks, 2 * batch), 256, 0, h->stream>>>(h->CT[0], h->CT[1], np, h->u, h->msc, h->uct_h,
+                                                                    h->uct_l, stop);
     LAUNCH_CHECK("split_operands");
   }
+  // forward: A = C^T U~ G over full tiles (At = (U~ C)^T, Bt = G^T), X = (A + A^T) / 2
   kk::MixedArgs fa{};
-  fa.n = np; fa.k_half = h->kc; fa.two_halves = 1; fa.ntiles = h->n_mupper; fa.nitems = 2 * batch;
-  fa.tiles = h->mtiles_upper; fa.stop = stop; fa.beta = h->beta;
+  fa.n = np; fa.k_half = h->kc; fa.two_halves = 0; fa.ntiles = h->n_mfull; fa.nitems = 2 * batch;
+  fa.tiles = h->mtiles_full; fa.stop = stop; fa.beta = h->beta;
   kk::MixedArgs ba{};
   ba.n = np; ba.k_half = h->kc; ba.two_halves = 0; ba.ntiles = h->n_mfull; ba.nitems = 2 * batch;
   ba.tiles = h->mtiles_full; ba.stop = stop; ba.beta = h->beta;
@@ -438,7 +436,7 @@ kk_status response_chunk_mixed(kk_handle h, int batch, const double* v, double* 
     const int s = z & 1;
     kk::MixedItem& fi = fa.item[z];
     fi.a0h = h->uct_h + z * np2; fi.a0l = h->uct_l + z * np2; fi.b0h = h->GTh[s]; fi.b0l = h->GTl[s];
-    fi.a1h = h->ugt_h + z * np2; fi.a1l = h->ugt_l + z * np2; fi.b1h = h->CTh[s]; fi.b1l = h->CTl[s];
+    fi.x32 = h->x32 + z * np2;
     fi.yh = h->yh + z * np2; fi.yl = h->yl + z * np2;
     fi.eps = h->eps[s]; fi.f = h->f[s]; fi.fc = h->fc[s]; fi.w = h->w[s];
     fi.xdiag = h->xdiag + (size_t)z * np;
@@ -497,7 +495,7 @@ kk_status allocate_prepared(kk_handle h) {
   std::vector<int2> up = tile_order(np, kk::FwdCfg::BM, kk::FwdCfg::BN, true);
   std::vector<int2> full = tile_order(np, kk::BackCfg::BM, kk::BackCfg::BN, false);
   std::vector<int2> stt = tile_order(np, kk::StoreCfg::BM, kk::StoreCfg::BN, false);
-  std::vector<int2> sup, sfull, mup, mfull;
+  std::vector<int2> sup, sfull, mfull;
   if (h->small_f64) {
     sup = tile_order(np, SmallF64::BM, SmallF64::BN, true);
     sfull = tile_order(np, SmallF64::BM, SmallF64::BN, false);
@@ -536,15 +534,9 @@ kk_status allocate_prepared(kk_handle h) {
       for (_Float16** q : {&h->Ch[s], &h->Cl[s], &h->CTh[s], &h->CTl[s], &h->GTh[s], &h->GTl[s]})
         if ((st = dalloc_t(h, q, np2))) return st;
     }
-    mup = h->small_mfwd ? tile_order(np, SmallMx::BM, SmallMx::BN, true)
-                        : tile_order(np, kk::MFwdCfg::BM, kk::MFwdCfg::BN, true);
     mfull = tile_order(np, kk::MBackCfg::BM, kk::MBackCfg::BN, false);
-    h->n_mupper = (int)mup.size();
     h->n_mfull = (int)mfull.size();
-    if ((st = dalloc_t(h, &h->mtiles_upper, mup.size()))) return st;
     if ((st = dalloc_t(h, &h->mtiles_full, mfull.size()))) return st;
-    HIP_OR_FAIL(hipMemcpyAsync(h->mtiles_upper, mup.data(), sizeof(int2) * mup.size(), hipMemcpyHostToDevice,
-                               h->stream));
     HIP_OR_FAIL(hipMemcpyAsync(h->mtiles_full, mfull.data(), sizeof(int2) * mfull.size(),
                                hipMemcpyHostToDevice, h->stream));
   }
@@ -636,7 +628,6 @@ kk_status kk_prepare(kk_handle h, int n_atoms, const int* atom_offsets, int n_ba
     h->natoms = n_atoms; h->nb = nb; h->np = np;
     h->kc = (nb + KSTEP - 1) / KSTEP * KSTEP;
     h->small_f64 = !mixed && np <= SMALL_NP_F64;
-    h->small_mfwd = mixed && np <= SMALL_NP_SPLIT;
     h->nparts = mixed ? (np / kk::MBackCfg::BN) * kk::MBackCfg::WAVES_N
                       : h->small_f64 ? (np / SmallF64::BN) * SmallF64::WAVES_N
                                      : (np / kk::BackCfg::BN) * kk::BackCfg::WAVES_N;

@@ -12,11 +12,13 @@
 //
 // Layout (NT form): out[m][n] = sum_k At[m][k] * Bt[n][k] with At, Bt stored
 // row-major with k contiguous, so each lane's 8 FP16 MFMA operands are one
-// 16-byte LDS read. The forward transform uses
-//   At = (U~ C)^T, Bt = G^T over the first K half and At = (U~ G)^T, Bt = C^T
-//   over the second (the two halves share one scale), giving C^T U~ G + G^T U~ C;
-// the back-transform uses At = C (row i, k = l) and Bt = Y (symmetric, so
-// row k of Y is column k).
+// 16-byte LDS read. The forward transform of a single system is a full-tile
+// product A = C^T U~ G (At = (U~ C)^T, Bt = G^T, EPI_STORE: A in FP32) followed
+// by fermi_symmetrize, which forms X = (A + A^T) / 2 in FP64 and Y = F o X.
+// The batched forward instead runs upper tiles over two K halves, At = (U~ C)^T,
+// Bt = G^T then At = (U~ G)^T, Bt = C^T (one scale), giving C^T U~ G + G^T U~ C
+// (EPI_FERMI). The back-transform uses At = C (row i, k = l) and Bt = Y
+// (symmetric, so row k of Y is column k).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -37,6 +39,7 @@ struct MixedItem {
   double* xdiag;                          // forward: diag X
   double* part;                           // back: Mulliken partials [parts][n]
   const double* sc;                       // device scalars: [0] = 1 / product scale, [1] = Y scale
+  float* x32;                             // EPI_STORE: the product A in FP32, [n][n]
 };
 
 struct MixedArgs {
@@ -284,7 +287,17 @@ __device__ __forceinline__ void mixed_epilogue(const MixedItem& it, const int n,
   const double inv = it.sc[0];
   const int mw = m0 + wm * (BM / Cfg::WAVES_M) + 4 * lh;
   const int nw = n0 + wn * (BN / Cfg::WAVES_N) + l32;
-  if constexpr (EPI == EPI_FERMI) {
+  if constexpr (EPI == EPI_STORE) {
+    // 32 consecutive columns of one row per instruction and accumulator element
+#pragma unroll
+    for (int i = 0; i < WTM; ++i)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = mw + i * 32 + 8 * (r / 4) + (r % 4);
+#pragma unroll
+        for (int j = 0; j < WTN; ++j) it.x32[(size_t)m * n + nw + j * 32] = acc[i][j][r];
+      }
+  } else if constexpr (EPI == EPI_FERMI) {
     // Y is written twice: the tile itself straight from the accumulator layout (32
     // consecutive columns per row and instruction, full cache lines per wave), and its
     // mirror through LDS (hi and lo tiles, transposed there) with 16-byte row stores.
@@ -570,6 +583,57 @@ __global__ __launch_bounds__(Cfg::THREADS, Cfg::MIN_BLOCKS) void gemm_mixed(cons
   const int z = logical / args.ntiles;
   mixed_tile<EPI, Cfg>(args.item[z], args.n, args.k_half, args.two_halves != 0,
                        args.tiles[logical - z * args.ntiles], args.beta);
+}
+
+// Second pass of the single-system split forward transform. For each 64 x 64
+// block pair (I <= J) of each item: X = (A + A^T) / 2 / s_prod in FP64 from the
+// FP32 product A, Y = F o X off the diagonal and Y_ii = -w_i X_ii (X_ii to
+// xdiag), split at the Y scale and written to block (I, J) and, through LDS,
+// to its mirror (J, I). blockIdx.x = pair (row-major over the upper triangle),
+// blockIdx.y = item; 256 threads.
+constexpr int SYM_B = 64;
+__global__ __launch_bounds__(256) void fermi_symmetrize(const MixedArgs args) {
+  if (args.stop != nullptr && *args.stop != 0) return;
+  const MixedItem& it = args.item[blockIdx.y];
+  const int n = args.n, nblk = n / SYM_B;
+  int I = 0, rem = blockIdx.x;
+  while (rem >= nblk - I) {
+    rem -= nblk - I;
+    ++I;
+  }
+  const int J = I + rem;
+  __shared__ float At[SYM_B][SYM_B + 1];               // block (J, I) of A
+  __shared__ _Float16 Th[SYM_B][SYM_B + 2], Tl[SYM_B][SYM_B + 2];  // Y block (I, J), transposed
+  const int tx = threadIdx.x % SYM_B, ty = threadIdx.x / SYM_B;
+  constexpr int RS = 256 / SYM_B;
+  for (int r = ty; r < SYM_B; r += RS) At[r][tx] = it.x32[(size_t)(J * SYM_B + r) * n + I * SYM_B + tx];
+  __syncthreads();
+  const double inv = it.sc[0], sy = it.sc[1], beta = args.beta;
+  const int c = J * SYM_B + tx;
+  const double en = it.eps[c], fn = it.f[c], fcn = it.fc[c];
+  for (int r = ty; r < SYM_B; r += RS) {
+    const int m = I * SYM_B + r;
+    const double x = 0.5 * inv * ((double)it.x32[(size_t)m * n + c] + (double)At[tx][r]);
+    double y;
+    if (m == c) {
+      it.xdiag[m] = x;
+      y = -it.w[m] * x * sy;
+    } else {
+      y = fermi_divided_difference(it.eps[m], it.f[m], it.fc[m], en, fn, fcn, beta) * x * sy;
+    }
+    const _Float16 h = (_Float16)(float)y, l = (_Float16)(float)(y - (double)h);
+    it.yh[(size_t)m * n + c] = h;
+    it.yl[(size_t)m * n + c] = l;
+    Th[tx][r] = h;
+    Tl[tx][r] = l;
+  }
+  if (I == J) return;  // a diagonal block is symmetric by construction
+  __syncthreads();
+  for (int r = ty; r < SYM_B; r += RS) {
+    const size_t o = (size_t)(J * SYM_B + r) * n + I * SYM_B + tx;
+    it.yh[o] = Th[r][tx];
+    it.yl[o] = Tl[r][tx];
+  }
 }
 
 using MCfg128x128 = MixedCfg<128, 128, 32, 2, 2, 2>;

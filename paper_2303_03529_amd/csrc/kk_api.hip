@@ -106,6 +106,7 @@ struct kk_handle_s {
   int n_upper = 0, n_full = 0, n_store = 0;
   // small systems: 64 x 64 tiles for the FP64 response transforms
   bool small_f64 = false;
+  bool full_fwd = false;  // FP64 forward as full tiles + fermi_symmetrize_f64 (see full_forward)
   int2 *stiles_upper = nullptr, *stiles_full = nullptr;
   int n_supper = 0, n_sfull = 0;
 
@@ -247,6 +248,25 @@ kk_status zero(kk_handle h, double* p, size_t n) {
 // Tile orders. Full grid: groups of 8 tile rows, sweep columns inside a group,
 // so the tiles resident on one XCD share A and B panels. Upper: the same
 // order restricted to tiles holding at least one element with m <= n.
+int cu_count() {
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  return cus;
+}
+
+// Form of the FP64 forward transform of one direction (both spins): the upper
+// tiles over two K halves with the Fermi product in the epilogue, or all tiles
+// over one half (half the cost each) followed by fermi_symmetrize_f64. The full
+// form is taken when it needs fewer rounds of workgroup slots, a partial round
+// counted whole (ties go to the one-kernel form). On MI355X this picks the full
+// form at Nb = 1152 (forward 0.15 vs 0.20 ms) and 9216 (46.4 vs 47.2 ms) and the
+// upper form at 3888 (3.89 vs 3.95 ms).
+bool full_forward(int n_upper, int n_full, int slots) {
+  const int upper_rounds = (2 * n_upper + slots - 1) / slots;
+  const int full_rounds = (2 * n_full + slots - 1) / slots;
+  return full_rounds < 2 * upper_rounds;
+}
+
 std::vector<int2> tile_order(int np, int bm, int bn, bool upper) {
   std::vector<int2> v;
   const int TM = np / bm, TN = np / bn;
@@ -289,6 +309,15 @@ kk_status launch_gemm(kk_handle h, int epi, kk::GemmArgs& a, bool small = false)
       kk::gemm_f64<kk::EPI_FERMI, SmallF64><<<grid, SmallF64::THREADS, 0, h->stream>>>(a);
     else
       kk::gemm_f64<kk::EPI_FERMI, kk::FwdCfg><<<grid, kk::FwdCfg::THREADS, 0, h->stream>>>(a);
+  } else if (epi == kk::EPI_XSTORE) {  // forward: full-tile product into Y, then Y = F o X in place
+    ProfileScope ps(h, 0);
+    if (small)
+      kk::gemm_f64<kk::EPI_XSTORE, SmallF64><<<grid, SmallF64::THREADS, 0, h->stream>>>(a);
+    else
+      kk::gemm_f64<kk::EPI_XSTORE, kk::BackCfg><<<grid, kk::BackCfg::THREADS, 0, h->stream>>>(a);
+    LAUNCH_CHECK("gemm_f64");
+    const int nblk = a.n / kk::SYM64_B;
+    kk::fermi_symmetrize_f64<<<dim3(nblk * (nblk + 1) / 2, a.nitems), 256, 0, h->stream>>>(a);
   } else if (epi == kk::EPI_FERMI_XY) {
     ProfileScope ps(h, 2);
     kk::gemm_f64<kk::EPI_FERMI_XY, kk::FwdCfg><<<grid, kk::FwdCfg::THREADS, 0, h->stream>>>(a);
@@ -352,8 +381,13 @@ kk_status response_chunk(kk_handle h, int batch, const double* v, double* q1, co
   }
   const bool small = h->small_f64;
   kk::GemmArgs fa{};
-  fa.n = np; fa.k_half = h->kc; fa.two_halves = 1; fa.ntiles = small ? h->n_supper : h->n_upper;
-  fa.nitems = 2 * batch; fa.tiles = small ? h->stiles_upper : h->tiles_upper; fa.stop = stop; fa.beta = h->beta;
+  // forward (full_fwd): A = C^T U~ G over full tiles into Y, then X = (A + A^T) / 2 and
+  // Y = F o X in place; otherwise upper tiles over both K halves with the Fermi epilogue
+  const bool full = h->full_fwd;
+  fa.n = np; fa.k_half = h->kc; fa.two_halves = full ? 0 : 1;
+  fa.ntiles = small ? (full ? h->n_sfull : h->n_supper) : (full ? h->n_full : h->n_upper);
+  fa.nitems = 2 * batch; fa.tiles = small ? (full ? h->stiles_full : h->stiles_upper) : (full ? h->tiles_full : h->tiles_upper);
+  fa.stop = stop; fa.beta = h->beta;
   kk::GemmArgs ba{};
   ba.n = np; ba.k_half = h->kc; ba.two_halves = 0; ba.ntiles = small ? h->n_sfull : h->n_full;
   ba.nitems = 2 * batch; ba.tiles = small ? h->stiles_full : h->tiles_full; ba.stop = stop; ba.beta = h->beta;
@@ -371,7 +405,7 @@ kk_status response_chunk(kk_handle h, int batch, const double* v, double* q1, co
       bi.part = h->part + (size_t)z * h->nparts * np;
     }
   kk_status st;
-  if ((st = launch_gemm(h, kk::EPI_FERMI, fa, small))) return st;
+  if ((st = launch_gemm(h, full ? kk::EPI_XSTORE : kk::EPI_FERMI, fa, small))) return st;
   if ((st = launch_gemm(h, kk::EPI_MULLIKEN, ba, small))) return st;
   {
     dim3 grid((N + kk::COMBINE_ATOMS - 1) / kk::COMBINE_ATOMS, batch);
@@ -511,6 +545,9 @@ kk_status allocate_prepared(kk_handle h) {
   h->n_upper = (int)up.size();
   h->n_full = (int)full.size();
   h->n_store = (int)stt.size();
+  static_assert(kk::FwdCfg::MIN_BLOCKS == kk::BackCfg::MIN_BLOCKS, "one slot count for both forward forms");
+  h->full_fwd = h->small_f64 ? full_forward(h->n_supper, h->n_sfull, cu_count() * SmallF64::MIN_BLOCKS)
+                             : full_forward(h->n_upper, h->n_full, cu_count() * kk::BackCfg::MIN_BLOCKS);
   if ((st = dalloc_t(h, &h->tiles_upper, up.size()))) return st;
   if ((st = dalloc_t(h, &h->tiles_full, full.size()))) return st;
   if ((st = dalloc_t(h, &h->tiles_store, stt.size()))) return st;
@@ -1255,12 +1292,6 @@ kk_status balloc(kk_batch b, T** p, size_t count) {
   kk_status st = dalloc(b->owned, &q, count * sizeof(T));
   *p = static_cast<T*>(q);
   return st;
-}
-
-int cu_count() {
-  int dev = 0, cus = 256;
-  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  return cus;
 }
 
 // Build the tile lists of both classes for a threshold: items (2 per system)

@@ -26,6 +26,9 @@
 //   EPI_FERMI_XY  EPI_FERMI that also writes X itself (both triangles) to xout,
 //               for the reverse pass, which needs X and Y of each direction.
 //   EPI_ACCUM   out[m][n] += acc                                (adjoint sums)
+//   EPI_XSTORE  out[m][n] = acc with the row scale applied like EPI_FERMI: the
+//               product A = C^T U~ G over full tiles (one K half), which
+//               fermi_symmetrize_f64 turns into Y in place
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -38,7 +41,7 @@ typedef double d2 __attribute__((ext_vector_type(2)));
 constexpr int PAD = 128;    // every padded dimension is a multiple of this
 constexpr int MAX_GEMM_BATCH = 16;
 
-enum { EPI_STORE = 0, EPI_FERMI = 1, EPI_MULLIKEN = 2, EPI_FERMI_XY = 3, EPI_ACCUM = 4 };
+enum { EPI_STORE = 0, EPI_FERMI = 1, EPI_MULLIKEN = 2, EPI_FERMI_XY = 3, EPI_ACCUM = 4, EPI_XSTORE = 5 };
 
 struct GemmItem {
   const double* a0;   // first K half: A operand, [K][n] row-major
@@ -149,7 +152,7 @@ __device__ __forceinline__ void f64_tile(const GemmItem& it, const int n, const 
   // The forward transform's row scales go through a 3-slot LDS ring: the BK scales of
   // stage s are loaded by the first BK threads at the start of step s - 2, put in slot
   // s % 3 at its end, and multiplied in when stage s is written to LDS (end of step s - 1).
-  constexpr bool SCALED = EPI == EPI_FERMI || EPI == EPI_FERMI_XY;
+  constexpr bool SCALED = EPI == EPI_FERMI || EPI == EPI_FERMI_XY || EPI == EPI_XSTORE;
   __shared__ double Ss[SCALED ? 3 : 1][BK];
   d2 ra[AP], rb[BP];
   double sreg = 0.0;
@@ -244,7 +247,7 @@ __device__ __forceinline__ void f64_tile(const GemmItem& it, const int n, const 
   //   m = m0 + wm*(BM/WAVES_M) + i*16 + lr + 4r,  n = n0 + wn*(BN/WAVES_N) + j*16 + lc.
   const int mw = m0 + wm * (BM / Cfg::WAVES_M) + lr;
   const int nw = n0 + wn * (BN / Cfg::WAVES_N) + lc;
-  if constexpr (EPI == EPI_STORE || EPI == EPI_ACCUM) {
+  if constexpr (EPI == EPI_STORE || EPI == EPI_ACCUM || EPI == EPI_XSTORE) {
 #pragma unroll
     for (int i = 0; i < WTM; ++i)
 #pragma unroll
@@ -312,6 +315,57 @@ __global__ __launch_bounds__(Cfg::THREADS, Cfg::MIN_BLOCKS) void gemm_f64(const 
   const int z = logical / args.ntiles;
   f64_tile<EPI, Cfg>(args.item[z], args.n, args.k_half, args.two_halves != 0,
                      args.tiles[logical - z * args.ntiles], args.beta);
+}
+
+// Second pass of the FP64 forward transform when it runs as a full-tile product
+// (EPI_XSTORE): out holds A = C^T U~ G; for each 32 x 32 block pair (I <= J),
+// X = (A + A^T) / 2, Y = F o X off the diagonal and Y_ii = -w_i X_ii (X_ii to
+// xdiag), written in place over A: block (I, J) element by element by the
+// thread that read it, block (J, I) through LDS after the whole of it was read.
+// blockIdx.x = pair (row-major over the upper triangle), blockIdx.y = item;
+// 256 threads.
+constexpr int SYM64_B = 32;
+__global__ __launch_bounds__(256) void fermi_symmetrize_f64(const GemmArgs args) {
+  if (args.stop != nullptr && *args.stop != 0) return;
+  const GemmItem& it = args.item[blockIdx.y];
+  const int n = args.n, nblk = n / SYM64_B;
+  int I = 0, rem = blockIdx.x;
+  while (rem >= nblk - I) {
+    rem -= nblk - I;
+    ++I;
+  }
+  const int J = I + rem;
+  __shared__ double At[SYM64_B][SYM64_B + 1];  // block (J, I) of A, then the mirror of Y
+  const int tx = threadIdx.x % SYM64_B, ty = threadIdx.x / SYM64_B;
+  constexpr int RS = 256 / SYM64_B;
+  double* const Y = it.out;
+  for (int r = ty; r < SYM64_B; r += RS) At[r][tx] = Y[(size_t)(J * SYM64_B + r) * n + I * SYM64_B + tx];
+  __syncthreads();
+  const double beta = args.beta;
+  const int c = J * SYM64_B + tx;
+  const double en = it.eps[c], fn = it.f[c], fcn = it.fc[c];
+  double yv[SYM64_B / RS];
+#pragma unroll
+  for (int q = 0; q < SYM64_B / RS; ++q) {
+    const int r = ty + q * RS, m = I * SYM64_B + r;
+    double* const o = Y + (size_t)m * n + c;
+    const double x = 0.5 * (*o + At[tx][r]);
+    double y;
+    if (m == c) {
+      it.xdiag[m] = x;
+      y = -it.w[m] * x;
+    } else {
+      y = fermi_divided_difference(it.eps[m], it.f[m], it.fc[m], en, fn, fcn, beta) * x;
+    }
+    *o = y;
+    yv[q] = y;
+  }
+  if (I == J) return;  // a diagonal block is symmetric by construction
+  __syncthreads();     // every read of At is done
+#pragma unroll
+  for (int q = 0; q < SYM64_B / RS; ++q) At[tx][ty + q * RS] = yv[q];
+  __syncthreads();
+  for (int r = ty; r < SYM64_B; r += RS) Y[(size_t)(J * SYM64_B + r) * n + I * SYM64_B + tx] = At[r][tx];
 }
 
 // Configurations. The default (128 x 128 tile, 8 waves of 32 x 64, two

@@ -585,13 +585,13 @@ __global__ __launch_bounds__(Cfg::THREADS, Cfg::MIN_BLOCKS) void gemm_mixed(cons
                        args.tiles[logical - z * args.ntiles], args.beta);
 }
 
-// Second pass of the single-system split forward transform. For each 64 x 64
+// Second pass of the single-system split forward transform. For each 32 x 32
 // block pair (I <= J) of each item: X = (A + A^T) / 2 / s_prod in FP64 from the
 // FP32 product A, Y = F o X off the diagonal and Y_ii = -w_i X_ii (X_ii to
 // xdiag), split at the Y scale and written to block (I, J) and, through LDS,
 // to its mirror (J, I). blockIdx.x = pair (row-major over the upper triangle),
 // blockIdx.y = item; 256 threads.
-constexpr int SYM_B = 64;
+constexpr int SYM_B = 32;  // 4 elements per thread (64 x 64, 16 each: 24 instead of 14 us at Nb = 1152)
 __global__ __launch_bounds__(256) void fermi_symmetrize(const MixedArgs args) {
   if (args.stop != nullptr && *args.stop != 0) return;
   const MixedItem& it = args.item[blockIdx.y];

@@ -79,7 +79,7 @@ static_assert(kk::PAD % SmallF64::BM == 0 && SPLIT_PAD % SmallMx::BM == 0, "smal
 // to KSTEP, which every K stage divides. The reverse pass keeps the full np.
 constexpr int KSTEP = 32;
 static_assert(KSTEP % kk::FwdCfg::BK == 0 && KSTEP % kk::BackCfg::BK == 0 && KSTEP % kk::StoreCfg::BK == 0 &&
-                  KSTEP % SmallF64::BK == 0 && KSTEP % kk::MFwdCfg::BK == 0 && KSTEP % kk::MBackCfg::BK == 0 &&
+                  KSTEP % SmallF64::BK == 0 && KSTEP % kk::MBackCfg::BK == 0 &&
                   KSTEP % SmallMx::BK == 0 && kk::PAD % KSTEP == 0,
               "KSTEP must be a multiple of every K stage and divide the padding");
 constexpr int MAX_CHUNK = kk::MAX_GEMM_BATCH / 2;  // directions per GEMM launch
@@ -114,13 +114,11 @@ struct kk_handle_s {
   int precision = KK_FP64;
   double* GT[2] = {nullptr, nullptr};
   _Float16 *Ch[2] = {nullptr, nullptr}, *Cl[2] = {nullptr, nullptr};
-  _Float16 *CTh[2] = {nullptr, nullptr}, *CTl[2] = {nullptr, nullptr};
   _Float16 *GTh[2] = {nullptr, nullptr}, *GTl[2] = {nullptr, nullptr};
   double* mconst = nullptr;  // per spin: s_C, s_G, max column norms of C and G
   int2* mtiles_full = nullptr;  // both split transforms of a single system: full tiles
   int n_mfull = 0;
-  // (U~ C)^T split per direction; (U~ G)^T only for a batch's two-half forward transform
-  _Float16 *uct_h = nullptr, *uct_l = nullptr, *ugt_h = nullptr, *ugt_l = nullptr;
+  _Float16 *uct_h = nullptr, *uct_l = nullptr;  // (U~ C)^T split per direction
   float* x32 = nullptr;  // split forward: the product C^T U~ G per direction, FP32
   _Float16 *yh = nullptr, *yl = nullptr;
   double* msc = nullptr;
@@ -177,7 +175,7 @@ struct kk_handle_s {
     ws_owned.clear();
     chunk_cap = 0;
     u = Y = xdiag = part = nullptr;
-    uct_h = uct_l = ugt_h = ugt_l = yh = yl = nullptr;
+    uct_h = uct_l = yh = yl = nullptr;
     x32 = nullptr;
     msc = nullptr;
   }
@@ -345,7 +343,7 @@ kk_status ensure_workspace(kk_handle h, int chunk) {
   if (h->precision == KK_FP64) {
     if ((st = dalloc_t(h, &h->Y, items * np * np, true))) return st;
   } else {
-    for (_Float16** q : {&h->uct_h, &h->uct_l, &h->ugt_h, &h->ugt_l, &h->yh, &h->yl})
+    for (_Float16** q : {&h->uct_h, &h->uct_l, &h->yh, &h->yl})
       if ((st = dalloc_t(h, q, items * np * np, true))) return st;
     if ((st = dalloc_t(h, &h->x32, items * np * np, true))) return st;
     if ((st = dalloc_t(h, &h->msc, items * 8, true))) return st;
@@ -358,9 +356,9 @@ kk_status ensure_workspace(kk_handle h, int chunk) {
 }
 
 int max_chunk(kk_handle h) {
-  // FP64: one Y per spin; split path: six FP16 matrices and one FP32 per spin
+  // FP64: one Y per spin; split path: four FP16 matrices and one FP32 per spin
   const size_t per_dir = (size_t)2 * h->np * h->np *
-                         (h->precision == KK_FP64 ? sizeof(double) : 6 * sizeof(_Float16) + sizeof(float));
+                         (h->precision == KK_FP64 ? sizeof(double) : 4 * sizeof(_Float16) + sizeof(float));
   size_t c = WORKSPACE_BUDGET / std::max<size_t>(per_dir, 1);
   return (int)std::max<size_t>(1, std::min<size_t>(c, MAX_CHUNK));
 }
@@ -461,10 +459,10 @@ kk_status response_chunk_mixed(kk_handle h, int batch, const double* v, double* 
   }
   // forward: A = C^T U~ G over full tiles (At = (U~ C)^T, Bt = G^T), X = (A + A^T) / 2
   kk::MixedArgs fa{};
-  fa.n = np; fa.k_half = h->kc; fa.two_halves = 0; fa.ntiles = h->n_mfull; fa.nitems = 2 * batch;
+  fa.n = np; fa.k = h->kc; fa.ntiles = h->n_mfull; fa.nitems = 2 * batch;
   fa.tiles = h->mtiles_full; fa.stop = stop; fa.beta = h->beta;
   kk::MixedArgs ba{};
-  ba.n = np; ba.k_half = h->kc; ba.two_halves = 0; ba.ntiles = h->n_mfull; ba.nitems = 2 * batch;
+  ba.n = np; ba.k = h->kc; ba.ntiles = h->n_mfull; ba.nitems = 2 * batch;
   ba.tiles = h->mtiles_full; ba.stop = stop; ba.beta = h->beta;
   for (int z = 0; z < 2 * batch; ++z) {
     const int s = z & 1;
@@ -568,7 +566,7 @@ kk_status allocate_prepared(kk_handle h) {
     if ((st = dalloc_t(h, &h->mscratch, (size_t)4 * np))) return st;
     for (int s = 0; s < 2; ++s) {
       if ((st = dalloc_t(h, &h->GT[s], np2))) return st;
-      for (_Float16** q : {&h->Ch[s], &h->Cl[s], &h->CTh[s], &h->CTl[s], &h->GTh[s], &h->GTl[s]})
+      for (_Float16** q : {&h->Ch[s], &h->Cl[s], &h->GTh[s], &h->GTl[s]})
         if ((st = dalloc_t(h, q, np2))) return st;
     }
     mfull = tile_order(np, kk::MBackCfg::BM, kk::MBackCfg::BN, false);
@@ -600,7 +598,6 @@ kk_status prepare_mixed(kk_handle h) {
     kk::const_scales<<<1, 1024, 0, h->stream>>>(rmax, rn2, rmax + np, rn2 + np, np, h->mconst + 4 * s);
     LAUNCH_CHECK("const_scales");
     kk::split_matrix<<<pg, pb, 0, h->stream>>>(h->C[s], np, 0, h->mconst + 4 * s, h->Ch[s], h->Cl[s]);
-    kk::split_matrix<<<pg, pb, 0, h->stream>>>(h->CT[s], np, 0, h->mconst + 4 * s, h->CTh[s], h->CTl[s]);
     kk::split_matrix<<<pg, pb, 0, h->stream>>>(h->GT[s], np, 0, h->mconst + 4 * s + 1, h->GTh[s], h->GTl[s]);
     LAUNCH_CHECK("split_matrix");
   }
@@ -1245,6 +1242,8 @@ struct kk_batch_s {
   kk::SysDesc* d_sys = nullptr;
   void* d_items_fwd = nullptr;   // BatchItemF64 or BatchItemMixed, 2 per system
   void* d_items_back = nullptr;
+  int* d_pair_off = nullptr;     // split form: first symmetrizing block pair of each forward item
+  int sym_pairs = 0;             // split form: block pairs over all forward items
   TileClass cls[2];              // 0: large tiles, 1: small tiles
   const double** d_delta = nullptr;
   double** d_out = nullptr;
@@ -1279,6 +1278,8 @@ struct kk_batch_s {
     owned.clear();
     for (auto& c : cls) c = TileClass{};
     d_sys = nullptr; d_items_fwd = d_items_back = nullptr; d_delta = nullptr; d_out = nullptr; d_info = nullptr;
+    d_pair_off = nullptr;
+    sym_pairs = 0;
     prepared = false;
     tuned = false;
   }
@@ -1306,7 +1307,7 @@ kk_status build_tile_lists(kk_batch b, int small_np_max) {
     const int np = b->np_of[i];
     const int c = np <= small_np_max ? 1 : 0;
     int bm, bn, sbm, sbn;
-    if (mixed) { bm = kk::MFwdCfg::BM; bn = kk::MFwdCfg::BN; sbm = SmallMx::BM; sbn = SmallMx::BN; }
+    if (mixed) { bm = kk::MBackCfg::BM; bn = kk::MBackCfg::BN; sbm = SmallMx::BM; sbn = SmallMx::BN; }
     else { bm = kk::FwdCfg::BM; bn = kk::FwdCfg::BN; sbm = SmallF64::BM; sbn = SmallF64::BN; }
     const int tbm = c ? sbm : bm, tbn = c ? sbn : bn;
     for (int s = 0; s < 2; ++s) {
@@ -1378,13 +1379,18 @@ kk_status enqueue_update(kk_batch b, int m) {
       kk::b_mixed_scales<<<dim3(2, ns), 1024, 0, b->stream>>>(b->d_sys);
       LAUNCH_CHECK("b_mixed_scales");
       const size_t np2 = (size_t)b->max_np * b->max_np;
-      const int blocks = (int)std::min<size_t>((np2 + 255) / 256, 2048);
-      kk::b_split<<<dim3(blocks, 4, ns), 256, 0, b->stream>>>(b->d_sys);
+      const int blocks = (int)std::min<size_t>((np2 / 8 + 255) / 256, 2048);
+      kk::b_split<<<dim3(blocks, 2, ns), 256, 0, b->stream>>>(b->d_sys);
       LAUNCH_CHECK("b_split");
       auto* fi = static_cast<const kk::BatchItemMixed*>(b->d_items_fwd);
       auto* bi = static_cast<const kk::BatchItemMixed*>(b->d_items_back);
-      if ((st = launch_persistent<kk::EPI_FERMI, kk::MFwdCfg>(b, fi, b->cls[0].fwd, b->cls[0].nfwd, 1))) return st;
-      if ((st = launch_persistent<kk::EPI_FERMI, SmallMx>(b, fi, b->cls[1].fwd, b->cls[1].nfwd, 1))) return st;
+      // forward: full-tile products A = C^T U~ G (the back-transform's tile lists), then
+      // one symmetrizing pass over all items
+      if ((st = launch_persistent<kk::EPI_STORE, kk::MBackCfg>(b, fi, b->cls[0].back, b->cls[0].nback, 0)))
+        return st;
+      if ((st = launch_persistent<kk::EPI_STORE, SmallMx>(b, fi, b->cls[1].back, b->cls[1].nback, 0))) return st;
+      kk::b_symmetrize<<<b->sym_pairs, 256, 0, b->stream>>>(fi, b->d_pair_off, 2 * ns);
+      LAUNCH_CHECK("b_symmetrize");
       if ((st = launch_persistent<kk::EPI_MULLIKEN, kk::MBackCfg>(b, bi, b->cls[0].back, b->cls[0].nback, 0)))
         return st;
       if ((st = launch_persistent<kk::EPI_MULLIKEN, SmallMx>(b, bi, b->cls[1].back, b->cls[1].nback, 0)))
@@ -1550,16 +1556,15 @@ kk_status kk_batch_prepare(kk_batch b, int n_systems, const int* n_atoms, const 
     d.w0 = h->w[0]; d.w1 = h->w[1]; d.wsum = h->wsum; d.t = h->t;
     d.V = h->V; d.Ft = h->Ft; d.ftilde = h->ftilde; d.q1 = h->q1; d.kst = h->kst;
     d.msc = h->msc; d.mconst = h->mconst;
-    d.CT0 = h->CT[0]; d.CT1 = h->CT[1]; d.GT0 = h->GT[0]; d.GT1 = h->GT[1];
-    d.uct_h = h->uct_h; d.uct_l = h->uct_l; d.ugt_h = h->ugt_h; d.ugt_l = h->ugt_l;
+    d.CT0 = h->CT[0]; d.CT1 = h->CT[1];
+    d.uct_h = h->uct_h; d.uct_l = h->uct_l;
     for (int s = 0; s < 2; ++s) {
       if (mixed) {
         kk::BatchItemMixed fi{}, bi{};
         fi.n = bi.n = h->np; fi.k = bi.k = h->kc; fi.beta = bi.beta = h->beta; fi.stop = bi.stop = &h->kst->stop;
         kk::MixedItem& F = fi.g;
         F.a0h = h->uct_h + s * np2; F.a0l = h->uct_l + s * np2; F.b0h = h->GTh[s]; F.b0l = h->GTl[s];
-        F.a1h = h->ugt_h + s * np2; F.a1l = h->ugt_l + s * np2; F.b1h = h->CTh[s]; F.b1l = h->CTl[s];
-        F.yh = h->yh + s * np2; F.yl = h->yl + s * np2;
+        F.yh = h->yh + s * np2; F.yl = h->yl + s * np2; F.x32 = h->x32 + s * np2;
         F.eps = h->eps[s]; F.f = h->f[s]; F.fc = h->fc[s]; F.w = h->w[s];
         F.xdiag = h->xdiag + s * np; F.sc = h->msc + s * 8;
         kk::MixedItem& B = bi.g;
@@ -1583,7 +1588,17 @@ kk_status kk_batch_prepare(kk_batch b, int n_systems, const int* n_atoms, const 
   }
   if ((st = balloc(b, &b->d_sys, n_systems))) return st;
   HIP_OR_FAIL(hipMemcpyAsync(b->d_sys, sd.data(), sizeof(kk::SysDesc) * n_systems, hipMemcpyHostToDevice, b->stream));
+  std::vector<int> pair_off;
   if (mixed) {
+    pair_off.assign(1, 0);
+    for (const kk::BatchItemMixed& it : mxf) {
+      const int nblk = it.n / kk::SYM_B;
+      pair_off.push_back(pair_off.back() + nblk * (nblk + 1) / 2);
+    }
+    b->sym_pairs = pair_off.back();
+    if ((st = balloc(b, &b->d_pair_off, pair_off.size()))) return st;
+    HIP_OR_FAIL(hipMemcpyAsync(b->d_pair_off, pair_off.data(), sizeof(int) * pair_off.size(), hipMemcpyHostToDevice,
+                               b->stream));
     kk::BatchItemMixed *f, *bk;
     if ((st = balloc(b, &f, mxf.size()))) return st;
     if ((st = balloc(b, &bk, mxb.size()))) return st;

@@ -31,8 +31,8 @@ struct SysDesc {
   // split-precision path
   double* msc;             // 2 x 8
   const double* mconst;    // 8
-  const double *CT0, *CT1, *GT0, *GT1;
-  _Float16 *uct_h, *uct_l, *ugt_h, *ugt_l;  // 2 x np^2 each
+  const double *CT0, *CT1;
+  _Float16 *uct_h, *uct_l;  // 2 x np^2 each
 };
 
 struct BatchItemF64 {
@@ -90,16 +90,29 @@ __global__ void b_mixed_scales(const SysDesc* __restrict__ d) {
   mixed_scales_dev(s.u, s.np, s.mconst, s.beta, s.msc, &s.kst->stop, blockIdx.x);
 }
 
-// blockIdx.z = system, blockIdx.y = (spin, operand): 0,1 = (U~ C)^T, 2,3 = (U~ G)^T
+// blockIdx.z = system, blockIdx.y = spin: the split forward operand (U~ C)^T
 __global__ void b_split(const SysDesc* __restrict__ d) {
   const SysDesc& s = d[blockIdx.z];
-  const int spin = blockIdx.y & 1, which = blockIdx.y >> 1;
+  const int spin = blockIdx.y;
   const size_t np2 = (size_t)s.np * s.np;
-  const double* src = which ? (spin ? s.GT1 : s.GT0) : (spin ? s.CT1 : s.CT0);
-  _Float16* hi = (which ? s.ugt_h : s.uct_h) + spin * np2;
-  _Float16* lo = (which ? s.ugt_l : s.uct_l) + spin * np2;
-  split_scaled_columns_dev(src, s.np, s.u + (size_t)spin * s.np, s.msc + spin * 8 + 3 + which, hi, lo,
-                           &s.kst->stop, blockIdx.x, gridDim.x);
+  split_scaled_columns_dev(spin ? s.CT1 : s.CT0, s.np, s.u + (size_t)spin * s.np, s.msc + spin * 8 + 3,
+                           s.uct_h + spin * np2, s.uct_l + spin * np2, &s.kst->stop, blockIdx.x, gridDim.x);
+}
+
+// The split forward's symmetrizing pass over every item of the batch: blockIdx.x
+// runs over the block pairs of all items, item z owning [pair_off[z], pair_off[z + 1]).
+__global__ __launch_bounds__(256) void b_symmetrize(const BatchItemMixed* __restrict__ items,
+                                                    const int* __restrict__ pair_off, int nitems) {
+  const int g = blockIdx.x;
+  int lo = 0, hi = nitems;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) / 2;
+    if (pair_off[mid] <= g) lo = mid;
+    else hi = mid;
+  }
+  const BatchItemMixed& it = items[lo];
+  if (*it.stop) return;
+  fermi_symmetrize_dev(it.g, it.n, it.beta, g - pair_off[lo]);
 }
 
 __global__ void b_combine(const SysDesc* __restrict__ d) {
@@ -148,18 +161,19 @@ __global__ __launch_bounds__(Cfg::THREADS) __attribute__((amdgpu_waves_per_eu(Cf
   }
 }
 
-// Held to MIN_BLOCKS workgroups per CU as well (it then spills a few values outside the K
-// loop): with the staged mirror write of the forward epilogue, left to itself the compiler
-// gives the forward form ~190 registers, one workgroup per CU, and the batch runs 4 % slower.
+// Held to MIN_BLOCKS workgroups per CU as well (the two-half forward form with a staged
+// mirror epilogue, which this kernel ran before the full-tile forward, took ~190 registers
+// and one workgroup per CU when left to itself, 4 % slower). The split products have one K
+// half, so the last argument (kept for one launcher of both precisions) must be 0.
 template <int EPI, class Cfg>
 __global__ __launch_bounds__(Cfg::THREADS) __attribute__((amdgpu_waves_per_eu((Cfg::MIN_BLOCKS * Cfg::THREADS / 64 + 3) / 4)))
 void b_gemm_mixed(const BatchItemMixed* __restrict__ items, const int4* __restrict__ tiles, int ntiles,
-                  int two_halves) {
+                  int /*two_halves*/) {
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int4 tl = tiles[t];
     const BatchItemMixed& it = items[tl.x];
     if (*it.stop) continue;
-    mixed_tile<EPI, Cfg>(it.g, it.n, it.k, two_halves != 0, make_int2(tl.y, tl.z), it.beta);
+    mixed_tile<EPI, Cfg>(it.g, it.n, it.k, make_int2(tl.y, tl.z));
   }
 }
 

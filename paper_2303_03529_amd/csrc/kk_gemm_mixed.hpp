@@ -12,13 +12,10 @@
 //
 // Layout (NT form): out[m][n] = sum_k At[m][k] * Bt[n][k] with At, Bt stored
 // row-major with k contiguous, so each lane's 8 FP16 MFMA operands are one
-// 16-byte LDS read. The forward transform of a single system is a full-tile
-// product A = C^T U~ G (At = (U~ C)^T, Bt = G^T, EPI_STORE: A in FP32) followed
-// by fermi_symmetrize, which forms X = (A + A^T) / 2 in FP64 and Y = F o X.
-// The batched forward instead runs upper tiles over two K halves, At = (U~ C)^T,
-// Bt = G^T then At = (U~ G)^T, Bt = C^T (one scale), giving C^T U~ G + G^T U~ C
-// (EPI_FERMI). The back-transform uses At = C (row i, k = l) and Bt = Y
-// (symmetric, so row k of Y is column k).
+// 16-byte LDS read. The forward transform is a full-tile product A = C^T U~ G
+// (At = (U~ C)^T, Bt = G^T; EPI_STORE: A in FP32) followed by fermi_symmetrize,
+// which forms X = (A + A^T) / 2 in FP64 and Y = F o X. The back-transform uses
+// At = C (row i, k = l) and Bt = Y (symmetric, so row k of Y is column k).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -31,8 +28,7 @@ typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef float f16x __attribute__((ext_vector_type(16)));
 
 struct MixedItem {
-  const _Float16 *a0h, *a0l, *b0h, *b0l;  // first K half (At, Bt), [n][n], k contiguous
-  const _Float16 *a1h, *a1l, *b1h, *b1l;  // second K half (forward transform only)
+  const _Float16 *a0h, *a0l, *b0h, *b0l;  // At, Bt as hi/lo pairs, [n][n], k contiguous
   _Float16 *yh, *yl;                      // forward: Y split at scale sc[1]
   const double* g;                        // back: G (FP64)
   const double *eps, *f, *fc, *w;         // forward: spectrum
@@ -43,7 +39,7 @@ struct MixedItem {
 };
 
 struct MixedArgs {
-  int n, k_half, two_halves, ntiles, nitems;
+  int n, k, ntiles, nitems;  // padded size, contraction length (<= n), tiles per item, items
   const int2* tiles;
   const int* stop;
   double beta;
@@ -64,10 +60,7 @@ struct MixedCfg {
   static constexpr bool DL = false;
   static constexpr int KP = BK + 8;                 // padded LDS row (halves)
   static_assert((KP / 8) % 2 == 1, "LDS row stride must be an odd number of 16-byte slots");
-  static constexpr int YP = BN + 8;                 // padded row of a Y staging tile (halves)
-  static constexpr int MAIN_BYTES = 2 * 2 * (BM + BN) * KP * 2;
-  static constexpr int EPI_BYTES = 2 * BM * YP * 2;  // the staged mirror tile, hi and lo
-  static constexpr int SMEM_BYTES = MAIN_BYTES > EPI_BYTES ? MAIN_BYTES : EPI_BYTES;
+  static constexpr int SMEM_BYTES = 2 * 2 * (BM + BN) * KP * 2;  // [buf][hi/lo] of A and B
   static_assert(64 % (BK / 8) == 0 && 16 % (BK / 8) == 0, "piece mapping");
   static_assert(BM % (32 * WAVES_M) == 0 && BN % (32 * WAVES_N) == 0, "wave tiling");
   static_assert(BK % 16 == 0, "BK");
@@ -87,17 +80,14 @@ struct MixedDlCfg {
   static constexpr int STAGE_BLK = 2 * (A_BLK + B_BLK);        // hi and lo of A and B
   static constexpr int PER_WAVE = STAGE_BLK / WAVES;
   static constexpr int STAGE_BYTES = STAGE_BLK * 1024;
-  static constexpr int YP = BN + 8;
-  static constexpr int EPI_BYTES = 2 * BM * YP * 2;
-  static constexpr int SMEM_BYTES = NS * STAGE_BYTES > EPI_BYTES ? NS * STAGE_BYTES : EPI_BYTES;
+  static constexpr int SMEM_BYTES = NS * STAGE_BYTES;
   static_assert(STAGE_BLK % WAVES == 0, "DMA blocks per wave");
   static_assert(BM % (32 * WAVES_M) == 0 && BN % (32 * WAVES_N) == 0, "wave tiling");
   static_assert(NS >= 3 && NS <= 5, "ring depth");
   static_assert(NS * STAGE_BYTES <= 160 * 1024, "LDS");
 };
 
-// LDS of one split-precision tile, shared by its main loop and its epilogue (one
-// static buffer per configuration): the K-stage buffers, then the Y staging tiles.
+// LDS of one split-precision tile's main loop (one static buffer per configuration).
 template <class Cfg>
 __device__ __forceinline__ unsigned char* mixed_smem() {
   __shared__ __attribute__((aligned(1024))) unsigned char smem[Cfg::SMEM_BYTES];
@@ -113,9 +103,8 @@ __device__ __forceinline__ void split_store(double v, _Float16* hi, _Float16* lo
 // Main loop with register staging: global -> registers -> LDS (double buffer).
 // Leaves the FP32 sums in acc; ends with a barrier.
 template <class Cfg>
-__device__ __forceinline__ void mixed_mainloop_lds(const MixedItem& it, const int n, const int k_half,
-                                                   const bool two_halves, const int m0, const int n0,
-                                                   f16x (&acc)[Cfg::WTM][Cfg::WTN]) {
+__device__ __forceinline__ void mixed_mainloop_lds(const MixedItem& it, const int n, const int kc, const int m0,
+                                                   const int n0, f16x (&acc)[Cfg::WTM][Cfg::WTN]) {
   constexpr int BM = Cfg::BM, BN = Cfg::BN, BK = Cfg::BK, KP = Cfg::KP;
   constexpr int WTM = Cfg::WTM, WTN = Cfg::WTN;
   constexpr int CPR = BK / 8;  // 16-byte chunks per row per matrix
@@ -125,7 +114,7 @@ __device__ __forceinline__ void mixed_mainloop_lds(const MixedItem& it, const in
   auto Bs = reinterpret_cast<_Float16 (*)[2][BN][KP]>(mixed_smem<Cfg>() + 2 * 2 * BM * KP * 2);
 
   const int tid = threadIdx.x;
-  const int nk = (two_halves ? 2 * k_half : k_half) / BK;
+  const int nk = kc / BK;
   const int wave = tid >> 6, lane = tid & 63;
   const int wm = wave / Cfg::WAVES_N, wn = wave % Cfg::WAVES_N;
   const int l32 = lane & 31, lh = lane >> 5;
@@ -179,12 +168,8 @@ __device__ __forceinline__ void mixed_mainloop_lds(const MixedItem& it, const in
 
 #define KK_MLOAD(kt)                                                                         \
   {                                                                                          \
-    int k0 = (kt) * BK;                                                                      \
-    const _Float16 *ah = it.a0h, *al = it.a0l, *bh = it.b0h, *bl = it.b0l;                   \
-    if (two_halves && k0 >= k_half) {                                                        \
-      ah = it.a1h; al = it.a1l; bh = it.b1h; bl = it.b1l; k0 -= k_half;                      \
-    }                                                                                        \
-    ah += k0; al += k0; bh += k0; bl += k0;                                                  \
+    const int k0 = (kt) * BK;                                                                \
+    const _Float16 *ah = it.a0h + k0, *al = it.a0l + k0, *bh = it.b0h + k0, *bl = it.b0l + k0; \
     _Pragma("unroll") for (int p = 0; p < APM; ++p) {                                        \
       sah[p] = *reinterpret_cast<const h8*>(ah + aoff[p]);                                   \
       sal[p] = *reinterpret_cast<const h8*>(al + aoff[p]);                                   \
@@ -274,7 +259,7 @@ __device__ __forceinline__ void mixed_mainloop_lds(const MixedItem& it, const in
 
 // Epilogue of a split-precision tile (both forms of the main loop).
 template <int EPI, class Cfg>
-__device__ __forceinline__ void mixed_epilogue(const MixedItem& it, const int n, const int2 tile, const double beta_arg,
+__device__ __forceinline__ void mixed_epilogue(const MixedItem& it, const int n, const int2 tile,
                                                const f16x (&acc)[Cfg::WTM][Cfg::WTN]) {
   constexpr int BM = Cfg::BM, BN = Cfg::BN;
   constexpr int WTM = Cfg::WTM, WTN = Cfg::WTN;
@@ -297,63 +282,6 @@ __device__ __forceinline__ void mixed_epilogue(const MixedItem& it, const int n,
 #pragma unroll
         for (int j = 0; j < WTN; ++j) it.x32[(size_t)m * n + nw + j * 32] = acc[i][j][r];
       }
-  } else if constexpr (EPI == EPI_FERMI) {
-    // Y is written twice: the tile itself straight from the accumulator layout (32
-    // consecutive columns per row and instruction, full cache lines per wave), and its
-    // mirror through LDS (hi and lo tiles, transposed there) with 16-byte row stores.
-    // Written straight from the accumulators the mirror's 2-byte stores land in 32 rows
-    // per instruction: 4 % of the forward, and 9 % of the back-transform, which then
-    // reads the partly written lines. A diagonal tile stages its full symmetric block.
-    static_assert(BM == BN, "the staged mirror needs square tiles");
-    constexpr int YP = Cfg::YP, CH = BN / 8;
-    const double beta = beta_arg, sy = it.sc[1];
-    const bool diag = tile.x == tile.y;
-    _Float16* const Th = reinterpret_cast<_Float16*>(mixed_smem<Cfg>());  // [BN][YP]: mirror, hi
-    _Float16* const Tl = Th + BN * YP;                                    // [BN][YP]: mirror, lo
-    double en[WTN], fn[WTN], fcn[WTN];
-#pragma unroll
-    for (int j = 0; j < WTN; ++j) {
-      const int c = nw + j * 32;
-      en[j] = it.eps[c]; fn[j] = it.f[c]; fcn[j] = it.fc[c];
-    }
-#pragma unroll
-    for (int i = 0; i < WTM; ++i)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int ml = mw - m0 + i * 32 + 8 * (r / 4) + (r % 4), m = m0 + ml;
-        const double em = it.eps[m], fm = it.f[m], fcm = it.fc[m];
-#pragma unroll
-        for (int j = 0; j < WTN; ++j) {
-          const int cl = nw - n0 + j * 32, c = n0 + cl;
-          if (m > c) continue;  // below the diagonal: the mirror of another lane's element
-          const double x = 0.5 * inv * (double)acc[i][j][r];
-          double y;
-          if (m == c) {
-            it.xdiag[m] = x;
-            y = -it.w[m] * x * sy;
-          } else {
-            y = fermi_divided_difference(em, fm, fcm, en[j], fn[j], fcn[j], beta) * x * sy;
-          }
-          const _Float16 h = (_Float16)(float)y, l = (_Float16)(float)(y - (double)h);
-          it.yh[(size_t)m * n + c] = h;
-          it.yl[(size_t)m * n + c] = l;
-          Th[cl * YP + ml] = h;
-          Tl[cl * YP + ml] = l;
-          if (diag) {
-            Th[ml * YP + cl] = h;
-            Tl[ml * YP + cl] = l;
-          }
-        }
-      }
-    __syncthreads();
-    // staged rows: row cl of the mirror is Y row n0 + cl from column m0 on
-    for (int q = threadIdx.x; q < BN * CH; q += Cfg::THREADS) {
-      const int row = q / CH, ch = q % CH;
-      const size_t o = (size_t)(n0 + row) * n + m0 + ch * 8;
-      *reinterpret_cast<h8*>(it.yh + o) = *reinterpret_cast<const h8*>(Th + row * YP + ch * 8);
-      *reinterpret_cast<h8*>(it.yl + o) = *reinterpret_cast<const h8*>(Tl + row * YP + ch * 8);
-    }
-    __syncthreads();
   } else {  // EPI_MULLIKEN
     const int p = tile.y * Cfg::WAVES_N + wn;
 #pragma unroll
@@ -402,9 +330,8 @@ __device__ __forceinline__ void wait_vmcnt() {
 // this wave's reads of the previous stage (lgkmcnt 0), so its slot can be refilled.
 // Leaves the FP32 sums in acc; ends with a barrier.
 template <class Cfg>
-__device__ __forceinline__ void mixed_mainloop_dl(const MixedItem& it, const int n, const int k_half,
-                                                       const bool two_halves, const int m0, const int n0,
-                                                       f16x (&acc)[Cfg::WTM][Cfg::WTN]) {
+__device__ __forceinline__ void mixed_mainloop_dl(const MixedItem& it, const int n, const int kc, const int m0,
+                                                  const int n0, f16x (&acc)[Cfg::WTM][Cfg::WTN]) {
   constexpr int BM = Cfg::BM, BN = Cfg::BN, BK = 32, NS = Cfg::NS, PW = Cfg::PER_WAVE;
   constexpr int WTM = Cfg::WTM, WTN = Cfg::WTN;
   constexpr int A_BLK = Cfg::A_BLK, B_BLK = Cfg::B_BLK, SB = Cfg::STAGE_BYTES;
@@ -412,7 +339,7 @@ __device__ __forceinline__ void mixed_mainloop_dl(const MixedItem& it, const int
   unsigned char* const ring = mixed_smem<Cfg>();
 
   const int tid = threadIdx.x;
-  const int nk = (two_halves ? 2 * k_half : k_half) / BK;
+  const int nk = kc / BK;
   const int wave = tid >> 6, lane = tid & 63;
   const int wm = wave / Cfg::WAVES_N, wn = wave % Cfg::WAVES_N;
   const int l32 = lane & 31, lh = lane >> 5;
@@ -454,13 +381,9 @@ __device__ __forceinline__ void mixed_mainloop_dl(const MixedItem& it, const int
   // operand pointers read from the kernel arguments once (scalar loads inside the loop
   // would force lgkmcnt(0) waits and serialize the pipelined LDS reads)
   const _Float16 *const p0[4] = {it.a0h, it.a0l, it.b0h, it.b0l};
-  const _Float16 *const p1[4] = {it.a1h, it.a1l, it.b1h, it.b1l};
   auto issue = [&](int kt) __attribute__((always_inline)) {
-    int k0 = kt * BK;
+    const int k0 = kt * BK;
     const _Float16 *ah = p0[0], *al = p0[1], *bh = p0[2], *bl = p0[3];
-    if (two_halves && k0 >= k_half) {
-      ah = p1[0]; al = p1[1]; bh = p1[2]; bl = p1[3]; k0 -= k_half;
-    }
     unsigned char* slot = ring + (kt % NS) * SB;
 #pragma unroll
     for (int j = 0; j < PW; ++j) {
@@ -562,17 +485,17 @@ __device__ __forceinline__ void mixed_mainloop_dl(const MixedItem& it, const int
   }
 }
 
-// One output tile (see f64_tile); ends with a barrier.
+// One output tile over a contraction of length kc (see f64_tile); ends with a barrier.
 template <int EPI, class Cfg>
-__device__ __forceinline__ void mixed_tile(const MixedItem& it, const int n, const int k_half, const bool two_halves,
-                                           const int2 tile, const double beta_arg) {
+__device__ __forceinline__ void mixed_tile(const MixedItem& it, const int n, const int kc, const int2 tile) {
+  static_assert(EPI == EPI_STORE || EPI == EPI_MULLIKEN, "split-precision epilogues");
   const int m0 = tile.x * Cfg::BM, n0 = tile.y * Cfg::BN;
   f16x acc[Cfg::WTM][Cfg::WTN];
   if constexpr (Cfg::DL)
-    mixed_mainloop_dl<Cfg>(it, n, k_half, two_halves, m0, n0, acc);
+    mixed_mainloop_dl<Cfg>(it, n, kc, m0, n0, acc);
   else
-    mixed_mainloop_lds<Cfg>(it, n, k_half, two_halves, m0, n0, acc);
-  mixed_epilogue<EPI, Cfg>(it, n, tile, beta_arg, acc);
+    mixed_mainloop_lds<Cfg>(it, n, kc, m0, n0, acc);
+  mixed_epilogue<EPI, Cfg>(it, n, tile, acc);
 }
 
 template <int EPI, class Cfg>
@@ -581,34 +504,31 @@ __global__ __launch_bounds__(Cfg::THREADS, Cfg::MIN_BLOCKS) void gemm_mixed(cons
   const int total = args.ntiles * args.nitems;
   const int logical = xcd_remap(blockIdx.x, total);
   const int z = logical / args.ntiles;
-  mixed_tile<EPI, Cfg>(args.item[z], args.n, args.k_half, args.two_halves != 0,
-                       args.tiles[logical - z * args.ntiles], args.beta);
+  mixed_tile<EPI, Cfg>(args.item[z], args.n, args.k, args.tiles[logical - z * args.ntiles]);
 }
 
-// Second pass of the single-system split forward transform. For each 32 x 32
-// block pair (I <= J) of each item: X = (A + A^T) / 2 / s_prod in FP64 from the
-// FP32 product A, Y = F o X off the diagonal and Y_ii = -w_i X_ii (X_ii to
-// xdiag), split at the Y scale and written to block (I, J) and, through LDS,
-// to its mirror (J, I). blockIdx.x = pair (row-major over the upper triangle),
-// blockIdx.y = item; 256 threads.
+// Second pass of the split forward transform in its full-tile form. For one
+// 32 x 32 block pair (I <= J) of an item: X = (A + A^T) / 2 / s_prod in FP64 from
+// the FP32 product A, Y = F o X off the diagonal and Y_ii = -w_i X_ii (X_ii to
+// xdiag), split at the Y scale and written to block (I, J) and, through LDS, to
+// its mirror (J, I). pair indexes the upper triangle row-major; 256 threads.
 constexpr int SYM_B = 32;  // 4 elements per thread (64 x 64, 16 each: 24 instead of 14 us at Nb = 1152)
-__global__ __launch_bounds__(256) void fermi_symmetrize(const MixedArgs args) {
-  if (args.stop != nullptr && *args.stop != 0) return;
-  const MixedItem& it = args.item[blockIdx.y];
-  const int n = args.n, nblk = n / SYM_B;
-  int I = 0, rem = blockIdx.x;
+__device__ __forceinline__ void fermi_symmetrize_dev(const MixedItem& it, const int n, const double beta,
+                                                     const int pair) {
+  const int nblk = n / SYM_B;
+  int I = 0, rem = pair;
   while (rem >= nblk - I) {
     rem -= nblk - I;
     ++I;
   }
   const int J = I + rem;
-  __shared__ float At[SYM_B][SYM_B + 1];               // block (J, I) of A
+  __shared__ float At[SYM_B][SYM_B + 1];                           // block (J, I) of A
   __shared__ _Float16 Th[SYM_B][SYM_B + 2], Tl[SYM_B][SYM_B + 2];  // Y block (I, J), transposed
   const int tx = threadIdx.x % SYM_B, ty = threadIdx.x / SYM_B;
   constexpr int RS = 256 / SYM_B;
   for (int r = ty; r < SYM_B; r += RS) At[r][tx] = it.x32[(size_t)(J * SYM_B + r) * n + I * SYM_B + tx];
   __syncthreads();
-  const double inv = it.sc[0], sy = it.sc[1], beta = args.beta;
+  const double inv = it.sc[0], sy = it.sc[1];
   const int c = J * SYM_B + tx;
   const double en = it.eps[c], fn = it.f[c], fcn = it.fc[c];
   for (int r = ty; r < SYM_B; r += RS) {
@@ -636,6 +556,12 @@ __global__ __launch_bounds__(256) void fermi_symmetrize(const MixedArgs args) {
   }
 }
 
+// Single system: blockIdx.x = block pair, blockIdx.y = item.
+__global__ __launch_bounds__(256) void fermi_symmetrize(const MixedArgs args) {
+  if (args.stop != nullptr && *args.stop != 0) return;
+  fermi_symmetrize_dev(args.item[blockIdx.y], args.n, args.beta, blockIdx.x);
+}
+
 using MCfg128x128 = MixedCfg<128, 128, 32, 2, 2, 2>;
 using MCfg128x128f8 = MixedCfg<128, 128, 32, 2, 2, 2, 8>;
 using MCfg128x128k64 = MixedCfg<128, 128, 64, 2, 2, 1>;
@@ -661,23 +587,19 @@ using MDl256x128n3 = MixedDlCfg<256, 128, 4, 2, 3, 8>;
 // shorter K stages (16), longer ones (64, one workgroup per CU) and wider tiles (128 x 256,
 // 256 x 128) by 5-25 %; the direct-to-LDS shapes above come within 2 % of it. Counters: no
 // LDS bank conflicts, LDS busy ~27 % and MFMA busy ~40 % of cycles, while the chip clock drops
-// to ~1.7 GHz during these kernels (2.4 GHz during the FP64 ones).
-#ifndef KK_MFWD_CFG
-#define KK_MFWD_CFG MCfg128x128w8f8
-#endif
+// to ~1.7 GHz during these kernels (2.4 GHz during the FP64 ones). The configuration serves
+// both products (the forward's A = C^T U~ G and the back-transform); -DKK_MBACK_CFG=...
+// selects another for re-tuning.
 #ifndef KK_MBACK_CFG
 #define KK_MBACK_CFG MCfg128x128w8f8
 #endif
-using MFwdCfg = KK_MFWD_CFG;
 using MBackCfg = KK_MBACK_CFG;
 
-// Padded dimension of the split-precision path: the largest tile side of the two
-// transforms (128 for the default), so that both tile the padded matrices exactly.
-constexpr int pad_max(int a, int b) { return a > b ? a : b; }
-constexpr int MIXED_PAD = pad_max(pad_max(MFwdCfg::BM, MFwdCfg::BN), pad_max(MBackCfg::BM, MBackCfg::BN));
-static_assert(MIXED_PAD % MFwdCfg::BM == 0 && MIXED_PAD % MFwdCfg::BN == 0 && MIXED_PAD % MBackCfg::BM == 0 &&
-                  MIXED_PAD % MBackCfg::BN == 0,
-              "both transforms' tiles must divide the padding");
+// Padded dimension of the split-precision path: the larger tile side of the product
+// configuration (128 for the default), so that its tiles cover the padded matrices exactly.
+constexpr int MIXED_PAD = MBackCfg::BM > MBackCfg::BN ? MBackCfg::BM : MBackCfg::BN;
+static_assert(MIXED_PAD % MBackCfg::BM == 0 && MIXED_PAD % MBackCfg::BN == 0 && MIXED_PAD % SYM_B == 0,
+              "the product tiles and the symmetrizing blocks must divide the padding");
 
 // ---------------------------------------------------------------------------
 // Split helpers

@@ -1223,10 +1223,9 @@ namespace {
 // Tile configurations a batch chooses between: large systems use the default
 // transforms, systems with np <= small_np_max use 64 x 64 tiles.
 
-struct TileClass {
-  int4* fwd = nullptr;
-  int4* back = nullptr;
-  int nfwd = 0, nback = 0;
+struct TileClass {  // full-tile list of one tile class, shared by both transforms
+  int4* tiles = nullptr;
+  int n = 0;
 };
 
 }  // namespace
@@ -1242,8 +1241,8 @@ struct kk_batch_s {
   kk::SysDesc* d_sys = nullptr;
   void* d_items_fwd = nullptr;   // BatchItemF64 or BatchItemMixed, 2 per system
   void* d_items_back = nullptr;
-  int* d_pair_off = nullptr;     // split form: first symmetrizing block pair of each forward item
-  int sym_pairs = 0;             // split form: block pairs over all forward items
+  int* d_pair_off = nullptr;     // first symmetrizing block pair of each forward item
+  int sym_pairs = 0;             // block pairs over all forward items
   TileClass cls[2];              // 0: large tiles, 1: small tiles
   const double** d_delta = nullptr;
   double** d_out = nullptr;
@@ -1297,23 +1296,23 @@ kk_status balloc(kk_batch b, T** p, size_t count) {
 
 // Build the tile lists of both classes for a threshold: items (2 per system)
 // sorted by decreasing np so the persistent workgroups start with the costly tiles.
+// Both transforms walk the full tiles (the forward as the product A = C^T U~ G).
 kk_status build_tile_lists(kk_batch b, int small_np_max) {
   const bool mixed = b->precision == KK_MIXED_F16;
   std::vector<int> order(b->ns);
   for (int i = 0; i < b->ns; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return b->np_of[x] > b->np_of[y]; });
-  std::vector<int4> lists[2][2];
+  std::vector<int4> lists[2];
   for (int i : order) {
     const int np = b->np_of[i];
     const int c = np <= small_np_max ? 1 : 0;
     int bm, bn, sbm, sbn;
     if (mixed) { bm = kk::MBackCfg::BM; bn = kk::MBackCfg::BN; sbm = SmallMx::BM; sbn = SmallMx::BN; }
-    else { bm = kk::FwdCfg::BM; bn = kk::FwdCfg::BN; sbm = SmallF64::BM; sbn = SmallF64::BN; }
+    else { bm = kk::BackCfg::BM; bn = kk::BackCfg::BN; sbm = SmallF64::BM; sbn = SmallF64::BN; }
     const int tbm = c ? sbm : bm, tbn = c ? sbn : bn;
     for (int s = 0; s < 2; ++s) {
       const int item = 2 * i + s;
-      for (const int2& t : tile_order(np, tbm, tbn, true)) lists[c][0].push_back(make_int4(item, t.x, t.y, 0));
-      for (const int2& t : tile_order(np, tbm, tbn, false)) lists[c][1].push_back(make_int4(item, t.x, t.y, 0));
+      for (const int2& t : tile_order(np, tbm, tbn, false)) lists[c].push_back(make_int4(item, t.x, t.y, 0));
     }
   }
   for (int i = 0; i < b->ns; ++i)
@@ -1322,25 +1321,19 @@ kk_status build_tile_lists(kk_batch b, int small_np_max) {
                              b->stream));
   for (int c = 0; c < 2; ++c) {
     TileClass& tc = b->cls[c];
-    tc.nfwd = (int)lists[c][0].size();
-    tc.nback = (int)lists[c][1].size();
-    if (!tc.fwd) {  // capacity for every tile of either class: the larger per-system count (small tiles)
-      size_t capf = 0, capb = 0;
+    tc.n = (int)lists[c].size();
+    if (!tc.tiles) {  // capacity for every system in either class: the larger per-system count (small tiles)
+      size_t cap = 0;
       for (int i = 0; i < b->ns; ++i) {
         const int np = b->np_of[i];
         const int sb = mixed ? SmallMx::BM : SmallF64::BM;
-        capf += 2 * (size_t)(np / sb) * (np / sb + 1) / 2 + 2 * (np / sb);
-        capb += 2 * (size_t)(np / sb) * (np / sb);
+        cap += 2 * (size_t)(np / sb) * (np / sb);
       }
       kk_status st;
-      if ((st = balloc(b, &tc.fwd, capf + 1))) return st;
-      if ((st = balloc(b, &tc.back, capb + 1))) return st;
+      if ((st = balloc(b, &tc.tiles, cap + 1))) return st;
     }
-    if (tc.nfwd)
-      HIP_OR_FAIL(hipMemcpyAsync(tc.fwd, lists[c][0].data(), sizeof(int4) * tc.nfwd, hipMemcpyHostToDevice, b->stream));
-    if (tc.nback)
-      HIP_OR_FAIL(hipMemcpyAsync(tc.back, lists[c][1].data(), sizeof(int4) * tc.nback, hipMemcpyHostToDevice,
-                                 b->stream));
+    if (tc.n)
+      HIP_OR_FAIL(hipMemcpyAsync(tc.tiles, lists[c].data(), sizeof(int4) * tc.n, hipMemcpyHostToDevice, b->stream));
   }
   HIP_OR_FAIL(hipStreamSynchronize(b->stream));
   return KK_OK;
@@ -1386,23 +1379,27 @@ kk_status enqueue_update(kk_batch b, int m) {
       auto* bi = static_cast<const kk::BatchItemMixed*>(b->d_items_back);
       // forward: full-tile products A = C^T U~ G (the back-transform's tile lists), then
       // one symmetrizing pass over all items
-      if ((st = launch_persistent<kk::EPI_STORE, kk::MBackCfg>(b, fi, b->cls[0].back, b->cls[0].nback, 0)))
+      if ((st = launch_persistent<kk::EPI_STORE, kk::MBackCfg>(b, fi, b->cls[0].tiles, b->cls[0].n, 0)))
         return st;
-      if ((st = launch_persistent<kk::EPI_STORE, SmallMx>(b, fi, b->cls[1].back, b->cls[1].nback, 0))) return st;
+      if ((st = launch_persistent<kk::EPI_STORE, SmallMx>(b, fi, b->cls[1].tiles, b->cls[1].n, 0))) return st;
       kk::b_symmetrize<<<b->sym_pairs, 256, 0, b->stream>>>(fi, b->d_pair_off, 2 * ns);
       LAUNCH_CHECK("b_symmetrize");
-      if ((st = launch_persistent<kk::EPI_MULLIKEN, kk::MBackCfg>(b, bi, b->cls[0].back, b->cls[0].nback, 0)))
+      if ((st = launch_persistent<kk::EPI_MULLIKEN, kk::MBackCfg>(b, bi, b->cls[0].tiles, b->cls[0].n, 0)))
         return st;
-      if ((st = launch_persistent<kk::EPI_MULLIKEN, SmallMx>(b, bi, b->cls[1].back, b->cls[1].nback, 0)))
+      if ((st = launch_persistent<kk::EPI_MULLIKEN, SmallMx>(b, bi, b->cls[1].tiles, b->cls[1].n, 0)))
         return st;
     } else {
       auto* fi = static_cast<const kk::BatchItemF64*>(b->d_items_fwd);
       auto* bi = static_cast<const kk::BatchItemF64*>(b->d_items_back);
-      if ((st = launch_persistent<kk::EPI_FERMI, kk::FwdCfg>(b, fi, b->cls[0].fwd, b->cls[0].nfwd, 1))) return st;
-      if ((st = launch_persistent<kk::EPI_FERMI, SmallF64>(b, fi, b->cls[1].fwd, b->cls[1].nfwd, 1))) return st;
-      if ((st = launch_persistent<kk::EPI_MULLIKEN, kk::BackCfg>(b, bi, b->cls[0].back, b->cls[0].nback, 0)))
+      // forward: full-tile products A = C^T U~ G into Y, then one in-place symmetrizing pass
+      if ((st = launch_persistent<kk::EPI_XSTORE, kk::BackCfg>(b, fi, b->cls[0].tiles, b->cls[0].n, 0)))
         return st;
-      if ((st = launch_persistent<kk::EPI_MULLIKEN, SmallF64>(b, bi, b->cls[1].back, b->cls[1].nback, 0)))
+      if ((st = launch_persistent<kk::EPI_XSTORE, SmallF64>(b, fi, b->cls[1].tiles, b->cls[1].n, 0))) return st;
+      kk::b_symmetrize_f64<<<b->sym_pairs, 256, 0, b->stream>>>(fi, b->d_pair_off, 2 * ns);
+      LAUNCH_CHECK("b_symmetrize_f64");
+      if ((st = launch_persistent<kk::EPI_MULLIKEN, kk::BackCfg>(b, bi, b->cls[0].tiles, b->cls[0].n, 0)))
+        return st;
+      if ((st = launch_persistent<kk::EPI_MULLIKEN, SmallF64>(b, bi, b->cls[1].tiles, b->cls[1].n, 0)))
         return st;
     }
     kk::b_combine<<<dim3((b->maxN + kk::COMBINE_ATOMS - 1) / kk::COMBINE_ATOMS, ns), kk::COMBINE_THREADS, 0,
@@ -1588,17 +1585,18 @@ kk_status kk_batch_prepare(kk_batch b, int n_systems, const int* n_atoms, const 
   }
   if ((st = balloc(b, &b->d_sys, n_systems))) return st;
   HIP_OR_FAIL(hipMemcpyAsync(b->d_sys, sd.data(), sizeof(kk::SysDesc) * n_systems, hipMemcpyHostToDevice, b->stream));
-  std::vector<int> pair_off;
-  if (mixed) {
-    pair_off.assign(1, 0);
-    for (const kk::BatchItemMixed& it : mxf) {
-      const int nblk = it.n / kk::SYM_B;
+  // symmetrizing block pairs of the forward items (2 per system, spin fastest)
+  std::vector<int> pair_off(1, 0);
+  for (int i = 0; i < n_systems; ++i)
+    for (int s = 0; s < 2; ++s) {
+      const int nblk = b->sys[i]->np / kk::SYM_B;
       pair_off.push_back(pair_off.back() + nblk * (nblk + 1) / 2);
     }
-    b->sym_pairs = pair_off.back();
-    if ((st = balloc(b, &b->d_pair_off, pair_off.size()))) return st;
-    HIP_OR_FAIL(hipMemcpyAsync(b->d_pair_off, pair_off.data(), sizeof(int) * pair_off.size(), hipMemcpyHostToDevice,
-                               b->stream));
+  b->sym_pairs = pair_off.back();
+  if ((st = balloc(b, &b->d_pair_off, pair_off.size()))) return st;
+  HIP_OR_FAIL(hipMemcpyAsync(b->d_pair_off, pair_off.data(), sizeof(int) * pair_off.size(), hipMemcpyHostToDevice,
+                             b->stream));
+  if (mixed) {
     kk::BatchItemMixed *f, *bk;
     if ((st = balloc(b, &f, mxf.size()))) return st;
     if ((st = balloc(b, &bk, mxb.size()))) return st;

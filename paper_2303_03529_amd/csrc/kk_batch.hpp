@@ -99,20 +99,33 @@ __global__ void b_split(const SysDesc* __restrict__ d) {
                            s.uct_h + spin * np2, s.uct_l + spin * np2, &s.kst->stop, blockIdx.x, gridDim.x);
 }
 
-// The split forward's symmetrizing pass over every item of the batch: blockIdx.x
-// runs over the block pairs of all items, item z owning [pair_off[z], pair_off[z + 1]).
-__global__ __launch_bounds__(256) void b_symmetrize(const BatchItemMixed* __restrict__ items,
-                                                    const int* __restrict__ pair_off, int nitems) {
-  const int g = blockIdx.x;
+// The forward's symmetrizing pass over every item of the batch: blockIdx.x runs over
+// the block pairs of all items, item z owning [pair_off[z], pair_off[z + 1]).
+__device__ __forceinline__ int pair_item(const int* __restrict__ pair_off, int nitems, int g) {
   int lo = 0, hi = nitems;
   while (hi - lo > 1) {
     const int mid = (lo + hi) / 2;
     if (pair_off[mid] <= g) lo = mid;
     else hi = mid;
   }
-  const BatchItemMixed& it = items[lo];
+  return lo;
+}
+static_assert(SYM_B == SYM64_B, "one block-pair list serves both precisions");
+
+__global__ __launch_bounds__(256) void b_symmetrize(const BatchItemMixed* __restrict__ items,
+                                                    const int* __restrict__ pair_off, int nitems) {
+  const int z = pair_item(pair_off, nitems, blockIdx.x);
+  const BatchItemMixed& it = items[z];
   if (*it.stop) return;
-  fermi_symmetrize_dev(it.g, it.n, it.beta, g - pair_off[lo]);
+  fermi_symmetrize_dev(it.g, it.n, it.beta, blockIdx.x - pair_off[z]);
+}
+
+__global__ __launch_bounds__(256) void b_symmetrize_f64(const BatchItemF64* __restrict__ items,
+                                                        const int* __restrict__ pair_off, int nitems) {
+  const int z = pair_item(pair_off, nitems, blockIdx.x);
+  const BatchItemF64& it = items[z];
+  if (*it.stop) return;
+  fermi_symmetrize_f64_dev(it.g, it.n, it.beta, blockIdx.x - pair_off[z]);
 }
 
 __global__ void b_combine(const SysDesc* __restrict__ d) {
@@ -146,9 +159,10 @@ __global__ void b_info(const SysDesc* __restrict__ d, int ns, KrylovState* __res
 // Persistent transforms: each workgroup takes tiles t = blockIdx.x, + gridDim.x, ...
 // from a list sorted by decreasing cost; a tile of a system whose Krylov
 // expansion has stopped is skipped (uniformly for the workgroup).
-// The FP64 forward form would take ~164 registers per lane and so hold one workgroup
-// per CU; capped to MIN_BLOCKS workgroups per CU it spills a few values in the
-// epilogue only, and the batch runs 13 % faster.
+// Held to MIN_BLOCKS workgroups per CU: the two-half forward form with the Fermi
+// epilogue, which this kernel ran before the full-tile forward, took ~164 registers per
+// lane and one workgroup per CU when left to itself (13 % slower); the full-tile
+// product and the back-transform fit without spilling.
 template <int EPI, class Cfg>
 __global__ __launch_bounds__(Cfg::THREADS) __attribute__((amdgpu_waves_per_eu(Cfg::WAVES_PER_EU))) void b_gemm_f64(const BatchItemF64* __restrict__ items,
                                                                           const int4* __restrict__ tiles,

@@ -322,14 +322,12 @@ __global__ __launch_bounds__(Cfg::THREADS, Cfg::MIN_BLOCKS) void gemm_f64(const 
 // X = (A + A^T) / 2, Y = F o X off the diagonal and Y_ii = -w_i X_ii (X_ii to
 // xdiag), written in place over A: block (I, J) element by element by the
 // thread that read it, block (J, I) through LDS after the whole of it was read.
-// blockIdx.x = pair (row-major over the upper triangle), blockIdx.y = item;
-// 256 threads.
+// pair indexes the upper triangle row-major; 256 threads.
 constexpr int SYM64_B = 32;
-__global__ __launch_bounds__(256) void fermi_symmetrize_f64(const GemmArgs args) {
-  if (args.stop != nullptr && *args.stop != 0) return;
-  const GemmItem& it = args.item[blockIdx.y];
-  const int n = args.n, nblk = n / SYM64_B;
-  int I = 0, rem = blockIdx.x;
+__device__ __forceinline__ void fermi_symmetrize_f64_dev(const GemmItem& it, const int n, const double beta,
+                                                         const int pair) {
+  const int nblk = n / SYM64_B;
+  int I = 0, rem = pair;
   while (rem >= nblk - I) {
     rem -= nblk - I;
     ++I;
@@ -341,7 +339,6 @@ __global__ __launch_bounds__(256) void fermi_symmetrize_f64(const GemmArgs args)
   double* const Y = it.out;
   for (int r = ty; r < SYM64_B; r += RS) At[r][tx] = Y[(size_t)(J * SYM64_B + r) * n + I * SYM64_B + tx];
   __syncthreads();
-  const double beta = args.beta;
   const int c = J * SYM64_B + tx;
   const double en = it.eps[c], fn = it.f[c], fcn = it.fc[c];
   double yv[SYM64_B / RS];
@@ -366,6 +363,12 @@ __global__ __launch_bounds__(256) void fermi_symmetrize_f64(const GemmArgs args)
   for (int q = 0; q < SYM64_B / RS; ++q) At[tx][ty + q * RS] = yv[q];
   __syncthreads();
   for (int r = ty; r < SYM64_B; r += RS) Y[(size_t)(J * SYM64_B + r) * n + I * SYM64_B + tx] = At[r][tx];
+}
+
+// Single system: blockIdx.x = block pair, blockIdx.y = item.
+__global__ __launch_bounds__(256) void fermi_symmetrize_f64(const GemmArgs args) {
+  if (args.stop != nullptr && *args.stop != 0) return;
+  fermi_symmetrize_f64_dev(args.item[blockIdx.y], args.n, args.beta, blockIdx.x);
 }
 
 // Configurations. The default (128 x 128 tile, 8 waves of 32 x 64, two

@@ -278,13 +278,14 @@ const char *kk_last_error(void);
 
 /*
  * Kernel timing for measurement. When enabled, the library records HIP events
- * on its stream around each launch of its two dense transform kernels
- * (kernel_id 0: forward eigenbasis transform with the Fermi Hadamard product;
- * 1: back-transform with the Mulliken projection; 2: the forward transform of
- * the reverse pass, which also writes X; 3: the reverse pass's accumulation of
- * Y0_b Xa + Y0_a Xb). kk_profile_read
- * synchronizes and returns the summed milliseconds and launch count since the
- * last reset. At most 8192 launches are recorded between resets.
+ * on its stream around each dense transform step of a single-system handle
+ * (kernel_id 0: the forward eigenbasis transform with the Fermi Hadamard
+ * product, one kernel or the full-tile product followed by its symmetrizing
+ * pass; 1: back-transform with the Mulliken projection; 2: the forward
+ * transform of the reverse pass, which also writes X; 3: the reverse pass's
+ * accumulation of Y0_b Xa + Y0_a Xb). kk_profile_read synchronizes and returns
+ * the summed milliseconds and step count since the last reset. At most 8192
+ * steps are recorded between resets.
  */
 kk_status kk_profile_enable(kk_handle h, int enable);
 kk_status kk_profile_reset(kk_handle h);

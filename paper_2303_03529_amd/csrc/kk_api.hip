@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <type_traits>
 #include <cstdarg>
 #include <cstdio>
@@ -1585,12 +1586,16 @@ kk_status kk_batch_prepare(kk_batch b, int n_systems, const int* n_atoms, const 
   }
   if ((st = balloc(b, &b->d_sys, n_systems))) return st;
   HIP_OR_FAIL(hipMemcpyAsync(b->d_sys, sd.data(), sizeof(kk::SysDesc) * n_systems, hipMemcpyHostToDevice, b->stream));
-  // symmetrizing block pairs of the forward items (2 per system, spin fastest)
+  // symmetrizing block pairs of the forward items (2 per system, spin fastest); the
+  // offsets index one launch's blocks, so their total must fit an int
   std::vector<int> pair_off(1, 0);
+  long long total_pairs = 0;
   for (int i = 0; i < n_systems; ++i)
     for (int s = 0; s < 2; ++s) {
-      const int nblk = b->sys[i]->np / kk::SYM_B;
-      pair_off.push_back(pair_off.back() + nblk * (nblk + 1) / 2);
+      const long long nblk = b->sys[i]->np / kk::SYM_B;
+      total_pairs += nblk * (nblk + 1) / 2;
+      if (total_pairs > INT_MAX) return fail(KK_EINVAL, "kk_batch_prepare: too many block pairs in one batch");
+      pair_off.push_back((int)total_pairs);
     }
   b->sym_pairs = pair_off.back();
   if ((st = balloc(b, &b->d_pair_off, pair_off.size()))) return st;

@@ -266,10 +266,15 @@ bool full_forward(int n_upper, int n_full, int slots) {
   return full_rounds < 2 * upper_rounds;
 }
 
+// Tile table order: groups of GROUP tile rows, each group walked column by column, so that
+// the workgroups of one XCD (a contiguous range of the table, see xcd_remap) share a few A
+// panels and sweep the B panels together. At Nb = 9216 on MI355X groups of 2-6 rows ran the
+// split transforms 2-3 % faster than 8 (16 and 32: 2-9 % slower; 1: slower); the FP64 ones
+// were indifferent between 2 and 8.
 std::vector<int2> tile_order(int np, int bm, int bn, bool upper) {
   std::vector<int2> v;
   const int TM = np / bm, TN = np / bn;
-  const int GROUP = 8;
+  const int GROUP = 4;
   for (int g0 = 0; g0 < TM; g0 += GROUP)
     for (int tn = 0; tn < TN; ++tn)
       for (int tm = g0; tm < std::min(TM, g0 + GROUP); ++tm)

@@ -244,9 +244,6 @@ kk_status zero(kk_handle h, double* p, size_t n) {
   return KK_OK;
 }
 
-// Tile orders. Full grid: groups of 8 tile rows, sweep columns inside a group,
-// so the tiles resident on one XCD share A and B panels. Upper: the same
-// order restricted to tiles holding at least one element with m <= n.
 int cu_count() {
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -270,7 +267,8 @@ bool full_forward(int n_upper, int n_full, int slots) {
 // the workgroups of one XCD (a contiguous range of the table, see xcd_remap) share a few A
 // panels and sweep the B panels together. At Nb = 9216 on MI355X groups of 2-6 rows ran the
 // split transforms 2-3 % faster than 8 (16 and 32: 2-9 % slower; 1: slower); the FP64 ones
-// were indifferent between 2 and 8.
+// were indifferent between 2 and 8. upper: the same order restricted to the tiles holding at
+// least one element with m <= n.
 std::vector<int2> tile_order(int np, int bm, int bn, bool upper) {
   std::vector<int2> v;
   const int TM = np / bm, TN = np / bn;

@@ -418,11 +418,13 @@ kk_status response_chunk(kk_handle h, int batch, const double* v, double* q1, co
   return KK_OK;
 }
 
-kk_status launch_mixed(kk_handle h, int epi, kk::MixedArgs& a) {
+// Split-precision transform step: the forward (full-tile product into the FP32
+// workspace, then the symmetrizing pass that writes the split Y) or the back-transform.
+kk_status launch_mixed(kk_handle h, bool forward, kk::MixedArgs& a) {
   const int grid = a.ntiles * a.nitems;
   if (grid <= 0) return KK_OK;
   if (a.nitems > kk::MAX_GEMM_BATCH) return fail(KK_EINVAL, "internal: too many GEMM items");
-  if (epi == kk::EPI_FERMI) {  // forward: full-tile product, then symmetrize and split Y
+  if (forward) {
     ProfileScope ps(h, 0);
     kk::gemm_mixed<kk::EPI_STORE, kk::MBackCfg><<<grid, kk::MBackCfg::THREADS, 0, h->stream>>>(a);
     LAUNCH_CHECK("gemm_mixed");
@@ -484,8 +486,8 @@ kk_status response_chunk_mixed(kk_handle h, int batch, const double* v, double* 
     bi.sc = h->msc + z * 8 + 2;
   }
   kk_status st;
-  if ((st = launch_mixed(h, kk::EPI_FERMI, fa))) return st;
-  if ((st = launch_mixed(h, kk::EPI_MULLIKEN, ba))) return st;
+  if ((st = launch_mixed(h, true, fa))) return st;
+  if ((st = launch_mixed(h, false, ba))) return st;
   {
     dim3 grid((N + kk::COMBINE_ATOMS - 1) / kk::COMBINE_ATOMS, batch);
     kk::combine<<<grid, kk::COMBINE_THREADS, 0, h->stream>>>(h->xdiag, h->part, h->nparts, h->w[0], h->w[1],

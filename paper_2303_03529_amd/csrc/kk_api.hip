@@ -59,10 +59,14 @@ kk_status fail(kk_status st, const char* fmt, ...) {
 
 // A split-precision handle also runs FP64 GEMMs on its padded size (the
 // setup products and the FP64 reverse sweep), so its padding is a multiple of
-// the tile sides of both kernel families.
-constexpr int SPLIT_PAD = kk::MIXED_PAD > kk::PAD ? kk::MIXED_PAD : kk::PAD;
-static_assert(SPLIT_PAD % kk::MIXED_PAD == 0 && SPLIT_PAD % kk::PAD == 0,
+// the tile sides of both kernel families. Handles with Nb above SPLIT_LARGE_NB,
+// and every system of a split batch, take the large product configuration.
+constexpr int SPLIT_PAD_LARGE = kk::MIXED_PAD_LARGE > kk::PAD ? kk::MIXED_PAD_LARGE : kk::PAD;
+constexpr int SPLIT_PAD_SMALL = kk::MIXED_PAD_SMALL > kk::PAD ? kk::MIXED_PAD_SMALL : kk::PAD;
+static_assert(SPLIT_PAD_LARGE % kk::MIXED_PAD_LARGE == 0 && SPLIT_PAD_LARGE % kk::PAD == 0 &&
+                  SPLIT_PAD_SMALL % kk::MIXED_PAD_SMALL == 0 && SPLIT_PAD_SMALL % kk::PAD == 0,
               "split-precision padding must be a multiple of every tile side");
+constexpr int SPLIT_LARGE_NB = 2304;
 // Small systems fill the chip better with 64 x 64 tiles (a 128-atom system has
 // 45 upper 128 x 128 forward tiles per spin for 256 CUs). Up to this padded
 // size the FP64 response transforms (both) use them; the reverse pass and the
@@ -73,14 +77,14 @@ static_assert(SPLIT_PAD % kk::MIXED_PAD == 0 && SPLIT_PAD % kk::PAD == 0,
 constexpr int SMALL_NP_F64 = 2304;
 using SmallF64 = kk::Cfg64x64;
 using SmallMx = kk::MCfg64x64f8;
-static_assert(kk::PAD % SmallF64::BM == 0 && SPLIT_PAD % SmallMx::BM == 0, "small tiles must divide the padding");
+static_assert(kk::PAD % SmallF64::BM == 0 && SPLIT_PAD_LARGE % SmallMx::BM == 0, "small tiles must divide the padding");
 // Rows nb..np-1 of every operand a response transform or a setup product
 // contracts over are zero (the padded copies of S, Z, Q and the potentials are
 // zero there, hence C, G and Y too), so those contractions stop at nb rounded up
 // to KSTEP, which every K stage divides. The reverse pass keeps the full np.
 constexpr int KSTEP = 32;
 static_assert(KSTEP % kk::FwdCfg::BK == 0 && KSTEP % kk::BackCfg::BK == 0 && KSTEP % kk::StoreCfg::BK == 0 &&
-                  KSTEP % SmallF64::BK == 0 && KSTEP % kk::MBackCfg::BK == 0 &&
+                  KSTEP % SmallF64::BK == 0 && KSTEP % kk::MLargeCfg::BK == 0 && KSTEP % kk::MSmallCfg::BK == 0 &&
                   KSTEP % SmallMx::BK == 0 && kk::PAD % KSTEP == 0,
               "KSTEP must be a multiple of every K stage and divide the padding");
 constexpr int MAX_CHUNK = kk::MAX_GEMM_BATCH / 2;  // directions per GEMM launch
@@ -107,6 +111,7 @@ struct kk_handle_s {
   int n_upper = 0, n_full = 0, n_store = 0;
   // small systems: 64 x 64 tiles for the FP64 response transforms
   bool small_f64 = false;
+  bool mx_large = false;  // split products on MLargeCfg (else MSmallCfg)
   bool full_fwd = false;  // FP64 forward as full tiles + fermi_symmetrize_f64 (see full_forward)
   int2 *stiles_upper = nullptr, *stiles_full = nullptr;
   int n_supper = 0, n_sfull = 0;
@@ -426,14 +431,20 @@ kk_status launch_mixed(kk_handle h, bool forward, kk::MixedArgs& a) {
   if (a.nitems > kk::MAX_GEMM_BATCH) return fail(KK_EINVAL, "internal: too many GEMM items");
   if (forward) {
     ProfileScope ps(h, 0);
-    kk::gemm_mixed<kk::EPI_STORE, kk::MBackCfg><<<grid, kk::MBackCfg::THREADS, 0, h->stream>>>(a);
+    if (h->mx_large)
+      kk::gemm_mixed<kk::EPI_STORE, kk::MLargeCfg><<<grid, kk::MLargeCfg::THREADS, 0, h->stream>>>(a);
+    else
+      kk::gemm_mixed<kk::EPI_STORE, kk::MSmallCfg><<<grid, kk::MSmallCfg::THREADS, 0, h->stream>>>(a);
     LAUNCH_CHECK("gemm_mixed");
     const int nblk = a.n / kk::SYM_B;
     kk::fermi_symmetrize<<<dim3(nblk * (nblk + 1) / 2, a.nitems), 256, 0, h->stream>>>(a);
     LAUNCH_CHECK("fermi_symmetrize");
   } else {
     ProfileScope ps(h, 1);
-    kk::gemm_mixed<kk::EPI_MULLIKEN, kk::MBackCfg><<<grid, kk::MBackCfg::THREADS, 0, h->stream>>>(a);
+    if (h->mx_large)
+      kk::gemm_mixed<kk::EPI_MULLIKEN, kk::MLargeCfg><<<grid, kk::MLargeCfg::THREADS, 0, h->stream>>>(a);
+    else
+      kk::gemm_mixed<kk::EPI_MULLIKEN, kk::MSmallCfg><<<grid, kk::MSmallCfg::THREADS, 0, h->stream>>>(a);
   }
   LAUNCH_CHECK("gemm_mixed");
   return KK_OK;
@@ -575,7 +586,8 @@ kk_status allocate_prepared(kk_handle h) {
       for (_Float16** q : {&h->Ch[s], &h->Cl[s], &h->GTh[s], &h->GTl[s]})
         if ((st = dalloc_t(h, q, np2))) return st;
     }
-    mfull = tile_order(np, kk::MBackCfg::BM, kk::MBackCfg::BN, false);
+    mfull = h->mx_large ? tile_order(np, kk::MLargeCfg::BM, kk::MLargeCfg::BN, false)
+                        : tile_order(np, kk::MSmallCfg::BM, kk::MSmallCfg::BN, false);
     h->n_mfull = (int)mfull.size();
     if ((st = dalloc_t(h, &h->mtiles_full, mfull.size()))) return st;
     HIP_OR_FAIL(hipMemcpyAsync(h->mtiles_full, mfull.data(), sizeof(int2) * mfull.size(),
@@ -633,10 +645,16 @@ kk_status kk_destroy(kk_handle h) {
   return KK_OK;
 }
 
-kk_status kk_prepare(kk_handle h, int n_atoms, const int* atom_offsets, int n_basis, const double* S,
-                     const double* Z, const double* Q_up, const double* Q_dn, const double* eps_up,
-                     const double* eps_dn, const double* gamma, double W, double kT,
-                     double n_electrons, int precision) {
+}  // extern "C"
+
+namespace {
+
+// kk_prepare; split_large selects the large split product configuration whatever the size
+// (a batch's systems).
+kk_status prepare_impl(kk_handle h, int n_atoms, const int* atom_offsets, int n_basis, const double* S,
+                       const double* Z, const double* Q_up, const double* Q_dn, const double* eps_up,
+                       const double* eps_dn, const double* gamma, double W, double kT, double n_electrons,
+                       int precision, bool split_large) {
   if (!h) return fail(KK_EINVAL, "kk_prepare: handle is NULL");
   if (n_atoms < 1 || n_basis < 1) return fail(KK_EINVAL, "kk_prepare: n_atoms and n_basis must be >= 1");
   if (2 * n_atoms > 8 * 1024) return fail(KK_EINVAL, "kk_prepare: at most 4096 atoms are supported");
@@ -655,10 +673,12 @@ kk_status kk_prepare(kk_handle h, int n_atoms, const int* atom_offsets, int n_ba
       return fail(KK_EINVAL, "kk_prepare: atom_offsets must be strictly increasing (atom %d)", a);
 
   const bool mixed = precision == KK_MIXED_F16;
-  const int pad = mixed ? SPLIT_PAD : kk::PAD;
+  const bool mx_large = mixed && (split_large || n_basis > SPLIT_LARGE_NB);
+  const int pad = mixed ? (mx_large ? SPLIT_PAD_LARGE : SPLIT_PAD_SMALL) : kk::PAD;
   const int nb = n_basis, np = (nb + pad - 1) / pad * pad;
   // Re-preparing the same shape (an SCF or MD loop) reuses every buffer.
-  const bool reuse = h->prepared && h->natoms == n_atoms && h->nb == nb && h->precision == precision;
+  const bool reuse = h->prepared && h->natoms == n_atoms && h->nb == nb && h->np == np &&
+                     h->precision == precision && h->mx_large == mx_large;
   h->prepared = false;
   h->fwd_valid = false;
   kk_status st;
@@ -668,7 +688,9 @@ kk_status kk_prepare(kk_handle h, int n_atoms, const int* atom_offsets, int n_ba
     h->natoms = n_atoms; h->nb = nb; h->np = np;
     h->kc = (nb + KSTEP - 1) / KSTEP * KSTEP;
     h->small_f64 = !mixed && np <= SMALL_NP_F64;
-    h->nparts = mixed ? (np / kk::MBackCfg::BN) * kk::MBackCfg::WAVES_N
+    h->mx_large = mx_large;
+    h->nparts = mixed ? (mx_large ? (np / kk::MLargeCfg::BN) * kk::MLargeCfg::WAVES_N
+                                  : (np / kk::MSmallCfg::BN) * kk::MSmallCfg::WAVES_N)
                       : h->small_f64 ? (np / SmallF64::BN) * SmallF64::WAVES_N
                                      : (np / kk::BackCfg::BN) * kk::BackCfg::WAVES_N;
     if ((st = allocate_prepared(h))) return st;
@@ -728,6 +750,18 @@ kk_status kk_prepare(kk_handle h, int n_atoms, const int* atom_offsets, int n_ba
   ++h->prepare_gen;
   g_err.clear();
   return KK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+kk_status kk_prepare(kk_handle h, int n_atoms, const int* atom_offsets, int n_basis, const double* S,
+                     const double* Z, const double* Q_up, const double* Q_dn, const double* eps_up,
+                     const double* eps_dn, const double* gamma, double W, double kT,
+                     double n_electrons, int precision) {
+  return prepare_impl(h, n_atoms, atom_offsets, n_basis, S, Z, Q_up, Q_dn, eps_up, eps_dn, gamma, W, kT,
+                      n_electrons, precision, false);
 }
 
 kk_status kk_get_mu(kk_handle h, double* mu) {
@@ -1313,7 +1347,7 @@ kk_status build_tile_lists(kk_batch b, int small_np_max) {
     const int np = b->np_of[i];
     const int c = np <= small_np_max ? 1 : 0;
     int bm, bn, sbm, sbn;
-    if (mixed) { bm = kk::MBackCfg::BM; bn = kk::MBackCfg::BN; sbm = SmallMx::BM; sbn = SmallMx::BN; }
+    if (mixed) { bm = kk::MLargeCfg::BM; bn = kk::MLargeCfg::BN; sbm = SmallMx::BM; sbn = SmallMx::BN; }
     else { bm = kk::BackCfg::BM; bn = kk::BackCfg::BN; sbm = SmallF64::BM; sbn = SmallF64::BN; }
     const int tbm = c ? sbm : bm, tbn = c ? sbn : bn;
     for (int s = 0; s < 2; ++s) {
@@ -1385,12 +1419,12 @@ kk_status enqueue_update(kk_batch b, int m) {
       auto* bi = static_cast<const kk::BatchItemMixed*>(b->d_items_back);
       // forward: full-tile products A = C^T U~ G (the back-transform's tile lists), then
       // one symmetrizing pass over all items
-      if ((st = launch_persistent<kk::EPI_STORE, kk::MBackCfg>(b, fi, b->cls[0].tiles, b->cls[0].n, 0)))
+      if ((st = launch_persistent<kk::EPI_STORE, kk::MLargeCfg>(b, fi, b->cls[0].tiles, b->cls[0].n, 0)))
         return st;
       if ((st = launch_persistent<kk::EPI_STORE, SmallMx>(b, fi, b->cls[1].tiles, b->cls[1].n, 0))) return st;
       kk::b_symmetrize<<<b->sym_pairs, 256, 0, b->stream>>>(fi, b->d_pair_off, 2 * ns);
       LAUNCH_CHECK("b_symmetrize");
-      if ((st = launch_persistent<kk::EPI_MULLIKEN, kk::MBackCfg>(b, bi, b->cls[0].tiles, b->cls[0].n, 0)))
+      if ((st = launch_persistent<kk::EPI_MULLIKEN, kk::MLargeCfg>(b, bi, b->cls[0].tiles, b->cls[0].n, 0)))
         return st;
       if ((st = launch_persistent<kk::EPI_MULLIKEN, SmallMx>(b, bi, b->cls[1].tiles, b->cls[1].n, 0)))
         return st;
@@ -1522,8 +1556,8 @@ kk_status kk_batch_prepare(kk_batch b, int n_systems, const int* n_atoms, const 
     if ((st = kk_create(&h, b->stream))) return st;
     b->sys.push_back(h);
     const int nb = n_atoms[i] >= 1 && atom_offsets[i] ? atom_offsets[i][n_atoms[i]] : 0;
-    if ((st = kk_prepare(h, n_atoms[i], atom_offsets[i], nb, S[i], Z[i], Q_up[i], Q_dn[i], eps_up[i],
-                         eps_dn[i], gamma[i], W[i], kT[i], n_electrons[i], precision))) {
+    if ((st = prepare_impl(h, n_atoms[i], atom_offsets[i], nb, S[i], Z[i], Q_up[i], Q_dn[i], eps_up[i],
+                           eps_dn[i], gamma[i], W[i], kT[i], n_electrons[i], precision, true))) {
       char buf[600];
       snprintf(buf, sizeof buf, "system %d: %s", i, g_err.c_str());
       return fail(st, "kk_batch_prepare: %s", buf);
@@ -1545,7 +1579,7 @@ kk_status kk_batch_prepare(kk_batch b, int n_systems, const int* n_atoms, const 
     kk_handle h = b->sys[i];
     const size_t np = h->np, np2 = np * np;
     // Mulliken partial rows: one per wave column of a tile column, for either tile class
-    b->parts_large[i] = mixed ? (h->np / kk::MBackCfg::BN) * kk::MBackCfg::WAVES_N
+    b->parts_large[i] = mixed ? (h->np / kk::MLargeCfg::BN) * kk::MLargeCfg::WAVES_N
                               : (h->np / kk::BackCfg::BN) * kk::BackCfg::WAVES_N;
     b->parts_small[i] = mixed ? (h->np / SmallMx::BN) * SmallMx::WAVES_N
                               : (h->np / SmallF64::BN) * SmallF64::WAVES_N;

@@ -582,23 +582,35 @@ using MDl128x128n3 = MixedDlCfg<128, 128, 4, 2, 3, 8>;
 using MDl128x128n4 = MixedDlCfg<128, 128, 4, 2, 4, 8>;
 using MDl256x128n3 = MixedDlCfg<256, 128, 4, 2, 3, 8>;
 
-// Default: 128 x 128 tiles of 8 waves (32 x 64 each), K stage 32, flush every 8 stages, two
-// workgroups (16 waves) per CU. At Nb = 9216 it beat the 4-wave 64 x 64 shape by 2-3 %, and
-// shorter K stages (16), longer ones (64, one workgroup per CU) and wider tiles (128 x 256,
-// 256 x 128) by 5-25 %; the direct-to-LDS shapes above come within 2 % of it. Counters: no
-// LDS bank conflicts, LDS busy ~27 % and MFMA busy ~40 % of cycles, while the chip clock drops
-// to ~1.7 GHz during these kernels (2.4 GHz during the FP64 ones). The configuration serves
-// both products (the forward's A = C^T U~ G and the back-transform); -DKK_MBACK_CFG=...
-// selects another for re-tuning.
-#ifndef KK_MBACK_CFG
-#define KK_MBACK_CFG MCfg128x128w8f8
+// Product configurations (each serves both products of a handle: the forward's
+// A = C^T U~ G and the back-transform). Large: the direct-to-LDS 256 x 128 shape with a
+// 3-stage ring, one workgroup per CU; with the full-tile forward it ran 5-9 % faster than the
+// register-staged 128 x 128 shape at Nb = 3888-9216 on MI355X (1024 atoms: forward step 10.7
+// vs 11.3 ms, back 9.5 vs 9.9 ms) and the 64-cluster batch 4.5 % faster, but 18 % slower at
+// Nb = 1152, where its 256 padding and one workgroup per CU leave the chip under-filled.
+// Small: 128 x 128 tiles of 8 waves (32 x 64 each), K stage 32, flush every 8 stages, two
+// workgroups (16 waves) per CU, which beat the 4-wave 64 x 64 shape by 2-3 % and shorter K
+// stages (16), longer ones (64) and 128 x 256 by 5-25 %. Counters: no LDS bank conflicts, LDS
+// busy ~27 % and MFMA busy ~40 % of cycles, while the chip clock drops to ~1.7 GHz during
+// these kernels (2.4 GHz during the FP64 ones). -DKK_MLARGE_CFG=... / -DKK_MSMALL_CFG=...
+// select others for re-tuning.
+#ifndef KK_MLARGE_CFG
+#define KK_MLARGE_CFG MDl256x128n3
 #endif
-using MBackCfg = KK_MBACK_CFG;
+#ifndef KK_MSMALL_CFG
+#define KK_MSMALL_CFG MCfg128x128w8f8
+#endif
+using MLargeCfg = KK_MLARGE_CFG;
+using MSmallCfg = KK_MSMALL_CFG;
 
-// Padded dimension of the split-precision path: the larger tile side of the product
-// configuration (128 for the default), so that its tiles cover the padded matrices exactly.
-constexpr int MIXED_PAD = MBackCfg::BM > MBackCfg::BN ? MBackCfg::BM : MBackCfg::BN;
-static_assert(MIXED_PAD % MBackCfg::BM == 0 && MIXED_PAD % MBackCfg::BN == 0 && MIXED_PAD % SYM_B == 0,
+// Padded dimension of a split-precision handle: the larger tile side of its product
+// configuration, so that the tiles cover the padded matrices exactly.
+template <class Cfg>
+constexpr int mixed_pad() { return Cfg::BM > Cfg::BN ? Cfg::BM : Cfg::BN; }
+constexpr int MIXED_PAD_LARGE = mixed_pad<MLargeCfg>(), MIXED_PAD_SMALL = mixed_pad<MSmallCfg>();
+static_assert(MIXED_PAD_LARGE % MLargeCfg::BM == 0 && MIXED_PAD_LARGE % MLargeCfg::BN == 0 &&
+                  MIXED_PAD_SMALL % MSmallCfg::BM == 0 && MIXED_PAD_SMALL % MSmallCfg::BN == 0 &&
+                  MIXED_PAD_LARGE % SYM_B == 0 && MIXED_PAD_SMALL % SYM_B == 0,
               "the product tiles and the symmetrizing blocks must divide the padding");
 
 // ---------------------------------------------------------------------------

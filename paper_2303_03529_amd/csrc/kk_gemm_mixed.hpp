@@ -581,13 +581,17 @@ using MCfg128x128w8f8 = MixedCfg<128, 128, 32, 4, 2, 2, 8>;
 using MDl128x128n3 = MixedDlCfg<128, 128, 4, 2, 3, 8>;
 using MDl128x128n4 = MixedDlCfg<128, 128, 4, 2, 4, 8>;
 using MDl256x128n3 = MixedDlCfg<256, 128, 4, 2, 3, 8>;
+using MDl256x128w16 = MixedDlCfg<256, 128, 8, 2, 3, 8>;  // 16 waves of 32 x 64
 
 // Product configurations (each serves both products of a handle: the forward's
 // A = C^T U~ G and the back-transform). Large: the direct-to-LDS 256 x 128 shape with a
-// 3-stage ring, one workgroup per CU; with the full-tile forward it ran 5-9 % faster than the
-// register-staged 128 x 128 shape at Nb = 3888-9216 on MI355X (1024 atoms: forward step 10.7
-// vs 11.3 ms, back 9.5 vs 9.9 ms) and the 64-cluster batch 4.5 % faster, but 18 % slower at
-// Nb = 1152, where its 256 padding and one workgroup per CU leave the chip under-filled.
+// 3-stage ring, one workgroup of 16 waves (32 x 64 each) per CU. With the full-tile forward
+// the 8-wave form of this shape ran 5-9 % faster than the register-staged 128 x 128 shape at
+// Nb = 3888-9216 on MI355X (1024 atoms: forward step 10.7 vs 11.3 ms, back 9.5 vs 9.9 ms) and
+// the 64-cluster batch 4.5 % faster, but 18 % slower at Nb = 1152, where its 256 padding and
+// one workgroup per CU leave the chip under-filled; 16 waves of 32 x 64 added 4 % at 1024
+// atoms and 2.5 % at 432 (16 waves of 64 x 32: 3 % and 1 %; 128 x 256: 1.5 %; flush every 4
+// stages: slower).
 // Small: 128 x 128 tiles of 8 waves (32 x 64 each), K stage 32, flush every 8 stages, two
 // workgroups (16 waves) per CU, which beat the 4-wave 64 x 64 shape by 2-3 % and shorter K
 // stages (16), longer ones (64) and 128 x 256 by 5-25 %. Counters: no LDS bank conflicts, LDS
@@ -595,7 +599,7 @@ using MDl256x128n3 = MixedDlCfg<256, 128, 4, 2, 3, 8>;
 // these kernels (2.4 GHz during the FP64 ones). -DKK_MLARGE_CFG=... / -DKK_MSMALL_CFG=...
 // select others for re-tuning.
 #ifndef KK_MLARGE_CFG
-#define KK_MLARGE_CFG MDl256x128n3
+#define KK_MLARGE_CFG MDl256x128w16
 #endif
 #ifndef KK_MSMALL_CFG
 #define KK_MSMALL_CFG MCfg128x128w8f8

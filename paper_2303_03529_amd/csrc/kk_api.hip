@@ -66,7 +66,10 @@ constexpr int SPLIT_PAD_SMALL = kk::MIXED_PAD_SMALL > kk::PAD ? kk::MIXED_PAD_SM
 static_assert(SPLIT_PAD_LARGE % kk::MIXED_PAD_LARGE == 0 && SPLIT_PAD_LARGE % kk::PAD == 0 &&
                   SPLIT_PAD_SMALL % kk::MIXED_PAD_SMALL == 0 && SPLIT_PAD_SMALL % kk::PAD == 0,
               "split-precision padding must be a multiple of every tile side");
-constexpr int SPLIT_LARGE_NB = 2304;
+#ifndef KK_SPLIT_LARGE_NB
+#define KK_SPLIT_LARGE_NB 2304
+#endif
+constexpr int SPLIT_LARGE_NB = KK_SPLIT_LARGE_NB;
 // Small systems fill the chip better with 64 x 64 tiles (a 128-atom system has
 // 45 upper 128 x 128 forward tiles per spin for 256 CUs). Up to this padded
 // size the FP64 response transforms (both) use them; the reverse pass and the

@@ -592,17 +592,20 @@ using MDl256x128w16 = MixedDlCfg<256, 128, 8, 2, 3, 8>;  // 16 waves of 32 x 64
 // one workgroup per CU leave the chip under-filled; 16 waves of 32 x 64 added 4 % at 1024
 // atoms and 2.5 % at 432 (16 waves of 64 x 32: 3 % and 1 %; 128 x 256: 1.5 %; flush every 4
 // stages: slower).
-// Small: 128 x 128 tiles of 8 waves (32 x 64 each), K stage 32, flush every 8 stages, two
-// workgroups (16 waves) per CU, which beat the 4-wave 64 x 64 shape by 2-3 % and shorter K
-// stages (16), longer ones (64) and 128 x 256 by 5-25 %. Counters: no LDS bank conflicts, LDS
-// busy ~27 % and MFMA busy ~40 % of cycles, while the chip clock drops to ~1.7 GHz during
-// these kernels (2.4 GHz during the FP64 ones). -DKK_MLARGE_CFG=... / -DKK_MSMALL_CFG=...
-// select others for re-tuning.
+// Small (Nb <= 2304): the direct-to-LDS main loop on 128 x 128 tiles of 8 waves (32 x 64
+// each), 3-stage ring (96 KB, one workgroup per CU). With the full-tile forward it beat the
+// register-staged 128 x 128 shape (K stage 32, two workgroups per CU) by 10 % at 128 atoms and
+// 2 % at 16 and 250 atoms; 4- and 5-stage rings were level or 1 % slower, 16 waves of 32 x 32
+// and 8 of 64 x 32 slower at 250 atoms, 4 waves of 64 x 64 7-9 % slower, and taking the large
+// shape from Nb = 2048 gained nothing at 250 atoms. Counters of the register-staged shapes: no
+// LDS bank conflicts, LDS busy ~27 % and MFMA busy ~40 % of cycles, while the chip clock drops
+// to ~1.7 GHz during these kernels (2.4 GHz during the FP64 ones). -DKK_MLARGE_CFG=...,
+// -DKK_MSMALL_CFG=... and -DKK_SPLIT_LARGE_NB=... select others for re-tuning.
 #ifndef KK_MLARGE_CFG
 #define KK_MLARGE_CFG MDl256x128w16
 #endif
 #ifndef KK_MSMALL_CFG
-#define KK_MSMALL_CFG MCfg128x128w8f8
+#define KK_MSMALL_CFG MDl128x128n3
 #endif
 using MLargeCfg = KK_MLARGE_CFG;
 using MSmallCfg = KK_MSMALL_CFG;

@@ -66,6 +66,9 @@ constexpr int SPLIT_PAD_SMALL = kk::MIXED_PAD_SMALL > kk::PAD ? kk::MIXED_PAD_SM
 static_assert(SPLIT_PAD_LARGE % kk::MIXED_PAD_LARGE == 0 && SPLIT_PAD_LARGE % kk::PAD == 0 &&
                   SPLIT_PAD_SMALL % kk::MIXED_PAD_SMALL == 0 && SPLIT_PAD_SMALL % kk::PAD == 0,
               "split-precision padding must be a multiple of every tile side");
+// The large shape pays for its coarser padding above this size: at 432 atoms (Nb = 3888,
+// padded to 4096 against 3968) it ran 48.6 updates/s against 42.4 on the small shape, at 686
+// atoms 12.9 against 11.4.
 #ifndef KK_SPLIT_LARGE_NB
 #define KK_SPLIT_LARGE_NB 2304
 #endif

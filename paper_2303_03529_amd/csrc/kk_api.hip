@@ -442,8 +442,14 @@ kk_status launch_mixed(kk_handle h, bool forward, kk::MixedArgs& a) {
     else
       kk::gemm_mixed<kk::EPI_STORE, kk::MSmallCfg><<<grid, kk::MSmallCfg::THREADS, 0, h->stream>>>(a);
     LAUNCH_CHECK("gemm_mixed");
-    const int nblk = a.n / kk::SYM_B;
-    kk::fermi_symmetrize<<<dim3(nblk * (nblk + 1) / 2, a.nitems), 256, 0, h->stream>>>(a);
+    if (h->mx_large) {
+      const int nblk = a.n / kk::SYM_B_LARGE;
+      kk::fermi_symmetrize<kk::SYM_B_LARGE, kk::SYM_T_LARGE>
+          <<<dim3(nblk * (nblk + 1) / 2, a.nitems), kk::SYM_T_LARGE, 0, h->stream>>>(a);
+    } else {
+      const int nblk = a.n / kk::SYM_B;
+      kk::fermi_symmetrize<kk::SYM_B, 256><<<dim3(nblk * (nblk + 1) / 2, a.nitems), 256, 0, h->stream>>>(a);
+    }
     LAUNCH_CHECK("fermi_symmetrize");
   } else {
     ProfileScope ps(h, 1);

@@ -508,31 +508,42 @@ __global__ __launch_bounds__(Cfg::THREADS, Cfg::MIN_BLOCKS) void gemm_mixed(cons
 }
 
 // Second pass of the split forward transform in its full-tile form. For one
-// 32 x 32 block pair (I <= J) of an item: X = (A + A^T) / 2 / s_prod in FP64 from
+// B x B block pair (I <= J) of an item: X = (A + A^T) / 2 / s_prod in FP64 from
 // the FP32 product A, Y = F o X off the diagonal and Y_ii = -w_i X_ii (X_ii to
 // xdiag), split at the Y scale and written to block (I, J) and, through LDS, to
-// its mirror (J, I). pair indexes the upper triangle row-major; 256 threads.
-constexpr int SYM_B = 32;  // 4 elements per thread (64 x 64, 16 each: 24 instead of 14 us at Nb = 1152)
+// its mirror (J, I). pair indexes the upper triangle row-major; T threads.
+// Small handles and batches: 32 x 32 blocks of 256 threads, 4 elements per thread (64 x 64
+// with 16 each: 24 instead of 14 us at Nb = 1152). Large handles: 64 x 64 blocks of 512
+// threads, whose 256-byte row reads and 128-byte row writes use HBM better than the 128- and
+// 64-byte segments of 32 x 32 blocks.
+constexpr int SYM_B = 32;
+#ifndef KK_SYM_B_LARGE
+#define KK_SYM_B_LARGE 64
+#endif
+constexpr int SYM_B_LARGE = KK_SYM_B_LARGE;
+constexpr int SYM_T_LARGE = SYM_B_LARGE >= 64 ? 512 : 256;
+template <int B = SYM_B, int T = 256>
 __device__ __forceinline__ void fermi_symmetrize_dev(const MixedItem& it, const int n, const double beta,
                                                      const int pair) {
-  const int nblk = n / SYM_B;
+  static_assert(T % B == 0 && B % (T / B) == 0, "thread mapping");
+  const int nblk = n / B;
   int I = 0, rem = pair;
   while (rem >= nblk - I) {
     rem -= nblk - I;
     ++I;
   }
   const int J = I + rem;
-  __shared__ float At[SYM_B][SYM_B + 1];                           // block (J, I) of A
-  __shared__ _Float16 Th[SYM_B][SYM_B + 2], Tl[SYM_B][SYM_B + 2];  // Y block (I, J), transposed
-  const int tx = threadIdx.x % SYM_B, ty = threadIdx.x / SYM_B;
-  constexpr int RS = 256 / SYM_B;
-  for (int r = ty; r < SYM_B; r += RS) At[r][tx] = it.x32[(size_t)(J * SYM_B + r) * n + I * SYM_B + tx];
+  __shared__ float At[B][B + 1];                   // block (J, I) of A
+  __shared__ _Float16 Th[B][B + 2], Tl[B][B + 2];  // Y block (I, J), transposed
+  const int tx = threadIdx.x % B, ty = threadIdx.x / B;
+  constexpr int RS = T / B;
+  for (int r = ty; r < B; r += RS) At[r][tx] = it.x32[(size_t)(J * B + r) * n + I * B + tx];
   __syncthreads();
   const double inv = it.sc[0], sy = it.sc[1];
-  const int c = J * SYM_B + tx;
+  const int c = J * B + tx;
   const double en = it.eps[c], fn = it.f[c], fcn = it.fc[c];
-  for (int r = ty; r < SYM_B; r += RS) {
-    const int m = I * SYM_B + r;
+  for (int r = ty; r < B; r += RS) {
+    const int m = I * B + r;
     const double x = 0.5 * inv * ((double)it.x32[(size_t)m * n + c] + (double)At[tx][r]);
     double y;
     if (m == c) {
@@ -549,17 +560,18 @@ __device__ __forceinline__ void fermi_symmetrize_dev(const MixedItem& it, const 
   }
   if (I == J) return;  // a diagonal block is symmetric by construction
   __syncthreads();
-  for (int r = ty; r < SYM_B; r += RS) {
-    const size_t o = (size_t)(J * SYM_B + r) * n + I * SYM_B + tx;
+  for (int r = ty; r < B; r += RS) {
+    const size_t o = (size_t)(J * B + r) * n + I * B + tx;
     it.yh[o] = Th[r][tx];
     it.yl[o] = Tl[r][tx];
   }
 }
 
 // Single system: blockIdx.x = block pair, blockIdx.y = item.
-__global__ __launch_bounds__(256) void fermi_symmetrize(const MixedArgs args) {
+template <int B, int T>
+__global__ __launch_bounds__(T) void fermi_symmetrize(const MixedArgs args) {
   if (args.stop != nullptr && *args.stop != 0) return;
-  fermi_symmetrize_dev(args.item[blockIdx.y], args.n, args.beta, blockIdx.x);
+  fermi_symmetrize_dev<B, T>(args.item[blockIdx.y], args.n, args.beta, blockIdx.x);
 }
 
 using MCfg128x128 = MixedCfg<128, 128, 32, 2, 2, 2>;
@@ -617,7 +629,7 @@ constexpr int mixed_pad() { return Cfg::BM > Cfg::BN ? Cfg::BM : Cfg::BN; }
 constexpr int MIXED_PAD_LARGE = mixed_pad<MLargeCfg>(), MIXED_PAD_SMALL = mixed_pad<MSmallCfg>();
 static_assert(MIXED_PAD_LARGE % MLargeCfg::BM == 0 && MIXED_PAD_LARGE % MLargeCfg::BN == 0 &&
                   MIXED_PAD_SMALL % MSmallCfg::BM == 0 && MIXED_PAD_SMALL % MSmallCfg::BN == 0 &&
-                  MIXED_PAD_LARGE % SYM_B == 0 && MIXED_PAD_SMALL % SYM_B == 0,
+                  MIXED_PAD_LARGE % SYM_B_LARGE == 0 && MIXED_PAD_SMALL % SYM_B == 0,
               "the product tiles and the symmetrizing blocks must divide the padding");
 
 // ---------------------------------------------------------------------------

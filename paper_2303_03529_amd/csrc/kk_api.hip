@@ -1434,7 +1434,7 @@ kk_status enqueue_update(kk_batch b, int m) {
       if ((st = launch_persistent<kk::EPI_STORE, kk::MLargeCfg>(b, fi, b->cls[0].tiles, b->cls[0].n, 0)))
         return st;
       if ((st = launch_persistent<kk::EPI_STORE, SmallMx>(b, fi, b->cls[1].tiles, b->cls[1].n, 0))) return st;
-      kk::b_symmetrize<<<b->sym_pairs, 256, 0, b->stream>>>(fi, b->d_pair_off, 2 * ns);
+      kk::b_symmetrize<<<b->sym_pairs, kk::BATCH_SYM_T_MIXED, 0, b->stream>>>(fi, b->d_pair_off, 2 * ns);
       LAUNCH_CHECK("b_symmetrize");
       if ((st = launch_persistent<kk::EPI_MULLIKEN, kk::MLargeCfg>(b, bi, b->cls[0].tiles, b->cls[0].n, 0)))
         return st;
@@ -1641,9 +1641,11 @@ kk_status kk_batch_prepare(kk_batch b, int n_systems, const int* n_atoms, const 
   // offsets index one launch's blocks, so their total must fit an int
   std::vector<int> pair_off(1, 0);
   long long total_pairs = 0;
+  const int bsym = mixed ? kk::BATCH_SYM_B_MIXED : kk::BATCH_SYM_B_F64;
   for (int i = 0; i < n_systems; ++i)
     for (int s = 0; s < 2; ++s) {
-      const long long nblk = b->sys[i]->np / kk::SYM_B;
+      if (b->sys[i]->np % bsym != 0) return fail(KK_EINVAL, "internal: padded size not a multiple of the block pairs");
+      const long long nblk = b->sys[i]->np / bsym;
       total_pairs += nblk * (nblk + 1) / 2;
       if (total_pairs > INT_MAX) return fail(KK_EINVAL, "kk_batch_prepare: too many block pairs in one batch");
       pair_off.push_back((int)total_pairs);

@@ -137,6 +137,12 @@ kk_status mulliken_project(kk_handle h, int batch, const double *dD_up, const do
  * call returns KK_BREAKDOWN when info is given. delta = 0 gives Kdelta = 0.
  * If O is not positive definite, Kdelta is set to zero and info->status (and
  * the return value when info is given) is KK_ESINGULAR.
+ * Unless kernel timing is on (kk_profile_enable), the update runs as one graph
+ * launch on a private stream of the handle, ordered after the work already on
+ * the handle's stream and before work enqueued there after the call (events);
+ * the graph is captured on first use and again when K0 (the pointer), m, the
+ * tolerance or the handle's buffers change. delta is copied in and Kdelta out
+ * on device, so the caller's buffers may change from call to call.
  */
 kk_status krylov_kernel_apply(kk_handle h, const double *delta, int m, const double *K0,
                               double *Kdelta, kk_info *info);

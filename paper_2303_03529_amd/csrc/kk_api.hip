@@ -156,6 +156,32 @@ struct kk_handle_s {
   int fwd_m = 0;
   const double* fwd_K0 = nullptr;
   long prepare_gen = 0;  // bumped by every successful kk_prepare
+  long alloc_gen = 0;    // bumped by every device allocation of the handle
+
+  // Captured single-system update (krylov_run without profiling): launched on a private
+  // stream joined to the caller's by events, reading delta from and writing K delta to
+  // handle-owned buffers so that the graph's pointers stay fixed; replayed while its key
+  // (K0, m, tol, allocation generation) holds.
+  hipStream_t gstream = nullptr;
+  hipEvent_t g_in = nullptr, g_out = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<void*> g_owned;
+  double *gdelta = nullptr, *gkd = nullptr;
+  int g_cap = 0;
+  const double* g_K0 = nullptr;
+  int g_m = -1;
+  double g_tol = -1.0;
+  long g_gen = -1;
+  bool no_graph = false;  // set if a capture failed: the eager path from then on
+
+  void drop_graph() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    gexec = nullptr;
+    graph = nullptr;
+    g_m = -1;
+  }
 
   // reverse-pass workspace (krylov_kernel_adjoint), allocated on first use
   std::vector<void*> adj_owned;
@@ -198,6 +224,8 @@ struct kk_handle_s {
       return;
     }
     (void)hipStreamSynchronize(stream);
+    if (gstream) (void)hipStreamSynchronize(gstream);
+    drop_graph();
     free_workspace();
     free_adjoint();
     fwd_valid = false;
@@ -227,6 +255,7 @@ kk_status dalloc_t(kk_handle h, T** p, size_t count, bool workspace = false) {
   void* q = nullptr;
   kk_status st = dalloc(workspace ? h->ws_owned : h->owned, &q, count * sizeof(T));
   *p = static_cast<T*>(q);
+  ++h->alloc_gen;
   return st;
 }
 
@@ -653,6 +682,12 @@ kk_status kk_destroy(kk_handle h) {
   if (!h) return fail(KK_EINVAL, "kk_destroy: handle is NULL");
   h->release();
   for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+  if (h->gstream) (void)hipStreamSynchronize(h->gstream);
+  h->drop_graph();
+  for (void* p : h->g_owned) (void)hipFree(p);
+  if (h->g_in) (void)hipEventDestroy(h->g_in);
+  if (h->g_out) (void)hipEventDestroy(h->g_out);
+  if (h->gstream) (void)hipStreamDestroy(h->gstream);
   delete h;
   return KK_OK;
 }
@@ -818,6 +853,9 @@ kk_status mulliken_project(kk_handle h, int batch, const double* dD_up, const do
 
 namespace {
 
+kk_status enqueue_krylov(kk_handle h, const double* delta, int m, double tol, const double* K0, double* Kdelta);
+kk_status krylov_graph(kk_handle h, const double* delta, int m, double tol, const double* K0, double* Kdelta);
+
 kk_status krylov_run(kk_handle h, const char* who, const double* delta, int m, double tol, const double* K0,
                      double* Kdelta, kk_info* info) {
   kk_status st = check_handle(h);
@@ -828,6 +866,38 @@ kk_status krylov_run(kk_handle h, const char* who, const double* delta, int m, d
     return fail(KK_EINVAL, "%s: need 1 <= m <= min(2N, %d), got %d", who, kk::MAX_RANK, m);
   if (!(tol >= 0.0)) return fail(KK_EINVAL, "%s: tolerance must be >= 0", who);
   if ((st = ensure_workspace(h, 1))) return st;
+  if (!h->profiling && !h->no_graph) {
+    st = krylov_graph(h, delta, m, tol, K0, Kdelta);
+    if (st == KK_EHIP && h->no_graph) st = enqueue_krylov(h, delta, m, tol, K0, Kdelta);  // capture refused
+  } else {
+    st = enqueue_krylov(h, delta, m, tol, K0, Kdelta);
+  }
+  if (st) return st;
+  h->fwd_valid = true;
+  h->fwd_m = m;
+  h->fwd_K0 = K0;
+  if (info) {
+    kk::KrylovState hs;
+    HIP_OR_FAIL(hipMemcpyAsync(&hs, h->kst, sizeof hs, hipMemcpyDeviceToHost, h->stream));
+    HIP_OR_FAIL(hipStreamSynchronize(h->stream));
+    info->rank_used = hs.rank;
+    info->status = hs.status;
+    info->min_pivot = hs.min_pivot;
+    info->max_pivot = hs.max_pivot;
+    info->ls_residual = hs.ls_residual;
+    g_err.clear();
+    if (hs.status == KK_ESINGULAR) return fail(KK_ESINGULAR, "%s: Gram matrix not positive definite", who);
+    return hs.status == 1 ? KK_BREAKDOWN : KK_OK;
+  }
+  g_err.clear();
+  return KK_OK;
+}
+
+// The launches of one update (Algorithm of Sec. II.E: precondition, m Krylov steps of
+// orthonormalize / response / precondition, least-squares solve) on h->stream.
+kk_status enqueue_krylov(kk_handle h, const double* delta, int m, double tol, const double* K0, double* Kdelta) {
+  kk_status st;
+  const int n2 = 2 * h->natoms;
   const int* stop = &h->kst->stop;
   const int gv_threads = 256, gv_blocks = (n2 * kk::WAVE + gv_threads - 1) / gv_threads;
   // orthonormalization: one block just large enough for 8 entries per thread
@@ -853,23 +923,72 @@ kk_status krylov_run(kk_handle h, const char* who, const double* delta, int m, d
   }
   kk::krylov_solve<<<1, 1024, 0, h->stream>>>(h->V, h->Ft, h->ftilde, n2, h->kst, Kdelta, 0.0);
   LAUNCH_CHECK("krylov_solve");
-  h->fwd_valid = true;
-  h->fwd_m = m;
-  h->fwd_K0 = K0;
-  if (info) {
-    kk::KrylovState hs;
-    HIP_OR_FAIL(hipMemcpyAsync(&hs, h->kst, sizeof hs, hipMemcpyDeviceToHost, h->stream));
-    HIP_OR_FAIL(hipStreamSynchronize(h->stream));
-    info->rank_used = hs.rank;
-    info->status = hs.status;
-    info->min_pivot = hs.min_pivot;
-    info->max_pivot = hs.max_pivot;
-    info->ls_residual = hs.ls_residual;
-    g_err.clear();
-    if (hs.status == KK_ESINGULAR) return fail(KK_ESINGULAR, "%s: Gram matrix not positive definite", who);
-    return hs.status == 1 ? KK_BREAKDOWN : KK_OK;
+  return KK_OK;
+}
+
+// One update as a graph launch: capture on first use and whenever the key changes.
+kk_status krylov_graph(kk_handle h, const double* delta, int m, double tol, const double* K0, double* Kdelta) {
+  const int n2 = 2 * h->natoms;
+  if (!h->gstream) {
+    HIP_OR_FAIL(hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking));
+    HIP_OR_FAIL(hipEventCreateWithFlags(&h->g_in, hipEventDisableTiming));
+    HIP_OR_FAIL(hipEventCreateWithFlags(&h->g_out, hipEventDisableTiming));
   }
-  g_err.clear();
+  if (n2 > h->g_cap) {
+    HIP_OR_FAIL(hipStreamSynchronize(h->gstream));
+    h->drop_graph();
+    for (void* p : h->g_owned) (void)hipFree(p);
+    h->g_owned.clear();
+    h->gdelta = h->gkd = nullptr;
+    h->g_cap = 0;
+    void *a = nullptr, *b = nullptr;
+    kk_status st;
+    if ((st = dalloc(h->g_owned, &a, sizeof(double) * n2))) return st;
+    if ((st = dalloc(h->g_owned, &b, sizeof(double) * n2))) return st;
+    h->gdelta = static_cast<double*>(a);
+    h->gkd = static_cast<double*>(b);
+    h->g_cap = n2;
+  }
+  hipStream_t user = h->stream;
+  HIP_OR_FAIL(hipEventRecord(h->g_in, user));
+  HIP_OR_FAIL(hipStreamWaitEvent(h->gstream, h->g_in, 0));
+  HIP_OR_FAIL(hipMemcpyAsync(h->gdelta, delta, sizeof(double) * n2, hipMemcpyDeviceToDevice, h->gstream));
+  const long gen = h->alloc_gen * 1000003L + h->prepare_gen;
+  if (!h->gexec || h->g_K0 != K0 || h->g_m != m || h->g_tol != tol || h->g_gen != gen) {
+    h->drop_graph();
+    h->stream = h->gstream;
+    hipError_t e = hipStreamBeginCapture(h->gstream, hipStreamCaptureModeThreadLocal);
+    kk_status st = KK_OK;
+    hipGraph_t g = nullptr;
+    if (e == hipSuccess) {
+      st = enqueue_krylov(h, h->gdelta, m, tol, K0, h->gkd);
+      e = hipStreamEndCapture(h->gstream, &g);
+    }
+    h->stream = user;
+    if (st || e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      (void)hipGetLastError();
+      if (st) return st;
+      h->no_graph = true;
+      return fail(KK_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+    }
+    e = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      (void)hipGetLastError();
+      h->no_graph = true;
+      return fail(KK_EHIP, "graph instantiation failed: %s", hipGetErrorString(e));
+    }
+    h->graph = g;
+    h->g_K0 = K0;
+    h->g_m = m;
+    h->g_tol = tol;
+    h->g_gen = gen;
+  }
+  HIP_OR_FAIL(hipGraphLaunch(h->gexec, h->gstream));
+  HIP_OR_FAIL(hipMemcpyAsync(Kdelta, h->gkd, sizeof(double) * n2, hipMemcpyDeviceToDevice, h->gstream));
+  HIP_OR_FAIL(hipEventRecord(h->g_out, h->gstream));
+  HIP_OR_FAIL(hipStreamWaitEvent(user, h->g_out, 0));
   return KK_OK;
 }
 

@@ -358,8 +358,14 @@ kk_status launch_gemm(kk_handle h, int epi, kk::GemmArgs& a, bool small = false)
     else
       kk::gemm_f64<kk::EPI_XSTORE, kk::BackCfg><<<grid, kk::BackCfg::THREADS, 0, h->stream>>>(a);
     LAUNCH_CHECK("gemm_f64");
-    const int nblk = a.n / kk::SYM64_B;
-    kk::fermi_symmetrize_f64<<<dim3(nblk * (nblk + 1) / 2, a.nitems), 256, 0, h->stream>>>(a);
+    if (small) {
+      const int nblk = a.n / kk::SYM64_B;
+      kk::fermi_symmetrize_f64<kk::SYM64_B, 256><<<dim3(nblk * (nblk + 1) / 2, a.nitems), 256, 0, h->stream>>>(a);
+    } else {
+      const int nblk = a.n / kk::SYM64_B_LARGE;
+      kk::fermi_symmetrize_f64<kk::SYM64_B_LARGE, kk::SYM64_T_LARGE>
+          <<<dim3(nblk * (nblk + 1) / 2, a.nitems), kk::SYM64_T_LARGE, 0, h->stream>>>(a);
+    }
   } else if (epi == kk::EPI_FERMI_XY) {
     ProfileScope ps(h, 2);
     kk::gemm_f64<kk::EPI_FERMI_XY, kk::FwdCfg><<<grid, kk::FwdCfg::THREADS, 0, h->stream>>>(a);
@@ -1573,7 +1579,7 @@ kk_status enqueue_update(kk_batch b, int m) {
       if ((st = launch_persistent<kk::EPI_XSTORE, kk::BackCfg>(b, fi, b->cls[0].tiles, b->cls[0].n, 0)))
         return st;
       if ((st = launch_persistent<kk::EPI_XSTORE, SmallF64>(b, fi, b->cls[1].tiles, b->cls[1].n, 0))) return st;
-      kk::b_symmetrize_f64<<<b->sym_pairs, 256, 0, b->stream>>>(fi, b->d_pair_off, 2 * ns);
+      kk::b_symmetrize_f64<<<b->sym_pairs, kk::BATCH_SYM_T_F64, 0, b->stream>>>(fi, b->d_pair_off, 2 * ns);
       LAUNCH_CHECK("b_symmetrize_f64");
       if ((st = launch_persistent<kk::EPI_MULLIKEN, kk::BackCfg>(b, bi, b->cls[0].tiles, b->cls[0].n, 0)))
         return st;

@@ -111,9 +111,9 @@ __device__ __forceinline__ int pair_item(const int* __restrict__ pair_off, int n
   return lo;
 }
 // Block side of the pair list: split batches pad every system to the large split tile and
-// take its 64 x 64 block pairs (512 threads); FP64 batches take 32 x 32 (256 threads).
+// take its 64 x 64 block pairs (512 threads); FP64 batches (padded to 128) 64 x 64 as well.
 constexpr int BATCH_SYM_B_MIXED = SYM_B_LARGE, BATCH_SYM_T_MIXED = SYM_T_LARGE;
-constexpr int BATCH_SYM_B_F64 = SYM64_B;
+constexpr int BATCH_SYM_B_F64 = SYM64_B_LARGE, BATCH_SYM_T_F64 = SYM64_T_LARGE;
 
 __global__ __launch_bounds__(BATCH_SYM_T_MIXED) void b_symmetrize(const BatchItemMixed* __restrict__ items,
                                                                   const int* __restrict__ pair_off, int nitems) {
@@ -123,12 +123,12 @@ __global__ __launch_bounds__(BATCH_SYM_T_MIXED) void b_symmetrize(const BatchIte
   fermi_symmetrize_dev<BATCH_SYM_B_MIXED, BATCH_SYM_T_MIXED>(it.g, it.n, it.beta, blockIdx.x - pair_off[z]);
 }
 
-__global__ __launch_bounds__(256) void b_symmetrize_f64(const BatchItemF64* __restrict__ items,
+__global__ __launch_bounds__(BATCH_SYM_T_F64) void b_symmetrize_f64(const BatchItemF64* __restrict__ items,
                                                         const int* __restrict__ pair_off, int nitems) {
   const int z = pair_item(pair_off, nitems, blockIdx.x);
   const BatchItemF64& it = items[z];
   if (*it.stop) return;
-  fermi_symmetrize_f64_dev(it.g, it.n, it.beta, blockIdx.x - pair_off[z]);
+  fermi_symmetrize_f64_dev<BATCH_SYM_B_F64, BATCH_SYM_T_F64>(it.g, it.n, it.beta, blockIdx.x - pair_off[z]);
 }
 
 __global__ void b_combine(const SysDesc* __restrict__ d) {

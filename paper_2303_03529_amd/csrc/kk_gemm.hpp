@@ -318,33 +318,38 @@ __global__ __launch_bounds__(Cfg::THREADS, Cfg::MIN_BLOCKS) void gemm_f64(const 
 }
 
 // Second pass of the FP64 forward transform when it runs as a full-tile product
-// (EPI_XSTORE): out holds A = C^T U~ G; for each 32 x 32 block pair (I <= J),
+// (EPI_XSTORE): out holds A = C^T U~ G; for each B x B block pair (I <= J),
 // X = (A + A^T) / 2, Y = F o X off the diagonal and Y_ii = -w_i X_ii (X_ii to
 // xdiag), written in place over A: block (I, J) element by element by the
 // thread that read it, block (J, I) through LDS after the whole of it was read.
-// pair indexes the upper triangle row-major; 256 threads.
+// pair indexes the upper triangle row-major; T threads. Small handles: 32 x 32 blocks of
+// 256 threads; large handles and FP64 batches: 64 x 64 blocks of 512 threads (512-byte rows).
 constexpr int SYM64_B = 32;
+constexpr int SYM64_B_LARGE = 64, SYM64_T_LARGE = 512;
+static_assert(PAD % SYM64_B_LARGE == 0, "the symmetrizing blocks must divide the padding");
+template <int B = SYM64_B, int T = 256>
 __device__ __forceinline__ void fermi_symmetrize_f64_dev(const GemmItem& it, const int n, const double beta,
                                                          const int pair) {
-  const int nblk = n / SYM64_B;
+  static_assert(T % B == 0 && B % (T / B) == 0, "thread mapping");
+  const int nblk = n / B;
   int I = 0, rem = pair;
   while (rem >= nblk - I) {
     rem -= nblk - I;
     ++I;
   }
   const int J = I + rem;
-  __shared__ double At[SYM64_B][SYM64_B + 1];  // block (J, I) of A, then the mirror of Y
-  const int tx = threadIdx.x % SYM64_B, ty = threadIdx.x / SYM64_B;
-  constexpr int RS = 256 / SYM64_B;
+  __shared__ double At[B][B + 1];  // block (J, I) of A, then the mirror of Y
+  const int tx = threadIdx.x % B, ty = threadIdx.x / B;
+  constexpr int RS = T / B;
   double* const Y = it.out;
-  for (int r = ty; r < SYM64_B; r += RS) At[r][tx] = Y[(size_t)(J * SYM64_B + r) * n + I * SYM64_B + tx];
+  for (int r = ty; r < B; r += RS) At[r][tx] = Y[(size_t)(J * B + r) * n + I * B + tx];
   __syncthreads();
-  const int c = J * SYM64_B + tx;
+  const int c = J * B + tx;
   const double en = it.eps[c], fn = it.f[c], fcn = it.fc[c];
-  double yv[SYM64_B / RS];
+  double yv[B / RS];
 #pragma unroll
-  for (int q = 0; q < SYM64_B / RS; ++q) {
-    const int r = ty + q * RS, m = I * SYM64_B + r;
+  for (int q = 0; q < B / RS; ++q) {
+    const int r = ty + q * RS, m = I * B + r;
     double* const o = Y + (size_t)m * n + c;
     const double x = 0.5 * (*o + At[tx][r]);
     double y;
@@ -360,15 +365,16 @@ __device__ __forceinline__ void fermi_symmetrize_f64_dev(const GemmItem& it, con
   if (I == J) return;  // a diagonal block is symmetric by construction
   __syncthreads();     // every read of At is done
 #pragma unroll
-  for (int q = 0; q < SYM64_B / RS; ++q) At[tx][ty + q * RS] = yv[q];
+  for (int q = 0; q < B / RS; ++q) At[tx][ty + q * RS] = yv[q];
   __syncthreads();
-  for (int r = ty; r < SYM64_B; r += RS) Y[(size_t)(J * SYM64_B + r) * n + I * SYM64_B + tx] = At[r][tx];
+  for (int r = ty; r < B; r += RS) Y[(size_t)(J * B + r) * n + I * B + tx] = At[r][tx];
 }
 
 // Single system: blockIdx.x = block pair, blockIdx.y = item.
-__global__ __launch_bounds__(256) void fermi_symmetrize_f64(const GemmArgs args) {
+template <int B, int T>
+__global__ __launch_bounds__(T) void fermi_symmetrize_f64(const GemmArgs args) {
   if (args.stop != nullptr && *args.stop != 0) return;
-  fermi_symmetrize_f64_dev(args.item[blockIdx.y], args.n, args.beta, blockIdx.x);
+  fermi_symmetrize_f64_dev<B, T>(args.item[blockIdx.y], args.n, args.beta, blockIdx.x);
 }
 
 // Configurations. The default (128 x 128 tile, 8 waves of 32 x 64, two

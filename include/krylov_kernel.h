@@ -55,8 +55,20 @@ typedef enum {
  *                 the Mulliken sums and the Krylov m x m solve stay FP64.
  *                 Responses and kernel results agree with FP64 to ~1e-7
  *                 relative on the bcc-Fe workloads (not a guaranteed bound).
+ *   KK_MIXED_BF16 the two transforms in BF16 MFMA products with FP32
+ *                 accumulation and a refinement pass: every split operand is
+ *                 kept as three BF16 pieces (hi, lo, residual; ~24 significant
+ *                 bits). A first pass forms hi*hi + hi*lo + lo*hi + lo*lo (~16
+ *                 bits); the refinement pass runs the same products over the
+ *                 residual pieces, hi*res + res*hi, and adds them to what the
+ *                 first pass stored (the forward product before its Fermi
+ *                 Hadamard step; the back-transform's Mulliken sums, which are
+ *                 linear in the product). Six products per transform instead of
+ *                 KK_MIXED_F16's three; BF16's exponent range needs no scaling.
+ *                 FP64 elsewhere as above; agreement with FP64 ~1e-7 relative.
+ *                 Single-system handles only (not in kk_batch_prepare).
  */
-typedef enum { KK_FP64 = 0, KK_MIXED_F16 = 1 } kk_precision;
+typedef enum { KK_FP64 = 0, KK_MIXED_F16 = 1, KK_MIXED_BF16 = 2 } kk_precision;
 
 typedef struct {
   int rank_used;       /* number of Krylov directions actually used (<= m)          */
@@ -88,7 +100,7 @@ kk_status kk_destroy(kk_handle h);
  *   W              Stoner constant (same energy unit as eps)
  *   kT             electronic temperature (> 0, energy unit of eps)
  *   n_electrons    total electron count over both spins, 0 < N_e < 2 Nb
- *   precision      KK_FP64 or KK_MIXED_F16 (see kk_precision)
+ *   precision      KK_FP64, KK_MIXED_F16 or KK_MIXED_BF16 (see kk_precision)
  * The library forms C^sigma = Z Q^sigma, G^sigma = S C^sigma, the occupations
  * f^sigma and solves the common chemical potential mu on the device. The
  * call allocates device memory and synchronizes the stream before returning,
@@ -141,8 +153,10 @@ kk_status mulliken_project(kk_handle h, int batch, const double *dD_up, const do
  * launch on a private stream of the handle, ordered after the work already on
  * the handle's stream and before work enqueued there after the call (events);
  * the graph is captured on first use and again when K0 (the pointer), m, the
- * tolerance or the handle's buffers change. delta is copied in and Kdelta out
- * on device, so the caller's buffers may change from call to call.
+ * tolerance, the handle's buffers or the prepared W or kT change (a re-prepare
+ * of the same shape, W and kT replays the existing graph on the new data).
+ * delta is copied in and Kdelta out on device, so the caller's buffers may
+ * change from call to call.
  */
 kk_status krylov_kernel_apply(kk_handle h, const double *delta, int m, const double *K0,
                               double *Kdelta, kk_info *info);
@@ -274,10 +288,21 @@ kk_status kk_batch_prepare(kk_batch b, int n_systems, const int *n_atoms, const 
 kk_status krylov_kernel_apply_batch(kk_batch b, const double *const *delta, int m, double *const *Kdelta,
                                     kk_info *info);
 
-/* Tuning chosen by the autotuner: the largest padded size that uses 64 x 64
- * tiles (0 = none), persistent workgroups per CU, and the fastest update's
- * time in milliseconds. */
+/* Tuning chosen by the autotuner (or set by kk_batch_set_tuning): the largest
+ * padded size that uses 64 x 64 tiles (0 = none), persistent workgroups per
+ * CU, and the fastest update's time in milliseconds (0 when set by hand). */
 kk_status kk_batch_tuning(kk_batch b, int *small_np_max, int *workgroups_per_cu, double *update_ms);
+
+/*
+ * kk_batch_set_tuning -- fix the tuning instead of letting the first update
+ * autotune: systems whose padded size is <= small_np_max (>= 0; 0 = none,
+ * a value above every system's = all) take the 64 x 64 tile class, the rest
+ * the large one; workgroups_per_cu (1..8) persistent workgroups per CU. Valid
+ * after kk_batch_prepare (which resets it); drops any captured graph, so the
+ * next update captures anew. For reproducible timings and for tests that must
+ * reach each tile class. Synchronizes the batch's stream.
+ */
+kk_status kk_batch_set_tuning(kk_batch b, int small_np_max, int workgroups_per_cu);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char *kk_last_error(void);

@@ -66,3 +66,30 @@ def xlbomd_update(n_hist: np.ndarray, Kf: np.ndarray, kappa: float, alpha: float
     prev = n_hist[1] if len(n_hist) > 1 else n_hist[0]
     diss = sum(ck * n_hist[k] for k, ck in enumerate(c))
     return 2.0 * n_hist[0] - prev - kappa * np.asarray(Kf) + alpha * diss
+
+
+def xlbomd_electrons(sysd: dict, n_start: np.ndarray, steps: int, kappa: float, alpha: float = 0.0, c=(1.0,),
+                     m_max: int = 4, rank_tol: float = 0.1, K0=None):
+    """Extended-Lagrangian propagation of n at fixed nuclei (Sec. II.F with the kernel of II.G).
+
+    The history starts with every row n(t - k dt) = n_start. Each step forms the
+    residual f = q[n(t)] - n(t) at a fresh expansion point, applies the
+    adaptive-rank kernel (as in the SCF above) and takes the update
+    n(t+dt) = 2 n(t) - n(t-dt) - kappa K f + alpha sum_k c_k n(t - k dt).
+    Returns (rms residual per step, residual vectors per step, final n).
+    """
+    kmax = max(len(c) - 1, 1)
+    hist = np.tile(np.asarray(n_start, dtype=np.float64), (kmax + 1, 1))
+    cc = np.zeros(kmax + 1)
+    cc[: len(c)] = c
+    res, fs = [], []
+    for _ in range(steps):
+        n = hist[0]
+        ep = expansion_point(sysd, n)
+        f = net_q_of_n(sysd, n, ep["Z"]) - n
+        res.append(rms(f))
+        fs.append(f)
+        Kf = kernel_apply(sysd, ep, f, m_max, K0, tol=rank_tol)
+        new = xlbomd_update(hist, Kf, kappa, alpha, cc)
+        hist = np.vstack([new[None, :], hist[:-1]])
+    return res, fs, hist[0]

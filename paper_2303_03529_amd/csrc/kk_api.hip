@@ -122,17 +122,19 @@ struct kk_handle_s {
   int2 *stiles_upper = nullptr, *stiles_full = nullptr;
   int n_supper = 0, n_sfull = 0;
 
-  // split-precision state (precision == KK_MIXED_F16)
+  // split-precision state (precision KK_MIXED_F16 or KK_MIXED_BF16; the BF16 form keeps a
+  // third piece of every split operand, *r, for its refinement pass)
   int precision = KK_FP64;
+  bool bf16 = false;
   double* GT[2] = {nullptr, nullptr};
-  _Float16 *Ch[2] = {nullptr, nullptr}, *Cl[2] = {nullptr, nullptr};
-  _Float16 *GTh[2] = {nullptr, nullptr}, *GTl[2] = {nullptr, nullptr};
+  _Float16 *Ch[2] = {nullptr, nullptr}, *Cl[2] = {nullptr, nullptr}, *Cr[2] = {nullptr, nullptr};
+  _Float16 *GTh[2] = {nullptr, nullptr}, *GTl[2] = {nullptr, nullptr}, *GTr[2] = {nullptr, nullptr};
   double* mconst = nullptr;  // per spin: s_C, s_G, max column norms of C and G
   int2* mtiles_full = nullptr;  // both split transforms of a single system: full tiles
   int n_mfull = 0;
-  _Float16 *uct_h = nullptr, *uct_l = nullptr;  // (U~ C)^T split per direction
+  _Float16 *uct_h = nullptr, *uct_l = nullptr, *uct_r = nullptr;  // (U~ C)^T split per direction
   float* x32 = nullptr;  // split forward: the product C^T U~ G per direction, FP32
-  _Float16 *yh = nullptr, *yl = nullptr;
+  _Float16 *yh = nullptr, *yl = nullptr, *yr = nullptr;
   double* msc = nullptr;
   double* mscratch = nullptr;  // 4 np doubles: row statistics for the split scales
 
@@ -161,7 +163,7 @@ struct kk_handle_s {
   // Captured single-system update (krylov_run without profiling): launched on a private
   // stream joined to the caller's by events, reading delta from and writing K delta to
   // handle-owned buffers so that the graph's pointers stay fixed; replayed while its key
-  // (K0, m, tol, allocation generation) holds.
+  // (K0, m, tol, allocation generation, W, beta) holds.
   hipStream_t gstream = nullptr;
   hipEvent_t g_in = nullptr, g_out = nullptr;
   hipGraph_t graph = nullptr;
@@ -173,6 +175,7 @@ struct kk_handle_s {
   int g_m = -1;
   double g_tol = -1.0;
   long g_gen = -1;
+  double g_W = 0.0, g_beta = 0.0;
   bool no_graph = false;  // set if a capture failed: the eager path from then on
 
   void drop_graph() {
@@ -213,7 +216,7 @@ struct kk_handle_s {
     ws_owned.clear();
     chunk_cap = 0;
     u = Y = xdiag = part = nullptr;
-    uct_h = uct_l = yh = yl = nullptr;
+    uct_h = uct_l = uct_r = yh = yl = yr = nullptr;
     x32 = nullptr;
     msc = nullptr;
   }
@@ -267,14 +270,16 @@ __global__ void zero_fill(double* p, size_t n) {
 
 // The per-direction split operand (U~ C)^T of every item of a response chunk in
 // one launch: blockIdx.y = item z = 2 direction + spin, split from C^T at its scale.
+template <bool BF16 = false, int NP = 2>
 __global__ void split_operands(const double* __restrict__ CT0, const double* __restrict__ CT1, int np,
                                const double* __restrict__ u, const double* __restrict__ msc,
                                _Float16* __restrict__ uct_h, _Float16* __restrict__ uct_l,
-                               const int* __restrict__ stop) {
+                               const int* __restrict__ stop, _Float16* __restrict__ uct_r) {
   const int z = blockIdx.y;
   const size_t off = (size_t)z * np * np;
-  kk::split_scaled_columns_dev((z & 1) ? CT1 : CT0, np, u + (size_t)z * np, msc + z * 8 + 3, uct_h + off,
-                               uct_l + off, stop, blockIdx.x, gridDim.x);
+  kk::split_scaled_columns_dev<BF16, NP>((z & 1) ? CT1 : CT0, np, u + (size_t)z * np, msc + z * 8 + 3, uct_h + off,
+                                         uct_l + off, stop, blockIdx.x, gridDim.x,
+                                         NP == 3 ? uct_r + off : nullptr);
 }
 
 kk_status zero(kk_handle h, double* p, size_t n) {
@@ -395,6 +400,9 @@ kk_status ensure_workspace(kk_handle h, int chunk) {
   } else {
     for (_Float16** q : {&h->uct_h, &h->uct_l, &h->yh, &h->yl})
       if ((st = dalloc_t(h, q, items * np * np, true))) return st;
+    if (h->bf16)
+      for (_Float16** q : {&h->uct_r, &h->yr})
+        if ((st = dalloc_t(h, q, items * np * np, true))) return st;
     if ((st = dalloc_t(h, &h->x32, items * np * np, true))) return st;
     if ((st = dalloc_t(h, &h->msc, items * 8, true))) return st;
   }
@@ -406,9 +414,10 @@ kk_status ensure_workspace(kk_handle h, int chunk) {
 }
 
 int max_chunk(kk_handle h) {
-  // FP64: one Y per spin; split path: four FP16 matrices and one FP32 per spin
+  // FP64: one Y per spin; split path: four (BF16: six) 16-bit matrices and one FP32 per spin
   const size_t per_dir = (size_t)2 * h->np * h->np *
-                         (h->precision == KK_FP64 ? sizeof(double) : 4 * sizeof(_Float16) + sizeof(float));
+                         (h->precision == KK_FP64 ? sizeof(double)
+                                                  : (h->bf16 ? 6 : 4) * sizeof(_Float16) + sizeof(float));
   size_t c = WORKSPACE_BUDGET / std::max<size_t>(per_dir, 1);
   return (int)std::max<size_t>(1, std::min<size_t>(c, MAX_CHUNK));
 }
@@ -464,12 +473,54 @@ kk_status response_chunk(kk_handle h, int batch, const double* v, double* q1, co
   return KK_OK;
 }
 
+// BF16 form, one transform step: the first pass (four products of the hi/lo pieces), then
+// the refinement pass over the residual pieces (a2 = the third piece of At, b2 of Bt: products
+// hi res + res hi, added to what the first pass stored), then for the forward the symmetrizing
+// pass that writes Y as three BF16 pieces.
+template <class Cfg1, class Cfg2>
+kk_status launch_bf16_step(kk_handle h, bool forward, kk::MixedArgs& a, const _Float16* const* a2,
+                           const _Float16* const* b2) {
+  const int grid = a.ntiles * a.nitems;
+  if (forward) {
+    kk::gemm_mixed<kk::EPI_STORE, Cfg1><<<grid, Cfg1::THREADS, 0, h->stream>>>(a);
+    LAUNCH_CHECK("gemm_mixed bf16");
+    kk::MixedArgs r = a;  // same items, the lo pieces replaced by the residual pieces
+    for (int z = 0; z < a.nitems; ++z) { r.item[z].a0l = a2[z]; r.item[z].b0l = b2[z]; }
+    kk::gemm_mixed<kk::EPI_STORE_ADD, Cfg2><<<grid, Cfg2::THREADS, 0, h->stream>>>(r);
+    LAUNCH_CHECK("gemm_mixed bf16 refinement");
+    if (h->mx_large) {
+      const int nblk = a.n / kk::SYM_B_LARGE;
+      kk::fermi_symmetrize<kk::SYM_B_LARGE, kk::SYM_T_LARGE, true, 3>
+          <<<dim3(nblk * (nblk + 1) / 2, a.nitems), kk::SYM_T_LARGE, 0, h->stream>>>(a);
+    } else {
+      const int nblk = a.n / kk::SYM_B;
+      kk::fermi_symmetrize<kk::SYM_B, 256, true, 3><<<dim3(nblk * (nblk + 1) / 2, a.nitems), 256, 0, h->stream>>>(a);
+    }
+    LAUNCH_CHECK("fermi_symmetrize bf16");
+  } else {
+    kk::gemm_mixed<kk::EPI_MULLIKEN, Cfg1><<<grid, Cfg1::THREADS, 0, h->stream>>>(a);
+    LAUNCH_CHECK("gemm_mixed bf16");
+    kk::MixedArgs r = a;
+    for (int z = 0; z < a.nitems; ++z) { r.item[z].a0l = a2[z]; r.item[z].b0l = b2[z]; }
+    kk::gemm_mixed<kk::EPI_MULLIKEN_ADD, Cfg2><<<grid, Cfg2::THREADS, 0, h->stream>>>(r);
+    LAUNCH_CHECK("gemm_mixed bf16 refinement");
+  }
+  return KK_OK;
+}
+
 // Split-precision transform step: the forward (full-tile product into the FP32
 // workspace, then the symmetrizing pass that writes the split Y) or the back-transform.
-kk_status launch_mixed(kk_handle h, bool forward, kk::MixedArgs& a) {
+// a2, b2 (BF16 form only): per item the third pieces of At and Bt for the refinement pass.
+kk_status launch_mixed(kk_handle h, bool forward, kk::MixedArgs& a, const _Float16* const* a2 = nullptr,
+                       const _Float16* const* b2 = nullptr) {
   const int grid = a.ntiles * a.nitems;
   if (grid <= 0) return KK_OK;
   if (a.nitems > kk::MAX_GEMM_BATCH) return fail(KK_EINVAL, "internal: too many GEMM items");
+  if (h->bf16) {
+    ProfileScope ps(h, forward ? 0 : 1);
+    return h->mx_large ? launch_bf16_step<kk::MLargeBf1, kk::MLargeBf2>(h, forward, a, a2, b2)
+                       : launch_bf16_step<kk::MSmallBf1, kk::MSmallBf2>(h, forward, a, a2, b2);
+  }
   if (forward) {
     ProfileScope ps(h, 0);
     if (h->mx_large)
@@ -517,8 +568,12 @@ kk_status response_chunk_mixed(kk_handle h, int batch, const double* v, double* 
   LAUNCH_CHECK("mixed_scales");
   {
     const int blocks = (int)std::max<size_t>(1, std::min<size_t>((np2 / 8 + 255) / 256, 16384 / (2 * batch)));
-    split_operands<<<dim3(blocks, 2 * batch), 256, 0, h->stream>>>(h->CT[0], h->CT[1], np, h->u, h->msc, h->uct_h,
-                                                                    h->uct_l, stop);
+    if (h->bf16)
+      split_operands<true, 3><<<dim3(blocks, 2 * batch), 256, 0, h->stream>>>(h->CT[0], h->CT[1], np, h->u, h->msc,
+                                                                               h->uct_h, h->uct_l, stop, h->uct_r);
+    else
+      split_operands<<<dim3(blocks, 2 * batch), 256, 0, h->stream>>>(h->CT[0], h->CT[1], np, h->u, h->msc, h->uct_h,
+                                                                      h->uct_l, stop, nullptr);
     LAUNCH_CHECK("split_operands");
   }
   // forward: A = C^T U~ G over full tiles (At = (U~ C)^T, Bt = G^T), X = (A + A^T) / 2
@@ -533,7 +588,7 @@ kk_status response_chunk_mixed(kk_handle h, int batch, const double* v, double* 
     kk::MixedItem& fi = fa.item[z];
     fi.a0h = h->uct_h + z * np2; fi.a0l = h->uct_l + z * np2; fi.b0h = h->GTh[s]; fi.b0l = h->GTl[s];
     fi.x32 = h->x32 + z * np2;
-    fi.yh = h->yh + z * np2; fi.yl = h->yl + z * np2;
+    fi.yh = h->yh + z * np2; fi.yl = h->yl + z * np2; fi.yr = h->bf16 ? h->yr + z * np2 : nullptr;
     fi.eps = h->eps[s]; fi.f = h->f[s]; fi.fc = h->fc[s]; fi.w = h->w[s];
     fi.xdiag = h->xdiag + (size_t)z * np;
     fi.sc = h->msc + z * 8;
@@ -543,9 +598,17 @@ kk_status response_chunk_mixed(kk_handle h, int batch, const double* v, double* 
     bi.part = h->part + (size_t)z * h->nparts * np;
     bi.sc = h->msc + z * 8 + 2;
   }
+  // BF16 refinement pass operands: residual pieces of (U~ C)^T and G^T (forward), C and Y (back)
+  const _Float16 *fa2[kk::MAX_GEMM_BATCH], *fb2[kk::MAX_GEMM_BATCH], *ba2[kk::MAX_GEMM_BATCH],
+      *bb2[kk::MAX_GEMM_BATCH];
+  if (h->bf16)
+    for (int z = 0; z < 2 * batch; ++z) {
+      fa2[z] = h->uct_r + z * np2; fb2[z] = h->GTr[z & 1];
+      ba2[z] = h->Cr[z & 1]; bb2[z] = h->yr + z * np2;
+    }
   kk_status st;
-  if ((st = launch_mixed(h, true, fa))) return st;
-  if ((st = launch_mixed(h, false, ba))) return st;
+  if ((st = launch_mixed(h, true, fa, fa2, fb2))) return st;
+  if ((st = launch_mixed(h, false, ba, ba2, bb2))) return st;
   {
     dim3 grid((N + kk::COMBINE_ATOMS - 1) / kk::COMBINE_ATOMS, batch);
     kk::combine<<<grid, kk::COMBINE_THREADS, 0, h->stream>>>(h->xdiag, h->part, h->nparts, h->w[0], h->w[1],
@@ -625,13 +688,16 @@ kk_status allocate_prepared(kk_handle h) {
                              h->stream));
   HIP_OR_FAIL(hipMemcpyAsync(h->tiles_store, stt.data(), sizeof(int2) * stt.size(), hipMemcpyHostToDevice,
                              h->stream));
-  if (h->precision == KK_MIXED_F16) {
+  if (h->precision != KK_FP64) {
     if ((st = dalloc_t(h, &h->mconst, 8))) return st;
     if ((st = dalloc_t(h, &h->mscratch, (size_t)4 * np))) return st;
     for (int s = 0; s < 2; ++s) {
       if ((st = dalloc_t(h, &h->GT[s], np2))) return st;
       for (_Float16** q : {&h->Ch[s], &h->Cl[s], &h->GTh[s], &h->GTl[s]})
         if ((st = dalloc_t(h, q, np2))) return st;
+      if (h->bf16)
+        for (_Float16** q : {&h->Cr[s], &h->GTr[s]})
+          if ((st = dalloc_t(h, q, np2))) return st;
     }
     mfull = h->mx_large ? tile_order(np, kk::MLargeCfg::BM, kk::MLargeCfg::BN, false)
                         : tile_order(np, kk::MSmallCfg::BM, kk::MSmallCfg::BN, false);
@@ -662,8 +728,16 @@ kk_status prepare_mixed(kk_handle h) {
     LAUNCH_CHECK("row_stats");
     kk::const_scales<<<1, 1024, 0, h->stream>>>(rmax, rn2, rmax + np, rn2 + np, np, h->mconst + 4 * s);
     LAUNCH_CHECK("const_scales");
-    kk::split_matrix<<<pg, pb, 0, h->stream>>>(h->C[s], np, 0, h->mconst + 4 * s, h->Ch[s], h->Cl[s]);
-    kk::split_matrix<<<pg, pb, 0, h->stream>>>(h->GT[s], np, 0, h->mconst + 4 * s + 1, h->GTh[s], h->GTl[s]);
+    if (h->bf16) {
+      kk::split_matrix<true, 3><<<pg, pb, 0, h->stream>>>(h->C[s], np, 0, h->mconst + 4 * s, h->Ch[s], h->Cl[s],
+                                                          h->Cr[s]);
+      kk::split_matrix<true, 3><<<pg, pb, 0, h->stream>>>(h->GT[s], np, 0, h->mconst + 4 * s + 1, h->GTh[s],
+                                                          h->GTl[s], h->GTr[s]);
+    } else {
+      kk::split_matrix<<<pg, pb, 0, h->stream>>>(h->C[s], np, 0, h->mconst + 4 * s, h->Ch[s], h->Cl[s], nullptr);
+      kk::split_matrix<<<pg, pb, 0, h->stream>>>(h->GT[s], np, 0, h->mconst + 4 * s + 1, h->GTh[s], h->GTl[s],
+                                                 nullptr);
+    }
     LAUNCH_CHECK("split_matrix");
   }
   return KK_OK;
@@ -717,7 +791,7 @@ kk_status prepare_impl(kk_handle h, int n_atoms, const int* atom_offsets, int n_
   if (!(kT > 0.0)) return fail(KK_EINVAL, "kk_prepare: kT must be > 0");
   if (!(n_electrons > 0.0 && n_electrons < 2.0 * n_basis))
     return fail(KK_EINVAL, "kk_prepare: need 0 < n_electrons < 2 n_basis");
-  if (precision != KK_FP64 && precision != KK_MIXED_F16)
+  if (precision != KK_FP64 && precision != KK_MIXED_F16 && precision != KK_MIXED_BF16)
     return fail(KK_EINVAL, "kk_prepare: unsupported precision %d", precision);
   if (atom_offsets[0] != 0 || atom_offsets[n_atoms] != n_basis)
     return fail(KK_EINVAL, "kk_prepare: atom_offsets must start at 0 and end at n_basis");
@@ -725,7 +799,7 @@ kk_status prepare_impl(kk_handle h, int n_atoms, const int* atom_offsets, int n_
     if (atom_offsets[a + 1] <= atom_offsets[a])
       return fail(KK_EINVAL, "kk_prepare: atom_offsets must be strictly increasing (atom %d)", a);
 
-  const bool mixed = precision == KK_MIXED_F16;
+  const bool mixed = precision != KK_FP64;
   const bool mx_large = mixed && (split_large || n_basis > SPLIT_LARGE_NB);
   const int pad = mixed ? (mx_large ? SPLIT_PAD_LARGE : SPLIT_PAD_SMALL) : kk::PAD;
   const int nb = n_basis, np = (nb + pad - 1) / pad * pad;
@@ -738,6 +812,7 @@ kk_status prepare_impl(kk_handle h, int n_atoms, const int* atom_offsets, int n_
   if (!reuse) {
     h->release();
     h->precision = precision;
+    h->bf16 = precision == KK_MIXED_BF16;
     h->natoms = n_atoms; h->nb = nb; h->np = np;
     h->kc = (nb + KSTEP - 1) / KSTEP * KSTEP;
     h->small_f64 = !mixed && np <= SMALL_NP_F64;
@@ -959,8 +1034,13 @@ kk_status krylov_graph(kk_handle h, const double* delta, int m, double tol, cons
   HIP_OR_FAIL(hipEventRecord(h->g_in, user));
   HIP_OR_FAIL(hipStreamWaitEvent(h->gstream, h->g_in, 0));
   HIP_OR_FAIL(hipMemcpyAsync(h->gdelta, delta, sizeof(double) * n2, hipMemcpyDeviceToDevice, h->gstream));
-  const long gen = h->alloc_gen * 1000003L + h->prepare_gen;
-  if (!h->gexec || h->g_K0 != K0 || h->g_m != m || h->g_tol != tol || h->g_gen != gen) {
+  // The graph bakes in buffer pointers and two prepared scalars (W and beta = 1/kT); a
+  // prepare of the same shape rewrites the buffers in place, so it keeps the graph unless
+  // one of those scalars changed.
+  if (!h->gexec || h->g_K0 != K0 || h->g_m != m || h->g_tol != tol || h->g_gen != h->alloc_gen ||
+      h->g_W != h->W || h->g_beta != h->beta) {
+    // the last replay may still be running on gstream: let it finish before its exec goes
+    HIP_OR_FAIL(hipStreamSynchronize(h->gstream));
     h->drop_graph();
     h->stream = h->gstream;
     hipError_t e = hipStreamBeginCapture(h->gstream, hipStreamCaptureModeThreadLocal);
@@ -989,7 +1069,9 @@ kk_status krylov_graph(kk_handle h, const double* delta, int m, double tol, cons
     h->g_K0 = K0;
     h->g_m = m;
     h->g_tol = tol;
-    h->g_gen = gen;
+    h->g_gen = h->alloc_gen;
+    h->g_W = h->W;
+    h->g_beta = h->beta;
   }
   HIP_OR_FAIL(hipGraphLaunch(h->gexec, h->gstream));
   HIP_OR_FAIL(hipMemcpyAsync(Kdelta, h->gkd, sizeof(double) * n2, hipMemcpyDeviceToDevice, h->gstream));
@@ -1677,6 +1759,9 @@ kk_status kk_batch_prepare(kk_batch b, int n_systems, const int* n_atoms, const 
                            const double* n_electrons, int precision) {
   if (!b) return fail(KK_EINVAL, "kk_batch_prepare: batch is NULL");
   if (n_systems < 1 || n_systems > 4096) return fail(KK_EINVAL, "kk_batch_prepare: need 1 <= n_systems <= 4096");
+  if (precision != KK_FP64 && precision != KK_MIXED_F16)
+    return fail(KK_EINVAL, "kk_batch_prepare: precision %d is not supported in batches (KK_FP64, KK_MIXED_F16)",
+                precision);
   if (!n_atoms || !atom_offsets || !S || !Z || !Q_up || !Q_dn || !eps_up || !eps_dn || !gamma || !W || !kT ||
       !n_electrons)
     return fail(KK_EINVAL, "kk_batch_prepare: NULL array argument");
@@ -1833,9 +1918,11 @@ kk_status krylov_kernel_apply_batch(kk_batch b, const double* const* delta, int 
   if ((st = upload_pointer_tables(b, delta, Kdelta))) return st;
   if (!b->tuned) {
     if ((st = autotune(b, m))) return st;
+    HIP_OR_FAIL(hipStreamSynchronize(b->stream));
     b->drop_graph();
   }
   if (b->graph_m != m) {
+    HIP_OR_FAIL(hipStreamSynchronize(b->stream));  // the last replay may still run
     b->drop_graph();
     HIP_OR_FAIL(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
     st = enqueue_update(b, m);
@@ -1872,6 +1959,24 @@ kk_status krylov_kernel_apply_batch(kk_batch b, const double* const* delta, int 
     if (singular) return fail(KK_ESINGULAR, "krylov_kernel_apply_batch: a Gram matrix is not positive definite");
     return breakdown ? KK_BREAKDOWN : KK_OK;
   }
+  g_err.clear();
+  return KK_OK;
+}
+
+kk_status kk_batch_set_tuning(kk_batch b, int small_np_max, int workgroups_per_cu) {
+  if (!b) return fail(KK_EINVAL, "kk_batch_set_tuning: batch is NULL");
+  if (!b->prepared) return fail(KK_ENOTPREPARED, "kk_batch_prepare has not succeeded on this batch");
+  if (small_np_max < 0) return fail(KK_EINVAL, "kk_batch_set_tuning: small_np_max must be >= 0");
+  if (workgroups_per_cu < 1 || workgroups_per_cu > 8)
+    return fail(KK_EINVAL, "kk_batch_set_tuning: need 1 <= workgroups_per_cu <= 8, got %d", workgroups_per_cu);
+  HIP_OR_FAIL(hipStreamSynchronize(b->stream));  // a replay may still read the tile lists
+  b->drop_graph();
+  kk_status st;
+  if ((st = build_tile_lists(b, small_np_max))) return st;
+  b->small_np_max = small_np_max;
+  b->grid_mult = workgroups_per_cu;
+  b->tuned_ms = 0.0;
+  b->tuned = true;
   g_err.clear();
   return KK_OK;
 }

@@ -25,11 +25,48 @@
 namespace kk {
 
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef float f16x __attribute__((ext_vector_type(16)));
 
+// Epilogues of the split products beyond kk_gemm.hpp's: the second (refinement) pass of the
+// BF16 form adds its product to what the first pass stored.
+enum { EPI_STORE_ADD = 6, EPI_MULLIKEN_ADD = 7 };
+
+// Products of a split pass, as a mask over the operand pairs (At piece, Bt piece) of a stage:
+// bit 0 (1, 0), bit 1 (0, 1), bit 2 (0, 0), bit 3 (1, 1).
+constexpr int PROD_F16X3 = 0x7;   // FP16: hi lo, lo hi, hi hi
+constexpr int PROD_ALL4 = 0xF;    // BF16 first pass: hi hi, hi lo, lo hi, lo lo
+constexpr int PROD_CROSS = 0x3;   // BF16 refinement pass on (hi, residual): hi res, res hi
+
+// One 32 x 32 x 16 MFMA on 16-bit operands held as raw 8-element registers.
+template <bool BF16>
+__device__ __forceinline__ f16x mfma16(const h8& a, const h8& b, const f16x& c) {
+  if constexpr (BF16)
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf8, a), __builtin_bit_cast(bf8, b), c, 0,
+                                                   0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+}
+
+// Every 16-bit operand buffer is typed _Float16; on a BF16 handle it holds BF16 bit patterns.
+template <bool BF16>
+__device__ __forceinline__ _Float16 to16(double v) {
+  if constexpr (BF16)
+    return __builtin_bit_cast(_Float16, (__bf16)(float)v);
+  else
+    return (_Float16)(float)v;
+}
+template <bool BF16>
+__device__ __forceinline__ double from16(_Float16 x) {
+  if constexpr (BF16)
+    return (double)(float)__builtin_bit_cast(__bf16, x);
+  else
+    return (double)x;
+}
+
 struct MixedItem {
-  const _Float16 *a0h, *a0l, *b0h, *b0l;  // At, Bt as hi/lo pairs, [n][n], k contiguous
-  _Float16 *yh, *yl;                      // forward: Y split at scale sc[1]
+  const _Float16 *a0h, *a0l, *b0h, *b0l;  // At, Bt as two 16-bit pieces each, [n][n], k contiguous
+  _Float16 *yh, *yl, *yr;                 // forward: Y split at scale sc[1] (yr: third BF16 piece)
   const double* g;                        // back: G (FP64)
   const double *eps, *f, *fc, *w;         // forward: spectrum
   double* xdiag;                          // forward: diag X
@@ -46,9 +83,12 @@ struct MixedArgs {
   MixedItem item[MAX_GEMM_BATCH];
 };
 
-template <int BM_, int BN_, int BK_, int WAVES_M_, int WAVES_N_, int MINB_, int FLUSH_ = 0>
+template <int BM_, int BN_, int BK_, int WAVES_M_, int WAVES_N_, int MINB_, int FLUSH_ = 0, bool BF16_ = false,
+          int PROD_ = PROD_F16X3>
 struct MixedCfg {
   static constexpr int BM = BM_, BN = BN_, BK = BK_;
+  static constexpr bool BF16 = BF16_;
+  static constexpr int PROD = PROD_;
   // FLUSH > 0: accumulate FLUSH stages in a fresh FP32 accumulator, then add it
   // to a running FP32 total (two-level summation, smaller rounding growth).
   static constexpr int FLUSH = FLUSH_;
@@ -68,9 +108,12 @@ struct MixedCfg {
 
 // Configuration of the direct-to-LDS main loop: BM x BN tile, K stage 32, a ring
 // of NS stages in LDS, one workgroup per CU.
-template <int BM_, int BN_, int WAVES_M_, int WAVES_N_, int NS_, int FLUSH_>
+template <int BM_, int BN_, int WAVES_M_, int WAVES_N_, int NS_, int FLUSH_, bool BF16_ = false,
+          int PROD_ = PROD_F16X3>
 struct MixedDlCfg {
   static constexpr bool DL = true;
+  static constexpr bool BF16 = BF16_;
+  static constexpr int PROD = PROD_;
   static constexpr int BM = BM_, BN = BN_, BK = 32, NS = NS_, FLUSH = FLUSH_;
   static constexpr int WAVES_M = WAVES_M_, WAVES_N = WAVES_N_, WAVES = WAVES_M * WAVES_N;
   static constexpr int THREADS = 64 * WAVES;
@@ -94,10 +137,15 @@ __device__ __forceinline__ unsigned char* mixed_smem() {
   return smem;
 }
 
-__device__ __forceinline__ void split_store(double v, _Float16* hi, _Float16* lo) {
-  const _Float16 h = (_Float16)(float)v;
-  *hi = h;
-  *lo = (_Float16)(float)(v - (double)h);
+// The NP 16-bit pieces of v: p0 = round(v), p1 = round(v - p0), p2 = round(v - p0 - p1).
+template <bool BF16, int NP>
+__device__ __forceinline__ void split_pieces(double v, _Float16 (&p)[NP]) {
+  double r = v;
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    p[q] = to16<BF16>(r);
+    if (q + 1 < NP) r -= from16<BF16>(p[q]);
+  }
 }
 
 // Main loop with register staging: global -> registers -> LDS (double buffer).
@@ -215,22 +263,32 @@ __device__ __forceinline__ void mixed_mainloop_lds(const MixedItem& it, const in
         bh[j] = *reinterpret_cast<const h8*>(&Bs[buf][0][r][kofs]);
         bl[j] = *reinterpret_cast<const h8*>(&Bs[buf][1][r][kofs]);
       }
-      // the three products cycle over the accumulators so no MFMA waits on the previous one
+      // the products cycle over the accumulators so no MFMA waits on the previous one
+      constexpr bool BF = Cfg::BF16;
+      if constexpr (Cfg::PROD & 8) {
 #pragma unroll
-      for (int i = 0; i < WTM; ++i)
+        for (int i = 0; i < WTM; ++i)
 #pragma unroll
-        for (int j = 0; j < WTN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(al[i], bh[j], acc[i][j], 0, 0, 0);
+          for (int j = 0; j < WTN; ++j) acc[i][j] = mfma16<BF>(al[i], bl[j], acc[i][j]);
+      }
+      if constexpr (Cfg::PROD & 1) {
 #pragma unroll
-      for (int i = 0; i < WTM; ++i)
+        for (int i = 0; i < WTM; ++i)
 #pragma unroll
-        for (int j = 0; j < WTN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+          for (int j = 0; j < WTN; ++j) acc[i][j] = mfma16<BF>(al[i], bh[j], acc[i][j]);
+      }
+      if constexpr (Cfg::PROD & 2) {
 #pragma unroll
-      for (int i = 0; i < WTM; ++i)
+        for (int i = 0; i < WTM; ++i)
 #pragma unroll
-        for (int j = 0; j < WTN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+          for (int j = 0; j < WTN; ++j) acc[i][j] = mfma16<BF>(ah[i], bl[j], acc[i][j]);
+      }
+      if constexpr (Cfg::PROD & 4) {
+#pragma unroll
+        for (int i = 0; i < WTM; ++i)
+#pragma unroll
+          for (int j = 0; j < WTN; ++j) acc[i][j] = mfma16<BF>(ah[i], bh[j], acc[i][j]);
+      }
     }
     if constexpr (Cfg::FLUSH > 0) {
       if ((kt + 1) % Cfg::FLUSH == 0 || !more) {
@@ -272,7 +330,7 @@ __device__ __forceinline__ void mixed_epilogue(const MixedItem& it, const int n,
   const double inv = it.sc[0];
   const int mw = m0 + wm * (BM / Cfg::WAVES_M) + 4 * lh;
   const int nw = n0 + wn * (BN / Cfg::WAVES_N) + l32;
-  if constexpr (EPI == EPI_STORE) {
+  if constexpr (EPI == EPI_STORE || EPI == EPI_STORE_ADD) {
     // 32 consecutive columns of one row per instruction and accumulator element
 #pragma unroll
     for (int i = 0; i < WTM; ++i)
@@ -280,9 +338,15 @@ __device__ __forceinline__ void mixed_epilogue(const MixedItem& it, const int n,
       for (int r = 0; r < 16; ++r) {
         const int m = mw + i * 32 + 8 * (r / 4) + (r % 4);
 #pragma unroll
-        for (int j = 0; j < WTN; ++j) it.x32[(size_t)m * n + nw + j * 32] = acc[i][j][r];
+        for (int j = 0; j < WTN; ++j) {
+          float* o = it.x32 + (size_t)m * n + nw + j * 32;
+          if constexpr (EPI == EPI_STORE_ADD)
+            *o += acc[i][j][r];
+          else
+            *o = acc[i][j][r];
+        }
       }
-  } else {  // EPI_MULLIKEN
+  } else {  // EPI_MULLIKEN, EPI_MULLIKEN_ADD
     const int p = tile.y * Cfg::WAVES_N + wn;
 #pragma unroll
     for (int i = 0; i < WTM; ++i)
@@ -298,7 +362,12 @@ __device__ __forceinline__ void mixed_epilogue(const MixedItem& it, const int n,
         s += __shfl_xor(s, 4);
         s += __shfl_xor(s, 8);
         s += __shfl_xor(s, 16);
-        if (l32 == 0) it.part[(size_t)p * n + m] = s;
+        if (l32 == 0) {
+          if constexpr (EPI == EPI_MULLIKEN_ADD)
+            it.part[(size_t)p * n + m] += s;
+          else
+            it.part[(size_t)p * n + m] = s;
+        }
       }
   }
 }
@@ -427,21 +496,31 @@ __device__ __forceinline__ void mixed_mainloop_dl(const MixedItem& it, const int
     }
   };
   auto mfma = [&](const h8 (&xa)[WTM][2], const h8 (&xb)[WTN][2]) __attribute__((always_inline)) {
+    constexpr bool BF = Cfg::BF16;
+    if constexpr (Cfg::PROD & 8) {
 #pragma unroll
-    for (int i = 0; i < WTM; ++i)
+      for (int i = 0; i < WTM; ++i)
 #pragma unroll
-      for (int j = 0; j < WTN; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(xa[i][1], xb[j][0], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < WTN; ++j) acc[i][j] = mfma16<BF>(xa[i][1], xb[j][1], acc[i][j]);
+    }
+    if constexpr (Cfg::PROD & 1) {
 #pragma unroll
-    for (int i = 0; i < WTM; ++i)
+      for (int i = 0; i < WTM; ++i)
 #pragma unroll
-      for (int j = 0; j < WTN; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(xa[i][0], xb[j][1], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < WTN; ++j) acc[i][j] = mfma16<BF>(xa[i][1], xb[j][0], acc[i][j]);
+    }
+    if constexpr (Cfg::PROD & 2) {
 #pragma unroll
-    for (int i = 0; i < WTM; ++i)
+      for (int i = 0; i < WTM; ++i)
 #pragma unroll
-      for (int j = 0; j < WTN; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(xa[i][0], xb[j][0], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < WTN; ++j) acc[i][j] = mfma16<BF>(xa[i][0], xb[j][1], acc[i][j]);
+    }
+    if constexpr (Cfg::PROD & 4) {
+#pragma unroll
+      for (int i = 0; i < WTM; ++i)
+#pragma unroll
+        for (int j = 0; j < WTN; ++j) acc[i][j] = mfma16<BF>(xa[i][0], xb[j][0], acc[i][j]);
+    }
   };
 
   h8 pa[WTM][2], pb[WTN][2], qa[WTM][2], qb[WTN][2];
@@ -488,7 +567,8 @@ __device__ __forceinline__ void mixed_mainloop_dl(const MixedItem& it, const int
 // One output tile over a contraction of length kc (see f64_tile); ends with a barrier.
 template <int EPI, class Cfg>
 __device__ __forceinline__ void mixed_tile(const MixedItem& it, const int n, const int kc, const int2 tile) {
-  static_assert(EPI == EPI_STORE || EPI == EPI_MULLIKEN, "split-precision epilogues");
+  static_assert(EPI == EPI_STORE || EPI == EPI_MULLIKEN || EPI == EPI_STORE_ADD || EPI == EPI_MULLIKEN_ADD,
+                "split-precision epilogues");
   const int m0 = tile.x * Cfg::BM, n0 = tile.y * Cfg::BN;
   f16x acc[Cfg::WTM][Cfg::WTN];
   if constexpr (Cfg::DL)
@@ -522,10 +602,11 @@ constexpr int SYM_B = 32;
 #endif
 constexpr int SYM_B_LARGE = KK_SYM_B_LARGE;
 constexpr int SYM_T_LARGE = SYM_B_LARGE >= 64 ? 512 : 256;
-template <int B = SYM_B, int T = 256>
+template <int B = SYM_B, int T = 256, bool BF16 = false, int NP = 2>
 __device__ __forceinline__ void fermi_symmetrize_dev(const MixedItem& it, const int n, const double beta,
                                                      const int pair) {
   static_assert(T % B == 0 && B % (T / B) == 0, "thread mapping");
+  static_assert(NP == 2 || NP == 3, "two or three pieces");
   const int nblk = n / B;
   int I = 0, rem = pair;
   while (rem >= nblk - I) {
@@ -534,7 +615,7 @@ __device__ __forceinline__ void fermi_symmetrize_dev(const MixedItem& it, const 
   }
   const int J = I + rem;
   __shared__ float At[B][B + 1];                   // block (J, I) of A
-  __shared__ _Float16 Th[B][B + 2], Tl[B][B + 2];  // Y block (I, J), transposed
+  __shared__ _Float16 Tp[NP][B][B + 2];            // Y pieces of block (I, J), transposed
   const int tx = threadIdx.x % B, ty = threadIdx.x / B;
   constexpr int RS = T / B;
   for (int r = ty; r < B; r += RS) At[r][tx] = it.x32[(size_t)(J * B + r) * n + I * B + tx];
@@ -552,26 +633,29 @@ __device__ __forceinline__ void fermi_symmetrize_dev(const MixedItem& it, const 
     } else {
       y = fermi_divided_difference(it.eps[m], it.f[m], it.fc[m], en, fn, fcn, beta) * x * sy;
     }
-    const _Float16 h = (_Float16)(float)y, l = (_Float16)(float)(y - (double)h);
-    it.yh[(size_t)m * n + c] = h;
-    it.yl[(size_t)m * n + c] = l;
-    Th[tx][r] = h;
-    Tl[tx][r] = l;
+    _Float16 pc[NP];
+    split_pieces<BF16, NP>(y, pc);
+    it.yh[(size_t)m * n + c] = pc[0];
+    it.yl[(size_t)m * n + c] = pc[1];
+    if constexpr (NP == 3) it.yr[(size_t)m * n + c] = pc[2];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) Tp[q][tx][r] = pc[q];
   }
   if (I == J) return;  // a diagonal block is symmetric by construction
   __syncthreads();
   for (int r = ty; r < B; r += RS) {
     const size_t o = (size_t)(J * B + r) * n + I * B + tx;
-    it.yh[o] = Th[r][tx];
-    it.yl[o] = Tl[r][tx];
+    it.yh[o] = Tp[0][r][tx];
+    it.yl[o] = Tp[1][r][tx];
+    if constexpr (NP == 3) it.yr[o] = Tp[2][r][tx];
   }
 }
 
 // Single system: blockIdx.x = block pair, blockIdx.y = item.
-template <int B, int T>
+template <int B, int T, bool BF16 = false, int NP = 2>
 __global__ __launch_bounds__(T) void fermi_symmetrize(const MixedArgs args) {
   if (args.stop != nullptr && *args.stop != 0) return;
-  fermi_symmetrize_dev<B, T>(args.item[blockIdx.y], args.n, args.beta, blockIdx.x);
+  fermi_symmetrize_dev<B, T, BF16, NP>(args.item[blockIdx.y], args.n, args.beta, blockIdx.x);
 }
 
 using MCfg128x128 = MixedCfg<128, 128, 32, 2, 2, 2>;
@@ -622,6 +706,23 @@ using MDl256x128w16 = MixedDlCfg<256, 128, 8, 2, 3, 8>;  // 16 waves of 32 x 64
 using MLargeCfg = KK_MLARGE_CFG;
 using MSmallCfg = KK_MSMALL_CFG;
 
+// The same tile shape with other split arithmetic (the BF16 form's two passes).
+template <class Cfg, bool BF16, int PROD>
+struct WithProducts;
+template <int BM, int BN, int WM, int WN, int NS, int FL, bool B0, int P0, bool BF16, int PROD>
+struct WithProducts<MixedDlCfg<BM, BN, WM, WN, NS, FL, B0, P0>, BF16, PROD> {
+  using type = MixedDlCfg<BM, BN, WM, WN, NS, FL, BF16, PROD>;
+};
+template <int BM, int BN, int BK, int WM, int WN, int MB, int FL, bool B0, int P0, bool BF16, int PROD>
+struct WithProducts<MixedCfg<BM, BN, BK, WM, WN, MB, FL, B0, P0>, BF16, PROD> {
+  using type = MixedCfg<BM, BN, BK, WM, WN, MB, FL, BF16, PROD>;
+};
+// BF16 form: first pass hi hi + hi lo + lo hi + lo lo, refinement pass hi res + res hi.
+using MLargeBf1 = WithProducts<MLargeCfg, true, PROD_ALL4>::type;
+using MLargeBf2 = WithProducts<MLargeCfg, true, PROD_CROSS>::type;
+using MSmallBf1 = WithProducts<MSmallCfg, true, PROD_ALL4>::type;
+using MSmallBf2 = WithProducts<MSmallCfg, true, PROD_CROSS>::type;
+
 // Padded dimension of a split-precision handle: the larger tile side of its product
 // configuration, so that the tiles cover the padded matrices exactly.
 template <class Cfg>
@@ -635,35 +736,42 @@ static_assert(MIXED_PAD_LARGE % MLargeCfg::BM == 0 && MIXED_PAD_LARGE % MLargeCf
 // ---------------------------------------------------------------------------
 // Split helpers
 
-// dst_hi/lo[r][c] = split(scale * src[r][c] (or src[c][r] if transpose)), all np x np.
+// dst_hi/lo[r][c] = split(scale * src[r][c] (or src[c][r] if transpose)), all np x np;
+// NP = 3 also writes the third piece to res (BF16 form).
+template <bool BF16 = false, int NP = 2>
 __global__ void split_matrix(const double* __restrict__ src, int np, int transpose, const double* __restrict__ scale_p,
-                             _Float16* __restrict__ hi, _Float16* __restrict__ lo) {
+                             _Float16* __restrict__ hi, _Float16* __restrict__ lo, _Float16* __restrict__ res) {
   __shared__ double t[32][33];
   const double s = *scale_p;
   const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  auto put = [&](size_t o, double v) {
+    _Float16 pc[NP];
+    split_pieces<BF16, NP>(v, pc);
+    hi[o] = pc[0];
+    lo[o] = pc[1];
+    if constexpr (NP == 3) res[o] = pc[2];
+  };
   if (transpose) {
     for (int k = ty; k < 32; k += 8) t[k][tx] = src[(size_t)(bx + k) * np + by + tx];
     __syncthreads();
-    for (int k = ty; k < 32; k += 8) {
-      const size_t o = (size_t)(by + k) * np + bx + tx;
-      split_store(s * t[tx][k], hi + o, lo + o);
-    }
+    for (int k = ty; k < 32; k += 8) put((size_t)(by + k) * np + bx + tx, s * t[tx][k]);
   } else {
     for (int k = ty; k < 32; k += 8) {
       const size_t o = (size_t)(by + k) * np + bx + tx;
-      split_store(s * src[o], hi + o, lo + o);
+      put(o, s * src[o]);
     }
   }
 }
 
 // Row-scaled split for the forward A operands: dst[r][c] = split(sc * u[c] * src[r][c]),
 // src = C^T or G^T in FP64 (row r = eigenstate, column c = orbital).
+template <bool BF16 = false, int NP = 2>
 __device__ __forceinline__ void split_scaled_columns_dev(const double* __restrict__ src, int np,
                                                          const double* __restrict__ u,
                                                          const double* __restrict__ sc_p, _Float16* __restrict__ hi,
                                                          _Float16* __restrict__ lo, const int* __restrict__ stop,
-                                                         int bx, int gdx) {
+                                                         int bx, int gdx, _Float16* __restrict__ re = nullptr) {
   if (stop != nullptr && *stop != 0) return;
   const double s = *sc_p;
   // 8 consecutive columns of one row per thread and step (np is a multiple of 128 and
@@ -674,20 +782,21 @@ __device__ __forceinline__ void split_scaled_columns_dev(const double* __restric
     const size_t base = (size_t)r * np + c0;
     const d2* sv = reinterpret_cast<const d2*>(src + base);
     const d2* uv = reinterpret_cast<const d2*>(u + c0);
-    h8 vh, vl;
+    h8 vp[NP];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const d2 v = sv[q], w = uv[q];
 #pragma unroll
       for (int e = 0; e < 2; ++e) {
-        const double x = s * w[e] * v[e];
-        const _Float16 h = (_Float16)(float)x;
-        vh[2 * q + e] = h;
-        vl[2 * q + e] = (_Float16)(float)(x - (double)h);
+        _Float16 pc[NP];
+        split_pieces<BF16, NP>(s * w[e] * v[e], pc);
+#pragma unroll
+        for (int k = 0; k < NP; ++k) vp[k][2 * q + e] = pc[k];
       }
     }
-    *reinterpret_cast<h8*>(hi + base) = vh;
-    *reinterpret_cast<h8*>(lo + base) = vl;
+    *reinterpret_cast<h8*>(hi + base) = vp[0];
+    *reinterpret_cast<h8*>(lo + base) = vp[1];
+    if constexpr (NP == 3) *reinterpret_cast<h8*>(re + base) = vp[2];
   }
 }
 

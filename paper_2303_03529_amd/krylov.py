@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(PKG_DIR, "libkrylov_kernel.so")
 
 KK_OK, KK_BREAKDOWN = 0, 1
 KK_EINVAL, KK_ENOMEM, KK_EHIP, KK_ENOTPREPARED, KK_ESINGULAR = -1, -2, -3, -4, -5
-KK_FP64, KK_MIXED_F16 = 0, 1
+KK_FP64, KK_MIXED_F16, KK_MIXED_BF16 = 0, 1, 2
 STATUS_NAMES = {0: "KK_OK", 1: "KK_BREAKDOWN", -1: "KK_EINVAL", -2: "KK_ENOMEM", -3: "KK_EHIP",
                 -4: "KK_ENOTPREPARED", -5: "KK_ESINGULAR"}
 
@@ -46,6 +46,7 @@ SIGNATURES = {
     "kk_batch_prepare": (_I, [_P, _I, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _I]),
     "krylov_kernel_apply_batch": (_I, [_P, _P, _I, _P, _P]),
     "kk_batch_tuning": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_D)]),
+    "kk_batch_set_tuning": (_I, [_P, _I, _I]),
     "kk_profile_enable": (_I, [_P, _I]),
     "kk_profile_reset": (_I, [_P]),
     "kk_profile_read": (_I, [_P, _I, ctypes.POINTER(_D), ctypes.POINTER(_I)]),
@@ -172,19 +173,21 @@ class Handle:
 
     def krylov_kernel_apply(self, delta, m: int, K0=None, out=None, info: bool = True):
         """K delta; returns (out, KrylovInfo or None). info=True synchronizes."""
+        return self._apply("krylov_kernel_apply", delta, m, K0, out, info)
+
+    def _apply(self, name, delta, m, K0, out, info):
         import torch
         n2 = 2 * self.n_atoms
         if out is None:
             out = torch.empty(n2, dtype=torch.float64, device=delta.device)
         k0p = _dev(K0, "K0", n2 * n2) if K0 is not None else ctypes.c_void_p()
+        fn = getattr(LIB, name)
         if info:
             inf = KKInfo()
-            _check(LIB.krylov_kernel_apply(self._h, _dev(delta, "delta", n2), int(m), k0p,
-                                           _dev(out, "Kdelta", n2), ctypes.byref(inf)),
-                   "krylov_kernel_apply", ok=(KK_OK, KK_BREAKDOWN, KK_ESINGULAR))
+            _check(fn(self._h, _dev(delta, "delta", n2), int(m), k0p, _dev(out, "Kdelta", n2), ctypes.byref(inf)),
+                   name, ok=(KK_OK, KK_BREAKDOWN, KK_ESINGULAR))
             return out, KrylovInfo(inf.rank_used, inf.status, inf.min_pivot, inf.max_pivot, inf.ls_residual)
-        _check(LIB.krylov_kernel_apply(self._h, _dev(delta, "delta", n2), int(m), k0p,
-                                       _dev(out, "Kdelta", n2), None), "krylov_kernel_apply")
+        _check(fn(self._h, _dev(delta, "delta", n2), int(m), k0p, _dev(out, "Kdelta", n2), None), name)
         return out, None
 
     def krylov_kernel_apply_adaptive(self, delta, m_max: int, tol: float, K0=None, out=None):
@@ -324,6 +327,11 @@ class Batch:
             return outs, [KrylovInfo(x.rank_used, x.status, x.min_pivot, x.max_pivot, x.ls_residual) for x in inf]
         _check(LIB.krylov_kernel_apply_batch(self._b, dt, int(m), ot, None), "krylov_kernel_apply_batch")
         return outs, None
+
+    def set_tuning(self, small_np_max: int, workgroups_per_cu: int):
+        """Fix the tile-class threshold and persistent workgroups per CU (no autotuning)."""
+        _check(LIB.kk_batch_set_tuning(self._b, int(small_np_max), int(workgroups_per_cu)), "kk_batch_set_tuning")
+        return self
 
     def tuning(self):
         a, g, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()

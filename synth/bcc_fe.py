@@ -204,3 +204,24 @@ def cluster_sizes(count: int = 64, seed: int = 64, lo: int = 16, hi: int = 250) 
 def krylov_vectors(n_atoms: int, count: int, seed: int) -> np.ndarray:
     """(count, 2N) iid N(0,1) direction vectors for response tests."""
     return np.random.default_rng(seed).standard_normal((count, 2 * n_atoms))
+
+
+def gradient_direction(sysd: dict, seed: int) -> dict:
+    """A seeded direction in (delta, U, W, H0) for directional-derivative checks.
+
+    delta: iid N(0, 1e-2) per entry; U and W: 10 % of their values; H0: a
+    symmetric matrix (E + E^T) / (2 sqrt(Nb)) with E iid N(0, 1), drawn in that
+    order from default_rng(seed).
+    """
+    rng = np.random.default_rng(seed)
+    nb = sysd["n_basis"]
+    dd = rng.standard_normal(2 * sysd["n_atoms"]) * 1e-2
+    E = rng.standard_normal((nb, nb))
+    dH = 0.5 * (E + E.T) / np.sqrt(nb)
+    return dict(delta=dd, U=0.1 * sysd["U"], W=0.1 * abs(sysd["W"]), H0=dH)
+
+
+def symmetric_direction(nb: int, seed: int) -> np.ndarray:
+    """(E + E^T) / (2 sqrt(Nb)), E iid N(0, 1) from default_rng(seed): a probe for matrix gradients."""
+    E = np.random.default_rng(seed).standard_normal((nb, nb))
+    return 0.5 * (E + E.T) / np.sqrt(nb)

@@ -20,7 +20,7 @@ from oracle.response import response  # noqa: E402
 from paper_2303_03529_amd import krylov  # noqa: E402
 from synth import krylov_vectors, make_system  # noqa: E402
 
-TOL = {krylov.KK_FP64: 1e-10, krylov.KK_MIXED_F16: 1e-6}
+TOL = {krylov.KK_FP64: 1e-10, krylov.KK_MIXED_F16: 1e-6, krylov.KK_MIXED_BF16: 1e-6}
 
 
 def ragged_orbitals(sysd, counts):
@@ -36,7 +36,8 @@ def ragged_orbitals(sysd, counts):
     return out
 
 
-@pytest.mark.parametrize("precision", [krylov.KK_FP64, krylov.KK_MIXED_F16], ids=["fp64", "split"])
+@pytest.mark.parametrize("precision", [krylov.KK_FP64, krylov.KK_MIXED_F16, krylov.KK_MIXED_BF16],
+                         ids=["fp64", "split", "bf16"])
 def test_single_atom(precision):
     sysd = make_system(n_atoms=1, seed=10_001)
     ep = expansion_point(sysd)
@@ -53,7 +54,8 @@ def test_single_atom(precision):
         h.close()
 
 
-@pytest.mark.parametrize("precision", [krylov.KK_FP64, krylov.KK_MIXED_F16], ids=["fp64", "split"])
+@pytest.mark.parametrize("precision", [krylov.KK_FP64, krylov.KK_MIXED_F16, krylov.KK_MIXED_BF16],
+                         ids=["fp64", "split", "bf16"])
 def test_atoms_with_different_orbital_counts(precision):
     base = make_system(2, seed=16)
     counts = np.array([1, 4, 9, 9, 4, 1, 9, 2, 9, 9, 3, 9, 5, 9, 9, 7])

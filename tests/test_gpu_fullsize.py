@@ -22,7 +22,7 @@ torch = pytest.importorskip("torch")
 if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
-from paper_2303_03529_amd.krylov import KK_FP64, KK_MIXED_F16  # noqa: E402
+from paper_2303_03529_amd.krylov import KK_FP64, KK_MIXED_BF16, KK_MIXED_F16  # noqa: E402
 from synth import make_system, krylov_vectors  # noqa: E402
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "fe1024_oracle.json")
@@ -86,15 +86,16 @@ def test_fullsize_invariants(fe1024, h64):
     assert rel(q[2], 2 * q[0] - 3 * q[1]) < 1e-12
 
 
-def test_fullsize_mixed_vs_oracle(fe1024, golden):
-    h = handle_from_device_setup(fe1024, KK_MIXED_F16)
+@pytest.mark.parametrize("precision", [KK_MIXED_F16, KK_MIXED_BF16], ids=["f16x3", "bf16"])
+def test_fullsize_mixed_vs_oracle(fe1024, golden, precision):
+    h = handle_from_device_setup(fe1024, precision)
     try:
         v = krylov_vectors(fe1024["n_atoms"], 1, golden["v_seed"])[0]
         q = h.density_response_batch(t(v)).cpu().numpy()[0]
         got, info = h.krylov_kernel_apply(t(fe1024["delta"]), golden["rank"])
         e_q = rel(q, golden["q1"])
         e_k = rel(got.cpu().numpy(), golden["Kdelta"])
-        print(f"1024-atom split-precision errors: response {e_q:.2e}, kernel {e_k:.2e}")
+        print(f"1024-atom split-precision ({precision}) errors: response {e_q:.2e}, kernel {e_k:.2e}")
         assert e_q < TOL_MIXED and e_k < TOL_MIXED
     finally:
         h.close()

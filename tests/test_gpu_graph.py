@@ -21,7 +21,7 @@ from oracle.krylov import kernel_apply  # noqa: E402
 from paper_2303_03529_amd import krylov  # noqa: E402
 from synth import make_system  # noqa: E402
 
-TOL = {krylov.KK_FP64: 1e-10, krylov.KK_MIXED_F16: 1e-6}
+TOL = {krylov.KK_FP64: 1e-10, krylov.KK_MIXED_F16: 1e-6, krylov.KK_MIXED_BF16: 1e-6}
 SAME = 1e-13  # both paths run the same kernels on the same inputs
 
 
@@ -43,7 +43,8 @@ def close(a, b):
     return float(np.linalg.norm(a - b)) <= SAME * float(np.linalg.norm(b))
 
 
-@pytest.mark.parametrize("precision", [krylov.KK_FP64, krylov.KK_MIXED_F16], ids=["fp64", "split"])
+@pytest.mark.parametrize("precision", [krylov.KK_FP64, krylov.KK_MIXED_F16, krylov.KK_MIXED_BF16],
+                         ids=["fp64", "split", "bf16"])
 def test_graph_replays_match_launch_by_launch(precision):
     sysd = make_system(2, seed=16)
     ep = expansion_point(sysd)

@@ -7,7 +7,7 @@ import scipy.sparse.linalg as spla
 from oracle.expansion import congruence_cholesky, expansion_point
 from oracle.krylov import kernel_apply
 from oracle.response import response
-from oracle.scf import net_q_of_n, rms, scf, xlbomd_update
+from oracle.scf import net_q_of_n, rms, scf, xlbomd_electrons, xlbomd_update
 from synth import make_system
 
 
@@ -84,3 +84,19 @@ def test_xlbomd_update_dissipation_term():
     got = xlbomd_update(hist, Kf, 1.3, 0.01, c)
     want = 2 * hist[0] - hist[1] - 1.3 * Kf + 0.01 * (0.5 * hist[0] - hist[1] + 0.25 * hist[2] + 2 * hist[3])
     assert np.abs(got - want).max() < 1e-14
+
+
+def test_xlbomd_electrons_full_rank_kernel_has_period_six():
+    """Near the ground state f(n) ~ J (n - n*). With the exact kernel (full rank, K f = J^-1 f =
+    n - n*) and kappa = 1 the update gives e_{k+1} = e_k - e_{k-1} for e = n - n*: a rotation by
+    60 degrees. Started at rest (e_{-1} = e_0) the sequence is e_0, 0, -e_0, -e_0, 0, e_0, e_0,
+    and so are the residuals f_k ~ J e_k, up to O(|e|^2) from the nonlinearity."""
+    sysd = make_system(2, seed=16)
+    n_star, _ = scf(sysd, sysd["n_ref"], tol=1e-12, max_iter=60, m_max=8, rank_tol=0.1, switch_at=10.0)
+    e0 = 1e-5 * np.random.default_rng(5).standard_normal(n_star.size)
+    res, fs, _ = xlbomd_electrons(sysd, n_star + e0, steps=7, kappa=1.0, m_max=2 * sysd["n_atoms"], rank_tol=0.0)
+    f0 = fs[0]
+    nf = np.linalg.norm(f0)
+    for k, sign in enumerate((1, 0, -1, -1, 0, 1, 1)):
+        assert np.linalg.norm(fs[k] - sign * f0) < 1e-4 * nf, (k, np.linalg.norm(fs[k] - sign * f0) / nf)
+    assert abs(res[0] - rms(f0)) == 0.0

@@ -8,10 +8,13 @@ a (q[n_old] - n_old); the kernel mixer starts once the charge error is below
 
 Every step runs in the HIP library: the ground-state map q[n]
 (kk_ground_state_charges after kk_prepare), the kernel
-(krylov_kernel_apply_adaptive) and the extended-Lagrangian update
-(kk_xlbomd_update). The caller side (DeviceSystem) builds and diagonalizes
-the spin Hamiltonians. Charges are net Mulliken charges (neutral-atom
-valence subtracted, Sec. III.A); the host only keeps the loop and the
+(krylov_kernel_apply_adaptive) and the n updates (kk_xlbomd_update: the
+extended-Lagrangian step, and the SCF mixer steps as that update with
+n(t - dt) = n(t), alpha = 0, so 2 n - n - kappa v = n - kappa v: kappa = 1,
+v = K f for the kernel mixer; kappa = -a, v = f for the linear one). The
+caller side (DeviceSystem) builds and diagonalizes the spin Hamiltonians.
+Charges are net Mulliken charges (neutral-atom valence subtracted,
+Sec. III.A); the host only keeps the loop, the residual q[n] - n and the
 convergence test.
 """
 
@@ -31,6 +34,11 @@ def net_charges(handle, valence_t) -> torch.Tensor:
     return handle.ground_state_charges(valence_t)
 
 
+def mixer_step(handle, n, v, kappa: float, zero1) -> torch.Tensor:
+    """n - kappa v through kk_xlbomd_update with a one-row history (n(t - dt) = n(t), alpha = 0)."""
+    return handle.xlbomd_update(n[None, :].contiguous(), v.contiguous(), kappa, 0.0, zero1)
+
+
 def scf(sysd: dict, n0, mixer: str = "kernel", tol: float = 1e-8, max_iter: int = 100, m_max: int = 8,
         rank_tol: float = 0.1, linear_coeff: float = 0.06, switch_at: float = 0.05,
         precision: int = krylov.KK_FP64, device: str = "cuda"):
@@ -39,6 +47,7 @@ def scf(sysd: dict, n0, mixer: str = "kernel", tol: float = 1e-8, max_iter: int 
     h = krylov.Handle()
     valence = torch.as_tensor(sysd["valence"], dtype=torch.float64, device=device)
     n = torch.as_tensor(np.asarray(n0, dtype=np.float64), device=device).clone()
+    zero1 = torch.zeros(1, dtype=torch.float64, device=device)
     hist = []
     try:
         for _ in range(max_iter):
@@ -50,11 +59,11 @@ def scf(sysd: dict, n0, mixer: str = "kernel", tol: float = 1e-8, max_iter: int 
                 break
             if mixer == "linear" or err > switch_at:
                 hist.append(dict(rms=err, rank=0, mode="linear"))
-                n = n + linear_coeff * f
+                n = mixer_step(h, n, f, -linear_coeff, zero1)
                 continue
             Kf, info = h.krylov_kernel_apply_adaptive(f.contiguous(), m_max, rank_tol)
             hist.append(dict(rms=err, rank=info.rank_used, mode="kernel", ls_residual=info.ls_residual))
-            n = n - Kf
+            n = mixer_step(h, n, Kf, 1.0, zero1)
     finally:
         h.close()
     return n.cpu().numpy(), hist
@@ -62,12 +71,13 @@ def scf(sysd: dict, n0, mixer: str = "kernel", tol: float = 1e-8, max_iter: int 
 
 def xlbomd_electrons(sysd: dict, n_start, steps: int, kappa: float, alpha: float = 0.0, c=(1.0,),
                      m_max: int = 4, rank_tol: float = 0.1, precision: int = krylov.KK_FP64,
-                     device: str = "cuda"):
+                     device: str = "cuda", return_residuals: bool = False):
     """Propagate n with the extended-Lagrangian update at fixed nuclei.
 
     n(t) and its history start at n_start. Each step prepares q[n(t)], applies
     the adaptive-rank kernel to f = q[n] - n and calls kk_xlbomd_update.
-    Returns the rms residual per step.
+    Returns the rms residual per step and the final n (and, with
+    return_residuals, the residual vectors per step).
     """
     ds = DeviceSystem(sysd, device)
     h = krylov.Handle()
@@ -77,18 +87,21 @@ def xlbomd_electrons(sysd: dict, n_start, steps: int, kappa: float, alpha: float
     hist = n0.repeat(kmax + 1, 1).contiguous()           # rows n(t - k dt)
     cc = torch.zeros(kmax + 1, dtype=torch.float64, device=device)
     cc[: len(c)] = torch.as_tensor(c, dtype=torch.float64)
-    out = []
+    out, fs = [], []
     try:
         for _ in range(steps):
             n = hist[0].contiguous()
             ds.prepare(h, n, precision)
             f = (net_charges(h, valence) - n).contiguous()
             out.append(float(torch.sqrt(torch.mean(f * f))))
+            fs.append(f.cpu().numpy())
             Kf, _ = h.krylov_kernel_apply_adaptive(f, m_max, rank_tol)
             n_new = h.xlbomd_update(hist, Kf, kappa, alpha, cc)
             hist = torch.cat([n_new[None, :], hist[:-1]], dim=0).contiguous()
     finally:
         h.close()
+    if return_residuals:
+        return out, hist[0].cpu().numpy(), fs
     return out, hist[0].cpu().numpy()
 
 

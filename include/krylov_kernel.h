@@ -162,6 +162,26 @@ kk_status krylov_kernel_apply(kk_handle h, const double *delta, int m, const dou
                               double *Kdelta, kk_info *info);
 
 /*
+ * krylov_kernel_apply_noalloc -- krylov_kernel_apply for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc). Same arguments, result and errors as
+ * krylov_kernel_apply on a prepared handle, but the call itself allocates
+ * nothing (no hipMalloc or hipFree, no library routine that allocates, no graph
+ * of its own): the one-direction response workspace comes from a fixed 48 MiB
+ * device array of the library, which every GPU holds until the process ends,
+ * and the launches go straight onto the handle's stream. A handle whose
+ * workspace does not fit is refused with KK_EINVAL before anything is enqueued
+ * (handles of Nb <= 1152, e.g. 128-atom bcc Fe, fit in every precision; FP64
+ * up to Nb = 1664, KK_MIXED_F16 up to 1408). kk_prepare still allocates the
+ * handle's prepared state.
+ * All calls on one GPU share that array and it keeps the last call's contents:
+ * calls that overlap on one GPU (two streams, or two threads) race, so the
+ * caller orders them. Kernel timing (kk_profile_enable) records as usual.
+ */
+kk_status krylov_kernel_apply_noalloc(kk_handle h, const double *delta, int m, const double *K0,
+                                      double *Kdelta, kk_info *info);
+
+/*
  * krylov_kernel_apply_adaptive -- the same kernel with the rank chosen on the
  * device: directions are added one at a time (at most m_max) and the expansion
  * stops as soon as the projected residual ||F~ c - f~|| / ||f~|| is <= tol, the

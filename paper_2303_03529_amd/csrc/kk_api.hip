@@ -22,6 +22,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1156,6 +1157,148 @@ kk_status kk_profile_read(kk_handle h, int kernel_id, double* total_ms, int* lau
   }
   *total_ms = tot;
   *launches = cnt;
+  return KK_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Allocation-free update (krylov_kernel_apply_noalloc).
+//
+// The response workspace of one direction (potentials, Y or its split-precision
+// operands, diag X, Mulliken partial rows) lives in a fixed device array instead of
+// handle memory the library allocates on first use. Every GPU that loads the library
+// holds its own copy of the array until the process ends; host code reaches it only
+// through the address hipGetSymbolAddress returns for the current device.
+
+namespace {
+
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(48) << 20;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of this device's scratch array (looked up once per device).
+kk_status scratch_for_current_device(void** out) {
+  int dev = 0;
+  HIP_OR_FAIL(hipGetDevice(&dev));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(KK_EINVAL, "device %d beyond the supported %d", dev, NOALLOC_MAX_DEVICES);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr) {
+      (void)hipGetLastError();
+      return fail(KK_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return KK_OK;
+}
+
+// Carves the one-direction response workspace of h out of a scratch region of `cap`
+// bytes (sub-buffers 256-byte aligned). With base = nullptr only the size is computed.
+struct ScratchLayout {
+  size_t bytes = 0;
+  double *u = nullptr, *Y = nullptr, *xdiag = nullptr, *part = nullptr, *msc = nullptr;
+  _Float16 *uct_h = nullptr, *uct_l = nullptr, *uct_r = nullptr, *yh = nullptr, *yl = nullptr, *yr = nullptr;
+  float* x32 = nullptr;
+};
+
+ScratchLayout scratch_layout(kk_handle h, unsigned char* base) {
+  ScratchLayout L;
+  const size_t np = h->np, items = 2, np2 = np * np;
+  auto take = [&](size_t nbytes) -> void* {
+    void* p = base ? base + L.bytes : nullptr;
+    L.bytes += (nbytes + 255) / 256 * 256;
+    return p;
+  };
+  L.u = static_cast<double*>(take(items * np * sizeof(double)));
+  if (h->precision == KK_FP64) {
+    L.Y = static_cast<double*>(take(items * np2 * sizeof(double)));
+  } else {
+    L.uct_h = static_cast<_Float16*>(take(items * np2 * sizeof(_Float16)));
+    L.uct_l = static_cast<_Float16*>(take(items * np2 * sizeof(_Float16)));
+    L.yh = static_cast<_Float16*>(take(items * np2 * sizeof(_Float16)));
+    L.yl = static_cast<_Float16*>(take(items * np2 * sizeof(_Float16)));
+    if (h->bf16) {
+      L.uct_r = static_cast<_Float16*>(take(items * np2 * sizeof(_Float16)));
+      L.yr = static_cast<_Float16*>(take(items * np2 * sizeof(_Float16)));
+    }
+    L.x32 = static_cast<float*>(take(items * np2 * sizeof(float)));
+    L.msc = static_cast<double*>(take(items * 8 * sizeof(double)));
+  }
+  L.xdiag = static_cast<double*>(take(items * np * sizeof(double)));
+  L.part = static_cast<double*>(take(items * (size_t)h->nparts * np * sizeof(double)));
+  return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+kk_status krylov_kernel_apply_noalloc(kk_handle h, const double* delta, int m, const double* K0, double* Kdelta,
+                                      kk_info* info) {
+  const char* who = "krylov_kernel_apply_noalloc";
+  kk_status st = check_handle(h);
+  if (st) return st;
+  const int n2 = 2 * h->natoms;
+  if (!delta || !Kdelta) return fail(KK_EINVAL, "%s: NULL array argument", who);
+  if (m < 1 || m > std::min(n2, kk::MAX_RANK))
+    return fail(KK_EINVAL, "%s: need 1 <= m <= min(2N, %d), got %d", who, kk::MAX_RANK, m);
+  const size_t need = scratch_layout(h, nullptr).bytes;
+  if (need > NOALLOC_SCRATCH_BYTES)
+    return fail(KK_EINVAL, "%s: this handle needs %zu bytes of scratch, above the fixed %zu (padded size %d)", who,
+                need, NOALLOC_SCRATCH_BYTES, h->np);
+  void* base = nullptr;
+  if ((st = scratch_for_current_device(&base))) return st;
+  const ScratchLayout L = scratch_layout(h, static_cast<unsigned char*>(base));
+
+  // Point the handle's one-direction workspace at the scratch for this call only.
+  struct Saved {
+    int chunk_cap;
+    double *u, *Y, *xdiag, *part, *msc;
+    _Float16 *uct_h, *uct_l, *uct_r, *yh, *yl, *yr;
+    float* x32;
+  } sv{h->chunk_cap, h->u, h->Y, h->xdiag, h->part, h->msc, h->uct_h, h->uct_l, h->uct_r, h->yh, h->yl, h->yr,
+       h->x32};
+  h->chunk_cap = 1;
+  h->u = L.u; h->Y = L.Y; h->xdiag = L.xdiag; h->part = L.part; h->msc = L.msc;
+  h->uct_h = L.uct_h; h->uct_l = L.uct_l; h->uct_r = L.uct_r; h->yh = L.yh; h->yl = L.yl; h->yr = L.yr;
+  h->x32 = L.x32;
+  // the padded tail of the potentials must read zero; the scratch holds the last call's data
+  st = zero(h, h->u, (size_t)2 * h->np);
+  if (!st) st = enqueue_krylov(h, delta, m, 0.0, K0, Kdelta);
+  h->chunk_cap = sv.chunk_cap;
+  h->u = sv.u; h->Y = sv.Y; h->xdiag = sv.xdiag; h->part = sv.part; h->msc = sv.msc;
+  h->uct_h = sv.uct_h; h->uct_l = sv.uct_l; h->uct_r = sv.uct_r; h->yh = sv.yh; h->yl = sv.yl; h->yr = sv.yr;
+  h->x32 = sv.x32;
+  if (st) return st;
+  h->fwd_valid = true;
+  h->fwd_m = m;
+  h->fwd_K0 = K0;
+  if (info) {
+    kk::KrylovState hs;
+    HIP_OR_FAIL(hipMemcpyAsync(&hs, h->kst, sizeof hs, hipMemcpyDeviceToHost, h->stream));
+    HIP_OR_FAIL(hipStreamSynchronize(h->stream));
+    info->rank_used = hs.rank;
+    info->status = hs.status;
+    info->min_pivot = hs.min_pivot;
+    info->max_pivot = hs.max_pivot;
+    info->ls_residual = hs.ls_residual;
+    g_err.clear();
+    if (hs.status == KK_ESINGULAR) return fail(KK_ESINGULAR, "%s: Gram matrix not positive definite", who);
+    return hs.status == 1 ? KK_BREAKDOWN : KK_OK;
+  }
+  g_err.clear();
   return KK_OK;
 }
 

@@ -37,6 +37,7 @@ SIGNATURES = {
     "mulliken_project": (_I, [_P, _I, _P, _P, _P]),
     "krylov_kernel_apply": (_I, [_P, _P, _I, _P, _P, _P]),
     "krylov_kernel_apply_adaptive": (_I, [_P, _P, _I, _D, _P, _P, _P]),
+    "krylov_kernel_apply_noalloc": (_I, [_P, _P, _I, _P, _P, _P]),
     "kk_ground_state_charges": (_I, [_P, _P, _P]),
     "kk_xlbomd_update": (_I, [_P, _P, _I, _P, _D, _D, _P, _P]),
     "krylov_kernel_adjoint": (_I, [_P, _P, _I, _P, _P, _I, _P, _P, _P, _P, _P, _P, _P]),
@@ -174,6 +175,11 @@ class Handle:
     def krylov_kernel_apply(self, delta, m: int, K0=None, out=None, info: bool = True):
         """K delta; returns (out, KrylovInfo or None). info=True synchronizes."""
         return self._apply("krylov_kernel_apply", delta, m, K0, out, info)
+
+    def krylov_kernel_apply_noalloc(self, delta, m: int, K0=None, out=None, info: bool = True):
+        """K delta through the entry point that allocates nothing (out must be given
+        to avoid allocating it here); returns (out, KrylovInfo or None)."""
+        return self._apply("krylov_kernel_apply_noalloc", delta, m, K0, out, info)
 
     def _apply(self, name, delta, m, K0, out, info):
         import torch

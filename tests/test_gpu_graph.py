@@ -101,3 +101,32 @@ def test_graph_with_reverse_pass_and_second_prepare():
         assert rel(kd3.cpu().numpy(), kernel_apply(other, ep2, other["delta"], 6)) < TOL[krylov.KK_FP64]
     finally:
         h.close()
+
+
+def test_graph_recapture_without_host_sync():
+    """Calls that change the rank (a new capture) or re-prepare the handle, issued back to back
+    with no host synchronization in between, while the previous replay is still running (a
+    128-atom update takes milliseconds): every result must equal the launch-by-launch one.
+    A re-prepare of the same shape with the same W and kT keeps the graph; another W recaptures."""
+    sysd = make_system(4, seed=128)
+    ep = expansion_point(sysd)
+    h = handle_from_expansion(sysd, ep, krylov.KK_FP64)
+    try:
+        delta = t(sysd["delta"])
+        args = (sysd["offsets"], t(sysd["S"]), t(ep["Z"]), t(ep["Q"][0]), t(ep["Q"][1]), t(ep["eps"][0]),
+                t(ep["eps"][1]), t(sysd["gamma"]))
+        plan = [(8, 1.0), (6, 1.0), (8, 1.0), (5, 1.0), (8, 1.05), (8, 1.05), (6, 1.0)]
+        outs = []
+        for m, wscale in plan:
+            if wscale != 1.0 or (outs and plan[len(outs) - 1][1] != wscale):
+                h.prepare(*args, sysd["W"] * wscale, sysd["kT"], sysd["n_electrons"], krylov.KK_FP64)
+            o = torch.empty_like(delta)
+            h.krylov_kernel_apply(delta, m, out=o, info=False)   # returns with the replay in flight
+            outs.append(o)
+        torch.cuda.synchronize()
+        for (m, wscale), o in zip(plan, outs):
+            h.prepare(*args, sysd["W"] * wscale, sysd["kT"], sysd["n_electrons"], krylov.KK_FP64)
+            ref, _ = launch_by_launch(h, delta, m)
+            assert close(o, ref), (m, wscale)
+    finally:
+        h.close()

@@ -31,6 +31,7 @@
 #include "kk_kernels.hpp"
 #include "kk_gemm_mixed.hpp"
 #include "kk_adjoint.hpp"
+#include "kk_fused.hpp"
 
 namespace {
 
@@ -94,7 +95,6 @@ static_assert(KSTEP % kk::FwdCfg::BK == 0 && KSTEP % kk::BackCfg::BK == 0 && KST
                   KSTEP % SmallF64::BK == 0 && KSTEP % kk::MLargeCfg::BK == 0 && KSTEP % kk::MSmallCfg::BK == 0 &&
                   KSTEP % SmallMx::BK == 0 && kk::PAD % KSTEP == 0,
               "KSTEP must be a multiple of every K stage and divide the padding");
-constexpr int MAX_CHUNK = kk::MAX_GEMM_BATCH / 2;  // directions per GEMM launch
 constexpr size_t WORKSPACE_BUDGET = size_t(12) << 30;  // bytes of Y workspace per handle
 constexpr int MAX_EVENTS = 8192;
 
@@ -105,6 +105,10 @@ struct kk_handle_s {
   bool prepared = false;
   int natoms = 0, nb = 0, np = 0, nparts = 0;
   int kc = 0;  // contraction length of the transforms: nb rounded up to KSTEP (<= np)
+  // K-split of the response transforms (choose_ksplit): the forward in kch chunks of kck rows,
+  // the back-transform in kchb (FP64: kch; split forms: 1), nbase Mulliken partial rows per
+  // back chunk (nparts = kchb nbase)
+  int kch = 1, kchb = 1, kck = 0, nbase = 0;
   double W = 0, kT = 0, beta = 0, n_e = 0;
   std::vector<void*> owned;  // every device allocation of the prepared state
 
@@ -138,6 +142,8 @@ struct kk_handle_s {
   _Float16 *yh = nullptr, *yl = nullptr, *yr = nullptr;
   double* msc = nullptr;
   double* mscratch = nullptr;  // 4 np doubles: row statistics for the split scales
+  double* cvec = nullptr;      // 2N: centring vector of the fused small-system step (kk_fused.hpp)
+  double* pmax = nullptr;      // 2 per block of the fused step: largest centred potentials
 
   // response workspace (grown on demand)
   int chunk_cap = 0;
@@ -296,6 +302,35 @@ int cu_count() {
   return cus;
 }
 
+// K-split of the response transforms of one small system. When the two items of a
+// transform (one per spin) have fewer tiles than the chip has CUs, each item's contraction
+// is cut into c chunks of kck rows (a multiple of KSTEP, at least KSPLIT_MIN_K, all c chunks
+// inside the padding, whose rows past kc are zero); every chunk is a GEMM item of its own
+// and the partial results are summed in a fixed order afterwards (forward: by the
+// symmetrizing pass; back: by combine, as further Mulliken partial rows). c minimizes the
+// per-CU work ceil(2 tiles c / CUs) / c and is taken when that is at most 3/4 of the
+// unsplit figure. At Nb = 1152 (81 tiles of 128 x 128 per spin, 162 for 256 CUs) c = 3.
+constexpr int KSPLIT_MAX = 4, KSPLIT_MIN_K = 128;
+int choose_ksplit(int np, int kc, int tiles, int cus, int* chunk_rows) {
+  *chunk_rows = kc;
+  if (2 * tiles > cus) return 1;
+  auto load = [&](int c) { return (double)((2 * tiles * c + cus - 1) / cus) / c; };
+  int best = 1;
+  for (int c = 2; c <= KSPLIT_MAX; ++c) {
+    const int ck = ((kc + c - 1) / c + KSTEP - 1) / KSTEP * KSTEP;
+    if (ck < KSPLIT_MIN_K || c * ck > np) continue;
+    if (load(c) < load(best)) {
+      best = c;
+      *chunk_rows = ck;
+    }
+  }
+  if (load(best) > 0.75 * load(1)) {
+    *chunk_rows = kc;
+    return 1;
+  }
+  return best;
+}
+
 // Form of the FP64 forward transform of one direction (both spins): the upper
 // tiles over two K halves with the Fermi product in the epilogue, or all tiles
 // over one half (half the cost each) followed by fermi_symmetrize_f64. The full
@@ -345,6 +380,48 @@ struct ProfileScope {
   }
 };
 
+// Symmetrizing passes of the small-system forward transforms over nch partial products
+// (kk_fused.hpp; nch = 1: the unsplit product), 32 x 32 block pairs of 256 threads.
+template <int NCH>
+void sym_f64_launch(kk_handle h, const kk::GemmArgs& sa, size_t cstride) {
+  const int nblk = sa.n / kk::SYM64_B;
+  kk::fermi_symmetrize_f64_chunks<kk::SYM64_B, 256, NCH>
+      <<<dim3(nblk * (nblk + 1) / 2, sa.nitems), 256, 0, h->stream>>>(sa, cstride);
+}
+kk_status launch_sym_f64(kk_handle h, const kk::GemmArgs& sa, int nch, size_t cstride) {
+  switch (nch) {
+    case 1: sym_f64_launch<1>(h, sa, cstride); break;
+    case 2: sym_f64_launch<2>(h, sa, cstride); break;
+    case 3: sym_f64_launch<3>(h, sa, cstride); break;
+    case 4: sym_f64_launch<4>(h, sa, cstride); break;
+    default: return fail(KK_EINVAL, "internal: K-split into %d chunks", nch);
+  }
+  LAUNCH_CHECK("fermi_symmetrize_f64_chunks");
+  return KK_OK;
+}
+template <bool BF16, int NP, int NCH>
+void sym_mixed_launch(kk_handle h, const kk::MixedArgs& sa, size_t cstride) {
+  const int nblk = sa.n / kk::SYM_B;
+  kk::fermi_symmetrize_chunks<kk::SYM_B, 256, BF16, NP, NCH>
+      <<<dim3(nblk * (nblk + 1) / 2, sa.nitems), 256, 0, h->stream>>>(sa, cstride);
+}
+template <bool BF16, int NP>
+kk_status launch_sym_mixed_t(kk_handle h, const kk::MixedArgs& sa, int nch, size_t cstride) {
+  switch (nch) {
+    case 1: sym_mixed_launch<BF16, NP, 1>(h, sa, cstride); break;
+    case 2: sym_mixed_launch<BF16, NP, 2>(h, sa, cstride); break;
+    case 3: sym_mixed_launch<BF16, NP, 3>(h, sa, cstride); break;
+    case 4: sym_mixed_launch<BF16, NP, 4>(h, sa, cstride); break;
+    default: return fail(KK_EINVAL, "internal: K-split into %d chunks", nch);
+  }
+  LAUNCH_CHECK("fermi_symmetrize_chunks");
+  return KK_OK;
+}
+kk_status launch_sym_mixed(kk_handle h, const kk::MixedArgs& sa, int nch, size_t cstride) {
+  return h->bf16 ? launch_sym_mixed_t<true, 3>(h, sa, nch, cstride)
+                 : launch_sym_mixed_t<false, 2>(h, sa, nch, cstride);
+}
+
 kk_status launch_gemm(kk_handle h, int epi, kk::GemmArgs& a, bool small = false) {
   const int grid = a.ntiles * a.nitems;
   if (grid <= 0) return KK_OK;
@@ -365,8 +442,8 @@ kk_status launch_gemm(kk_handle h, int epi, kk::GemmArgs& a, bool small = false)
       kk::gemm_f64<kk::EPI_XSTORE, kk::BackCfg><<<grid, kk::BackCfg::THREADS, 0, h->stream>>>(a);
     LAUNCH_CHECK("gemm_f64");
     if (small) {
-      const int nblk = a.n / kk::SYM64_B;
-      kk::fermi_symmetrize_f64<kk::SYM64_B, 256><<<dim3(nblk * (nblk + 1) / 2, a.nitems), 256, 0, h->stream>>>(a);
+      kk_status st = launch_sym_f64(h, a, 1, 0);
+      if (st) return st;
     } else {
       const int nblk = a.n / kk::SYM64_B_LARGE;
       kk::fermi_symmetrize_f64<kk::SYM64_B_LARGE, kk::SYM64_T_LARGE>
@@ -396,15 +473,16 @@ kk_status ensure_workspace(kk_handle h, int chunk) {
   h->free_workspace();
   kk_status st;
   if ((st = dalloc_t(h, &h->u, items * np, true))) return st;
+  const size_t kch = h->kch;  // K-split: one partial product per chunk
   if (h->precision == KK_FP64) {
-    if ((st = dalloc_t(h, &h->Y, items * np * np, true))) return st;
+    if ((st = dalloc_t(h, &h->Y, items * kch * np * np, true))) return st;
   } else {
     for (_Float16** q : {&h->uct_h, &h->uct_l, &h->yh, &h->yl})
       if ((st = dalloc_t(h, q, items * np * np, true))) return st;
     if (h->bf16)
       for (_Float16** q : {&h->uct_r, &h->yr})
         if ((st = dalloc_t(h, q, items * np * np, true))) return st;
-    if ((st = dalloc_t(h, &h->x32, items * np * np, true))) return st;
+    if ((st = dalloc_t(h, &h->x32, items * kch * np * np, true))) return st;
     if ((st = dalloc_t(h, &h->msc, items * 8, true))) return st;
   }
   if ((st = dalloc_t(h, &h->xdiag, items * np, true))) return st;
@@ -415,28 +493,68 @@ kk_status ensure_workspace(kk_handle h, int chunk) {
 }
 
 int max_chunk(kk_handle h) {
-  // FP64: one Y per spin; split path: four (BF16: six) 16-bit matrices and one FP32 per spin
+  // FP64: one Y per spin and chunk; split path: four (BF16: six) 16-bit matrices per spin and
+  // one FP32 per spin and chunk
+  const size_t kch = h->kch;
   const size_t per_dir = (size_t)2 * h->np * h->np *
-                         (h->precision == KK_FP64 ? sizeof(double)
-                                                  : (h->bf16 ? 6 : 4) * sizeof(_Float16) + sizeof(float));
+                         (h->precision == KK_FP64 ? kch * sizeof(double)
+                                                  : (h->bf16 ? 6 : 4) * sizeof(_Float16) + kch * sizeof(float));
   size_t c = WORKSPACE_BUDGET / std::max<size_t>(per_dir, 1);
-  return (int)std::max<size_t>(1, std::min<size_t>(c, MAX_CHUNK));
+  return (int)std::max<size_t>(1, std::min<size_t>(c, kk::MAX_GEMM_BATCH / (2 * kch)));
 }
 
-// Responses of `batch` directions v (batch x 2N) into q1 (batch x 2N); batch <= chunk_cap.
-// identity = true: potentials v_q +/- v_m per atom (gamma = I, W = 1), the transposed-response
-// form the reverse pass needs.
-kk_status response_chunk(kk_handle h, int batch, const double* v, double* q1, const int* stop,
-                         bool identity = false) {
-  const int N = h->natoms, np = h->np;
-  {
-    const int waves = N * batch, threads = 256;
-    const int blocks = (waves * kk::WAVE + threads - 1) / threads;
-    kk::potentials<<<blocks, threads, 0, h->stream>>>(identity ? nullptr : h->gamma, N, identity ? 1.0 : h->W, v,
-                                                       batch, h->offsets, np,
-                                                       h->u, stop);
-    LAUNCH_CHECK("potentials");
+// K-split FP64 transforms (choose_ksplit) of `batch` directions whose potentials are in h->u:
+// the forward as kch full-tile partial products per item into Y (chunk j of item z at
+// Y + (z kch + j) np^2), summed and symmetrized into the first; the back-transform as kch
+// partial Mulliken products per item, rows j nbase .. (j + 1) nbase - 1 of the item's partials.
+kk_status ksplit_transforms_f64(kk_handle h, int batch, const int* stop) {
+  const int np = h->np, kch = h->kch, ck = h->kck;
+  const size_t np2 = (size_t)np * np;
+  kk::GemmArgs fa{}, sa{}, ba{};
+  fa.n = np; fa.k_half = ck; fa.two_halves = 0; fa.ntiles = h->n_full; fa.nitems = 2 * batch * kch;
+  fa.tiles = h->tiles_full; fa.stop = stop; fa.beta = h->beta;
+  sa = fa;
+  sa.nitems = 2 * batch;
+  ba = fa;
+  for (int z = 0; z < 2 * batch; ++z) {
+    const int s = z & 1;
+    double* Y0 = h->Y + (size_t)z * kch * np2;
+    kk::GemmItem& si = sa.item[z];
+    si = kk::GemmItem{};
+    si.out = Y0; si.eps = h->eps[s]; si.f = h->f[s]; si.fc = h->fc[s]; si.w = h->w[s];
+    si.xdiag = h->xdiag + (size_t)z * np;
+    for (int j = 0; j < kch; ++j) {
+      const size_t k0 = (size_t)j * ck;
+      kk::GemmItem& fi = fa.item[z * kch + j];
+      fi = kk::GemmItem{};
+      fi.a0 = h->C[s] + k0 * np; fi.b0 = h->G[s] + k0 * np; fi.scale = h->u + (size_t)z * np + k0;
+      fi.out = Y0 + j * np2;
+      kk::GemmItem& bi = ba.item[z * kch + j];
+      bi = kk::GemmItem{};
+      bi.a0 = h->CT[s] + k0 * np; bi.b0 = Y0 + k0 * np; bi.g = h->G[s];
+      bi.part = h->part + ((size_t)z * h->nparts + (size_t)j * h->nbase) * np;
+    }
   }
+  if (fa.nitems > kk::MAX_GEMM_BATCH) return fail(KK_EINVAL, "internal: too many GEMM items");
+  {
+    ProfileScope ps(h, 0);
+    kk::gemm_f64<kk::EPI_XSTORE, kk::BackCfg><<<fa.ntiles * fa.nitems, kk::BackCfg::THREADS, 0, h->stream>>>(fa);
+    LAUNCH_CHECK("gemm_f64 k-split");
+    kk_status st = launch_sym_f64(h, sa, kch, np2);
+    if (st) return st;
+  }
+  {
+    ProfileScope ps(h, 1);
+    kk::gemm_f64<kk::EPI_MULLIKEN, kk::BackCfg><<<ba.ntiles * ba.nitems, kk::BackCfg::THREADS, 0, h->stream>>>(ba);
+    LAUNCH_CHECK("gemm_f64 k-split");
+  }
+  return KK_OK;
+}
+
+// The two FP64 response transforms of `batch` directions whose potentials are in h->u.
+kk_status transforms_f64(kk_handle h, int batch, const int* stop) {
+  if (h->kch > 1) return ksplit_transforms_f64(h, batch, stop);
+  const int np = h->np;
   const bool small = h->small_f64;
   kk::GemmArgs fa{};
   // forward (full_fwd): A = C^T U~ G over full tiles into Y, then X = (A + A^T) / 2 and
@@ -465,10 +583,32 @@ kk_status response_chunk(kk_handle h, int batch, const double* v, double* q1, co
   kk_status st;
   if ((st = launch_gemm(h, full ? kk::EPI_XSTORE : kk::EPI_FERMI, fa, small))) return st;
   if ((st = launch_gemm(h, kk::EPI_MULLIKEN, ba, small))) return st;
+  return KK_OK;
+}
+
+// Responses of `batch` directions v (batch x 2N) into q1 (batch x 2N); batch <= chunk_cap.
+// identity = true: potentials v_q +/- v_m per atom (gamma = I, W = 1), the transposed-response
+// form the reverse pass needs.
+// prologue_done: the potentials of the single direction are already in h->u (the fused
+// Krylov step wrote them); vsub, ft (K0 = -I only): combine also writes ft = -(q1 - vsub).
+kk_status response_chunk(kk_handle h, int batch, const double* v, double* q1, const int* stop,
+                         bool identity = false, bool prologue_done = false, const double* vsub = nullptr,
+                         double* ft = nullptr) {
+  const int N = h->natoms, np = h->np;
+  if (!prologue_done) {
+    const int waves = N * batch, threads = 256;
+    const int blocks = (waves * kk::WAVE + threads - 1) / threads;
+    kk::potentials<<<blocks, threads, 0, h->stream>>>(identity ? nullptr : h->gamma, N, identity ? 1.0 : h->W, v,
+                                                       batch, h->offsets, np,
+                                                       h->u, stop);
+    LAUNCH_CHECK("potentials");
+  }
+  kk_status st;
+  if ((st = transforms_f64(h, batch, stop))) return st;
   {
     dim3 grid((N + kk::COMBINE_ATOMS - 1) / kk::COMBINE_ATOMS, batch);
     kk::combine<<<grid, kk::COMBINE_THREADS, 0, h->stream>>>(h->xdiag, h->part, h->nparts, h->w[0], h->w[1],
-                                                  h->wsum, h->t, h->nb, np, h->offsets, N, q1, stop);
+                                                  h->wsum, h->t, h->nb, np, h->offsets, N, q1, stop, vsub, ft);
     LAUNCH_CHECK("combine");
   }
   return KK_OK;
@@ -478,9 +618,11 @@ kk_status response_chunk(kk_handle h, int batch, const double* v, double* q1, co
 // the refinement pass over the residual pieces (a2 = the third piece of At, b2 of Bt: products
 // hi res + res hi, added to what the first pass stored), then for the forward the symmetrizing
 // pass that writes Y as three BF16 pieces.
+// K-split (sym != nullptr): a's items are the kch chunks of each of sym's items, whose
+// symmetrizing pass sums their partial products.
 template <class Cfg1, class Cfg2>
 kk_status launch_bf16_step(kk_handle h, bool forward, kk::MixedArgs& a, const _Float16* const* a2,
-                           const _Float16* const* b2) {
+                           const _Float16* const* b2, const kk::MixedArgs* sym, int kch) {
   const int grid = a.ntiles * a.nitems;
   if (forward) {
     kk::gemm_mixed<kk::EPI_STORE, Cfg1><<<grid, Cfg1::THREADS, 0, h->stream>>>(a);
@@ -489,13 +631,13 @@ kk_status launch_bf16_step(kk_handle h, bool forward, kk::MixedArgs& a, const _F
     for (int z = 0; z < a.nitems; ++z) { r.item[z].a0l = a2[z]; r.item[z].b0l = b2[z]; }
     kk::gemm_mixed<kk::EPI_STORE_ADD, Cfg2><<<grid, Cfg2::THREADS, 0, h->stream>>>(r);
     LAUNCH_CHECK("gemm_mixed bf16 refinement");
-    if (h->mx_large) {
+    if (!h->mx_large) {
+      kk_status st = launch_sym_mixed(h, sym != nullptr ? *sym : a, kch, (size_t)a.n * a.n);
+      if (st) return st;
+    } else {
       const int nblk = a.n / kk::SYM_B_LARGE;
       kk::fermi_symmetrize<kk::SYM_B_LARGE, kk::SYM_T_LARGE, true, 3>
           <<<dim3(nblk * (nblk + 1) / 2, a.nitems), kk::SYM_T_LARGE, 0, h->stream>>>(a);
-    } else {
-      const int nblk = a.n / kk::SYM_B;
-      kk::fermi_symmetrize<kk::SYM_B, 256, true, 3><<<dim3(nblk * (nblk + 1) / 2, a.nitems), 256, 0, h->stream>>>(a);
     }
     LAUNCH_CHECK("fermi_symmetrize bf16");
   } else {
@@ -512,15 +654,17 @@ kk_status launch_bf16_step(kk_handle h, bool forward, kk::MixedArgs& a, const _F
 // Split-precision transform step: the forward (full-tile product into the FP32
 // workspace, then the symmetrizing pass that writes the split Y) or the back-transform.
 // a2, b2 (BF16 form only): per item the third pieces of At and Bt for the refinement pass.
+// sym, kch: the K-split form, as for launch_bf16_step (small product configuration only).
 kk_status launch_mixed(kk_handle h, bool forward, kk::MixedArgs& a, const _Float16* const* a2 = nullptr,
-                       const _Float16* const* b2 = nullptr) {
+                       const _Float16* const* b2 = nullptr, const kk::MixedArgs* sym = nullptr, int kch = 1) {
   const int grid = a.ntiles * a.nitems;
   if (grid <= 0) return KK_OK;
   if (a.nitems > kk::MAX_GEMM_BATCH) return fail(KK_EINVAL, "internal: too many GEMM items");
+  if (kch > 1 && h->mx_large) return fail(KK_EINVAL, "internal: K-split on the large split tiles");
   if (h->bf16) {
     ProfileScope ps(h, forward ? 0 : 1);
-    return h->mx_large ? launch_bf16_step<kk::MLargeBf1, kk::MLargeBf2>(h, forward, a, a2, b2)
-                       : launch_bf16_step<kk::MSmallBf1, kk::MSmallBf2>(h, forward, a, a2, b2);
+    return h->mx_large ? launch_bf16_step<kk::MLargeBf1, kk::MLargeBf2>(h, forward, a, a2, b2, sym, kch)
+                       : launch_bf16_step<kk::MSmallBf1, kk::MSmallBf2>(h, forward, a, a2, b2, sym, kch);
   }
   if (forward) {
     ProfileScope ps(h, 0);
@@ -529,13 +673,13 @@ kk_status launch_mixed(kk_handle h, bool forward, kk::MixedArgs& a, const _Float
     else
       kk::gemm_mixed<kk::EPI_STORE, kk::MSmallCfg><<<grid, kk::MSmallCfg::THREADS, 0, h->stream>>>(a);
     LAUNCH_CHECK("gemm_mixed");
-    if (h->mx_large) {
+    if (!h->mx_large) {
+      kk_status st = launch_sym_mixed(h, sym != nullptr ? *sym : a, kch, (size_t)a.n * a.n);
+      if (st) return st;
+    } else {
       const int nblk = a.n / kk::SYM_B_LARGE;
       kk::fermi_symmetrize<kk::SYM_B_LARGE, kk::SYM_T_LARGE>
           <<<dim3(nblk * (nblk + 1) / 2, a.nitems), kk::SYM_T_LARGE, 0, h->stream>>>(a);
-    } else {
-      const int nblk = a.n / kk::SYM_B;
-      kk::fermi_symmetrize<kk::SYM_B, 256><<<dim3(nblk * (nblk + 1) / 2, a.nitems), 256, 0, h->stream>>>(a);
     }
     LAUNCH_CHECK("fermi_symmetrize");
   } else {
@@ -552,23 +696,34 @@ kk_status launch_mixed(kk_handle h, bool forward, kk::MixedArgs& a, const _Float
 // Split-precision responses: same steps as response_chunk, with the two
 // transforms on FP16 x 3 MFMA products (Y kept as an FP16 split).
 kk_status response_chunk_mixed(kk_handle h, int batch, const double* v, double* q1, const int* stop,
-                               bool identity = false) {
+                               bool identity = false, bool prologue_done = false, const double* vsub = nullptr,
+                               double* ft = nullptr) {
   const int N = h->natoms, np = h->np;
   const size_t np2 = (size_t)np * np;
-  {
-    const int waves = N * batch, threads = 256;
-    const int blocks = (waves * kk::WAVE + threads - 1) / threads;
-    kk::potentials<<<blocks, threads, 0, h->stream>>>(identity ? nullptr : h->gamma, N, identity ? 1.0 : h->W, v,
-                                                       batch, h->offsets, np,
-                                                       h->u, stop);
-    LAUNCH_CHECK("potentials");
-  }
-  kk::center_potentials<<<batch, 1024, 0, h->stream>>>(h->u, np, h->nb, h->w[0], h->w[1], stop);
-  LAUNCH_CHECK("center_potentials");
-  kk::mixed_scales<<<2 * batch, 1024, 0, h->stream>>>(h->u, np, h->mconst, h->beta, h->msc, stop);
-  LAUNCH_CHECK("mixed_scales");
-  {
-    const int blocks = (int)std::max<size_t>(1, std::min<size_t>((np2 / 8 + 255) / 256, 16384 / (2 * batch)));
+  const int blocks = (int)std::max<size_t>(1, std::min<size_t>((np2 / 8 + 255) / 256, 16384 / (2 * batch)));
+  if (prologue_done) {  // one direction after orth_potentials: scales from its block maxima, then the split
+    const int nblk = (N + kk::FUSED_ATOMS - 1) / kk::FUSED_ATOMS;
+    if (h->bf16)
+      kk::split_operands_fused<true, 3><<<dim3(blocks, 2), 256, 0, h->stream>>>(
+          h->CT[0], h->CT[1], np, h->u, h->pmax, nblk, h->mconst, h->beta, h->msc, h->uct_h, h->uct_l, h->uct_r,
+          stop);
+    else
+      kk::split_operands_fused<false, 2><<<dim3(blocks, 2), 256, 0, h->stream>>>(
+          h->CT[0], h->CT[1], np, h->u, h->pmax, nblk, h->mconst, h->beta, h->msc, h->uct_h, h->uct_l, nullptr,
+          stop);
+    LAUNCH_CHECK("split_operands_fused");
+  } else {
+    {
+      const int waves = N * batch, threads = 256;
+      const int wblocks = (waves * kk::WAVE + threads - 1) / threads;
+      kk::potentials<<<wblocks, threads, 0, h->stream>>>(identity ? nullptr : h->gamma, N, identity ? 1.0 : h->W, v,
+                                                          batch, h->offsets, np, h->u, stop);
+      LAUNCH_CHECK("potentials");
+    }
+    kk::center_potentials<<<batch, 1024, 0, h->stream>>>(h->u, np, h->nb, h->w[0], h->w[1], stop);
+    LAUNCH_CHECK("center_potentials");
+    kk::mixed_scales<<<2 * batch, 1024, 0, h->stream>>>(h->u, np, h->mconst, h->beta, h->msc, stop);
+    LAUNCH_CHECK("mixed_scales");
     if (h->bf16)
       split_operands<true, 3><<<dim3(blocks, 2 * batch), 256, 0, h->stream>>>(h->CT[0], h->CT[1], np, h->u, h->msc,
                                                                                h->uct_h, h->uct_l, stop, h->uct_r);
@@ -577,52 +732,75 @@ kk_status response_chunk_mixed(kk_handle h, int batch, const double* v, double* 
                                                                       h->uct_l, stop, nullptr);
     LAUNCH_CHECK("split_operands");
   }
-  // forward: A = C^T U~ G over full tiles (At = (U~ C)^T, Bt = G^T), X = (A + A^T) / 2
+  // forward: A = C^T U~ G over full tiles (At = (U~ C)^T, Bt = G^T), X = (A + A^T) / 2.
+  // K-split (kch > 1, forward only): item z's chunk j is GEMM item z kch + j over contraction
+  // rows [j kck, (j + 1) kck) (operands k-contiguous: a column offset) with its FP32 partial
+  // product at x32 + (z kch + j) np^2; sa holds the unsplit items for the symmetrizing pass,
+  // which sums the partials. (A split back-transform, kchb > 1, would write chunk j's Mulliken
+  // partials at rows j nbase.. of the item's partials.)
+  const int kch = h->kch, kchb = h->kchb;
+  const size_t ck = kch > 1 ? h->kck : 0, ckb = kchb > 1 ? h->kck : 0;
   kk::MixedArgs fa{};
-  fa.n = np; fa.k = h->kc; fa.ntiles = h->n_mfull; fa.nitems = 2 * batch;
+  fa.n = np; fa.k = kch > 1 ? h->kck : h->kc; fa.ntiles = h->n_mfull; fa.nitems = 2 * batch * kch;
   fa.tiles = h->mtiles_full; fa.stop = stop; fa.beta = h->beta;
-  kk::MixedArgs ba{};
-  ba.n = np; ba.k = h->kc; ba.ntiles = h->n_mfull; ba.nitems = 2 * batch;
-  ba.tiles = h->mtiles_full; ba.stop = stop; ba.beta = h->beta;
-  for (int z = 0; z < 2 * batch; ++z) {
-    const int s = z & 1;
-    kk::MixedItem& fi = fa.item[z];
-    fi.a0h = h->uct_h + z * np2; fi.a0l = h->uct_l + z * np2; fi.b0h = h->GTh[s]; fi.b0l = h->GTl[s];
-    fi.x32 = h->x32 + z * np2;
-    fi.yh = h->yh + z * np2; fi.yl = h->yl + z * np2; fi.yr = h->bf16 ? h->yr + z * np2 : nullptr;
-    fi.eps = h->eps[s]; fi.f = h->f[s]; fi.fc = h->fc[s]; fi.w = h->w[s];
-    fi.xdiag = h->xdiag + (size_t)z * np;
-    fi.sc = h->msc + z * 8;
-    kk::MixedItem& bi = ba.item[z];
-    bi.a0h = h->Ch[s]; bi.a0l = h->Cl[s]; bi.b0h = h->yh + z * np2; bi.b0l = h->yl + z * np2;
-    bi.g = h->G[s];
-    bi.part = h->part + (size_t)z * h->nparts * np;
-    bi.sc = h->msc + z * 8 + 2;
-  }
+  kk::MixedArgs ba = fa;
+  ba.k = kchb > 1 ? h->kck : h->kc;
+  ba.nitems = 2 * batch * kchb;
+  kk::MixedArgs sa = fa;
+  sa.nitems = 2 * batch;
+  if (fa.nitems > kk::MAX_GEMM_BATCH || ba.nitems > kk::MAX_GEMM_BATCH)
+    return fail(KK_EINVAL, "internal: too many GEMM items");
   // BF16 refinement pass operands: residual pieces of (U~ C)^T and G^T (forward), C and Y (back)
   const _Float16 *fa2[kk::MAX_GEMM_BATCH], *fb2[kk::MAX_GEMM_BATCH], *ba2[kk::MAX_GEMM_BATCH],
       *bb2[kk::MAX_GEMM_BATCH];
-  if (h->bf16)
-    for (int z = 0; z < 2 * batch; ++z) {
-      fa2[z] = h->uct_r + z * np2; fb2[z] = h->GTr[z & 1];
-      ba2[z] = h->Cr[z & 1]; bb2[z] = h->yr + z * np2;
+  for (int z = 0; z < 2 * batch; ++z) {
+    const int s = z & 1;
+    kk::MixedItem& si = sa.item[z];
+    si = kk::MixedItem{};
+    si.x32 = h->x32 + (size_t)z * kch * np2;
+    si.yh = h->yh + z * np2; si.yl = h->yl + z * np2; si.yr = h->bf16 ? h->yr + z * np2 : nullptr;
+    si.eps = h->eps[s]; si.f = h->f[s]; si.fc = h->fc[s]; si.w = h->w[s];
+    si.xdiag = h->xdiag + (size_t)z * np;
+    si.sc = h->msc + z * 8;
+    for (int j = 0; j < kch; ++j) {
+      const size_t k0 = j * ck;
+      const int q = z * kch + j;
+      kk::MixedItem& fi = fa.item[q];
+      fi = si;
+      fi.a0h = h->uct_h + z * np2 + k0; fi.a0l = h->uct_l + z * np2 + k0;
+      fi.b0h = h->GTh[s] + k0; fi.b0l = h->GTl[s] + k0;
+      fi.x32 = si.x32 + j * np2;
+      if (h->bf16) { fa2[q] = h->uct_r + z * np2 + k0; fb2[q] = h->GTr[s] + k0; }
     }
+    for (int j = 0; j < kchb; ++j) {
+      const size_t k0 = j * ckb;
+      const int q = z * kchb + j;
+      kk::MixedItem& bi = ba.item[q];
+      bi = kk::MixedItem{};
+      bi.a0h = h->Ch[s] + k0; bi.a0l = h->Cl[s] + k0; bi.b0h = h->yh + z * np2 + k0; bi.b0l = h->yl + z * np2 + k0;
+      bi.g = h->G[s];
+      bi.part = h->part + ((size_t)z * h->nparts + (size_t)j * h->nbase) * np;
+      bi.sc = h->msc + z * 8 + 2;
+      if (h->bf16) { ba2[q] = h->Cr[s] + k0; bb2[q] = h->yr + z * np2 + k0; }
+    }
+  }
   kk_status st;
-  if ((st = launch_mixed(h, true, fa, fa2, fb2))) return st;
+  if ((st = launch_mixed(h, true, fa, fa2, fb2, kch > 1 ? &sa : nullptr, kch))) return st;
   if ((st = launch_mixed(h, false, ba, ba2, bb2))) return st;
   {
     dim3 grid((N + kk::COMBINE_ATOMS - 1) / kk::COMBINE_ATOMS, batch);
     kk::combine<<<grid, kk::COMBINE_THREADS, 0, h->stream>>>(h->xdiag, h->part, h->nparts, h->w[0], h->w[1],
-                                                  h->wsum, h->t, h->nb, np, h->offsets, N, q1, stop);
+                                                  h->wsum, h->t, h->nb, np, h->offsets, N, q1, stop, vsub, ft);
     LAUNCH_CHECK("combine");
   }
   return KK_OK;
 }
 
 kk_status response_any(kk_handle h, int batch, const double* v, double* q1, const int* stop,
-                       bool identity = false) {
-  return h->precision == KK_FP64 ? response_chunk(h, batch, v, q1, stop, identity)
-                                 : response_chunk_mixed(h, batch, v, q1, stop, identity);
+                       bool identity = false, bool prologue_done = false, const double* vsub = nullptr,
+                       double* ft = nullptr) {
+  return h->precision == KK_FP64 ? response_chunk(h, batch, v, q1, stop, identity, prologue_done, vsub, ft)
+                                 : response_chunk_mixed(h, batch, v, q1, stop, identity, prologue_done, vsub, ft);
 }
 
 kk_status check_handle(kk_handle h) {
@@ -672,8 +850,9 @@ kk_status allocate_prepared(kk_handle h) {
   h->n_full = (int)full.size();
   h->n_store = (int)stt.size();
   static_assert(kk::FwdCfg::MIN_BLOCKS == kk::BackCfg::MIN_BLOCKS, "one slot count for both forward forms");
-  h->full_fwd = h->small_f64 ? full_forward(h->n_supper, h->n_sfull, cu_count() * SmallF64::MIN_BLOCKS)
-                             : full_forward(h->n_upper, h->n_full, cu_count() * kk::BackCfg::MIN_BLOCKS);
+  h->full_fwd = h->kch > 1 ||
+                (h->small_f64 ? full_forward(h->n_supper, h->n_sfull, cu_count() * SmallF64::MIN_BLOCKS)
+                              : full_forward(h->n_upper, h->n_full, cu_count() * kk::BackCfg::MIN_BLOCKS));
   if ((st = dalloc_t(h, &h->tiles_upper, up.size()))) return st;
   if ((st = dalloc_t(h, &h->tiles_full, full.size()))) return st;
   if ((st = dalloc_t(h, &h->tiles_store, stt.size()))) return st;
@@ -692,6 +871,8 @@ kk_status allocate_prepared(kk_handle h) {
   if (h->precision != KK_FP64) {
     if ((st = dalloc_t(h, &h->mconst, 8))) return st;
     if ((st = dalloc_t(h, &h->mscratch, (size_t)4 * np))) return st;
+    if ((st = dalloc_t(h, &h->cvec, (size_t)2 * n_atoms))) return st;
+    if ((st = dalloc_t(h, &h->pmax, (size_t)2 * kk::FUSED_MAX_BLOCKS))) return st;
     for (int s = 0; s < 2; ++s) {
       if ((st = dalloc_t(h, &h->GT[s], np2))) return st;
       for (_Float16** q : {&h->Ch[s], &h->Cl[s], &h->GTh[s], &h->GTl[s]})
@@ -729,6 +910,11 @@ kk_status prepare_mixed(kk_handle h) {
     LAUNCH_CHECK("row_stats");
     kk::const_scales<<<1, 1024, 0, h->stream>>>(rmax, rn2, rmax + np, rn2 + np, np, h->mconst + 4 * s);
     LAUNCH_CHECK("const_scales");
+    if (s == 0 && 2 * h->natoms <= kk::FUSED_MAX_N2) {
+      kk::centre_vector<<<h->natoms + 1, 256, 0, h->stream>>>(h->gamma, h->natoms, h->W, h->offsets, h->w[0], h->w[1],
+                                                               h->wsum, h->cvec);
+      LAUNCH_CHECK("centre_vector");
+    }
     if (h->bf16) {
       kk::split_matrix<true, 3><<<pg, pb, 0, h->stream>>>(h->C[s], np, 0, h->mconst + 4 * s, h->Ch[s], h->Cl[s],
                                                           h->Cr[s]);
@@ -816,12 +1002,24 @@ kk_status prepare_impl(kk_handle h, int n_atoms, const int* atom_offsets, int n_
     h->bf16 = precision == KK_MIXED_BF16;
     h->natoms = n_atoms; h->nb = nb; h->np = np;
     h->kc = (nb + KSTEP - 1) / KSTEP * KSTEP;
-    h->small_f64 = !mixed && np <= SMALL_NP_F64;
+    // the K-split runs on the 128 x 128 tiles of either form (a batch's systems never split)
+    h->kch = 1;
+    h->kck = h->kc;
+    if (!split_large && !mx_large) {
+      const int tiles = mixed ? (np / kk::MSmallCfg::BM) * (np / kk::MSmallCfg::BN)
+                              : (np / kk::BackCfg::BM) * (np / kk::BackCfg::BN);
+      h->kch = choose_ksplit(np, h->kc, tiles, cu_count(), &h->kck);
+    }
+    // The split back-transform ran slower split (Nb = 1152: 37.4 against 35.1 us): its
+    // epilogue (the Mulliken product with G, per tile) is repeated per chunk.
+    h->kchb = mixed ? 1 : h->kch;
+    h->small_f64 = !mixed && np <= SMALL_NP_F64 && h->kch == 1;
     h->mx_large = mx_large;
-    h->nparts = mixed ? (mx_large ? (np / kk::MLargeCfg::BN) * kk::MLargeCfg::WAVES_N
-                                  : (np / kk::MSmallCfg::BN) * kk::MSmallCfg::WAVES_N)
-                      : h->small_f64 ? (np / SmallF64::BN) * SmallF64::WAVES_N
-                                     : (np / kk::BackCfg::BN) * kk::BackCfg::WAVES_N;
+    h->nbase = mixed ? (mx_large ? (np / kk::MLargeCfg::BN) * kk::MLargeCfg::WAVES_N
+                                 : (np / kk::MSmallCfg::BN) * kk::MSmallCfg::WAVES_N)
+                     : h->small_f64 ? (np / SmallF64::BN) * SmallF64::WAVES_N
+                                    : (np / kk::BackCfg::BN) * kk::BackCfg::WAVES_N;
+    h->nparts = h->kchb * h->nbase;
     if ((st = allocate_prepared(h))) return st;
   }
   h->W = W; h->kT = kT; h->beta = 1.0 / kT; h->n_e = n_electrons;
@@ -989,15 +1187,30 @@ kk_status enqueue_krylov(kk_handle h, const double* delta, int m, double tol, co
   LAUNCH_CHECK("krylov_reset");
   kk::precondition<<<gv_blocks, gv_threads, 0, h->stream>>>(K0, delta, nullptr, h->ftilde, n2, nullptr);
   LAUNCH_CHECK("precondition");
+  // Small systems: one launch orthonormalizes and builds the potentials (kk_fused.hpp), and
+  // with K0 = -I the combine also preconditions.
+  const bool fused = n2 <= kk::FUSED_MAX_N2;
   for (int k = 0; k < m; ++k) {
     const double* src = (k == 0) ? h->ftilde : h->Ft + (size_t)(k - 1) * n2;
-    kk::krylov_orthonormalize<<<1, orth_threads, 0, h->stream>>>(src, h->V, n2, h->kst);
-    LAUNCH_CHECK("krylov_orthonormalize");
     const double* vk = h->V + (size_t)k * n2;
-    if ((st = response_any(h, 1, vk, h->q1, stop))) return st;
-    kk::precondition<<<gv_blocks, gv_threads, 0, h->stream>>>(K0, h->q1, vk, h->Ft + (size_t)k * n2, n2,
-                                                               stop);
-    LAUNCH_CHECK("precondition");
+    double* ftk = h->Ft + (size_t)k * n2;
+    if (fused) {
+      const bool split = h->precision != KK_FP64;
+      kk::orth_potentials<<<(h->natoms + kk::FUSED_ATOMS - 1) / kk::FUSED_ATOMS, kk::FUSED_THREADS, 0,
+                            h->stream>>>(src, h->V, n2, h->kst, k, h->gamma, h->natoms, h->W, h->offsets, h->np,
+                                         h->u, split ? h->cvec : nullptr, split ? h->pmax : nullptr);
+      LAUNCH_CHECK("orth_potentials");
+      if ((st = response_any(h, 1, vk, h->q1, stop, false, true, K0 ? nullptr : vk, K0 ? nullptr : ftk)))
+        return st;
+    } else {
+      kk::krylov_orthonormalize<<<1, orth_threads, 0, h->stream>>>(src, h->V, n2, h->kst);
+      LAUNCH_CHECK("krylov_orthonormalize");
+      if ((st = response_any(h, 1, vk, h->q1, stop))) return st;
+    }
+    if (!fused || K0 != nullptr) {
+      kk::precondition<<<gv_blocks, gv_threads, 0, h->stream>>>(K0, h->q1, vk, ftk, n2, stop);
+      LAUNCH_CHECK("precondition");
+    }
     if (tol > 0.0 && k + 1 < m) {  // residual of the rank-(k+1) solve; may end the expansion
       kk::krylov_solve<<<1, 1024, 0, h->stream>>>(h->V, h->Ft, h->ftilde, n2, h->kst, Kdelta, tol);
       LAUNCH_CHECK("krylov_solve");
@@ -1173,7 +1386,7 @@ kk_status kk_profile_read(kk_handle h, int kernel_id, double* total_ms, int* lau
 
 namespace {
 
-constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(48) << 20;
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(64) << 20;
 constexpr int NOALLOC_MAX_DEVICES = 64;
 
 }  // namespace
@@ -1215,7 +1428,7 @@ struct ScratchLayout {
 
 ScratchLayout scratch_layout(kk_handle h, unsigned char* base) {
   ScratchLayout L;
-  const size_t np = h->np, items = 2, np2 = np * np;
+  const size_t np = h->np, items = 2, np2 = np * np, kch = h->kch;
   auto take = [&](size_t nbytes) -> void* {
     void* p = base ? base + L.bytes : nullptr;
     L.bytes += (nbytes + 255) / 256 * 256;
@@ -1223,7 +1436,7 @@ ScratchLayout scratch_layout(kk_handle h, unsigned char* base) {
   };
   L.u = static_cast<double*>(take(items * np * sizeof(double)));
   if (h->precision == KK_FP64) {
-    L.Y = static_cast<double*>(take(items * np2 * sizeof(double)));
+    L.Y = static_cast<double*>(take(items * kch * np2 * sizeof(double)));
   } else {
     L.uct_h = static_cast<_Float16*>(take(items * np2 * sizeof(_Float16)));
     L.uct_l = static_cast<_Float16*>(take(items * np2 * sizeof(_Float16)));
@@ -1233,7 +1446,7 @@ ScratchLayout scratch_layout(kk_handle h, unsigned char* base) {
       L.uct_r = static_cast<_Float16*>(take(items * np2 * sizeof(_Float16)));
       L.yr = static_cast<_Float16*>(take(items * np2 * sizeof(_Float16)));
     }
-    L.x32 = static_cast<float*>(take(items * np2 * sizeof(float)));
+    L.x32 = static_cast<float*>(take(items * kch * np2 * sizeof(float)));
     L.msc = static_cast<double*>(take(items * 8 * sizeof(double)));
   }
   L.xdiag = static_cast<double*>(take(items * np * sizeof(double)));

@@ -244,7 +244,8 @@ __device__ __forceinline__ void combine_dev(const double* __restrict__ xdiag, co
                                             const double* __restrict__ w_dn, const double* __restrict__ wsum_p,
                                             const double* __restrict__ t, int nb, int np,
                                             const int* __restrict__ offsets, int natoms, double* __restrict__ q1,
-                                            const int* __restrict__ stop, int bx, int by) {
+                                            const int* __restrict__ stop, int bx, int by,
+                                            const double* __restrict__ vsub = nullptr, double* __restrict__ ft = nullptr) {
   if (stop != nullptr && *stop != 0) return;
   __shared__ double sh[17];
   const int b = by;
@@ -268,8 +269,13 @@ __device__ __forceinline__ void combine_dev(const double* __restrict__ xdiag, co
     dn[sp] = wave_sum(acc) + dmu * t[sp * natoms + a];
   }
   if (lane == 0) {
-    q1[(size_t)b * 2 * natoms + a] = dn[0] + dn[1];
-    q1[(size_t)b * 2 * natoms + natoms + a] = dn[0] - dn[1];
+    const double qa = dn[0] + dn[1], ma = dn[0] - dn[1];
+    q1[(size_t)b * 2 * natoms + a] = qa;
+    q1[(size_t)b * 2 * natoms + natoms + a] = ma;
+    if (ft != nullptr) {  // the preconditioned directional derivative with K0 = -I: -(q1 - v)
+      ft[a] = -(qa - vsub[a]);
+      ft[natoms + a] = -(ma - vsub[natoms + a]);
+    }
   }
 }
 
@@ -281,9 +287,10 @@ __global__ void combine(const double* __restrict__ xdiag, const double* __restri
                         const double* __restrict__ w_up, const double* __restrict__ w_dn,
                         const double* __restrict__ wsum_p, const double* __restrict__ t, int nb, int np,
                         const int* __restrict__ offsets, int natoms, double* __restrict__ q1,
-                        const int* __restrict__ stop) {
+                        const int* __restrict__ stop, const double* __restrict__ vsub = nullptr,
+                        double* __restrict__ ft = nullptr) {
   combine_dev(xdiag, part, nparts, nparts, w_up, w_dn, wsum_p, t, nb, np, offsets, natoms, q1, stop, blockIdx.x,
-              blockIdx.y);
+              blockIdx.y, vsub, ft);
 }
 
 // sum of both spins' w (one block).

@@ -503,6 +503,23 @@ int max_chunk(kk_handle h) {
   return (int)std::max<size_t>(1, std::min<size_t>(c, kk::MAX_GEMM_BATCH / (2 * kch)));
 }
 
+// The last step of a response: q1 (and with K0 = -I the preconditioned derivative ft) from
+// the Mulliken partial rows and diag X (combine; combine_small for the fused small step).
+kk_status launch_combine(kk_handle h, int batch, double* q1, const int* stop, const double* vsub, double* ft) {
+  const int N = h->natoms;
+  dim3 grid((N + kk::COMBINE_ATOMS - 1) / kk::COMBINE_ATOMS, batch);
+  if (2 * N <= kk::FUSED_MAX_N2)
+    kk::combine_small<<<grid, kk::COMBINE_THREADS, 0, h->stream>>>(h->xdiag, h->part, h->nparts, h->w[0], h->w[1],
+                                                                  h->wsum, h->t, h->nb, h->np, h->offsets, N, q1,
+                                                                  stop, vsub, ft);
+  else
+    kk::combine<<<grid, kk::COMBINE_THREADS, 0, h->stream>>>(h->xdiag, h->part, h->nparts, h->w[0], h->w[1],
+                                                             h->wsum, h->t, h->nb, h->np, h->offsets, N, q1, stop,
+                                                             vsub, ft);
+  LAUNCH_CHECK("combine");
+  return KK_OK;
+}
+
 // K-split FP64 transforms (choose_ksplit) of `batch` directions whose potentials are in h->u:
 // the forward as kch full-tile partial products per item into Y (chunk j of item z at
 // Y + (z kch + j) np^2), summed and symmetrized into the first; the back-transform as kch
@@ -605,13 +622,7 @@ kk_status response_chunk(kk_handle h, int batch, const double* v, double* q1, co
   }
   kk_status st;
   if ((st = transforms_f64(h, batch, stop))) return st;
-  {
-    dim3 grid((N + kk::COMBINE_ATOMS - 1) / kk::COMBINE_ATOMS, batch);
-    kk::combine<<<grid, kk::COMBINE_THREADS, 0, h->stream>>>(h->xdiag, h->part, h->nparts, h->w[0], h->w[1],
-                                                  h->wsum, h->t, h->nb, np, h->offsets, N, q1, stop, vsub, ft);
-    LAUNCH_CHECK("combine");
-  }
-  return KK_OK;
+  return launch_combine(h, batch, q1, stop, vsub, ft);
 }
 
 // BF16 form, one transform step: the first pass (four products of the hi/lo pieces), then
@@ -787,13 +798,7 @@ kk_status response_chunk_mixed(kk_handle h, int batch, const double* v, double* 
   kk_status st;
   if ((st = launch_mixed(h, true, fa, fa2, fb2, kch > 1 ? &sa : nullptr, kch))) return st;
   if ((st = launch_mixed(h, false, ba, ba2, bb2))) return st;
-  {
-    dim3 grid((N + kk::COMBINE_ATOMS - 1) / kk::COMBINE_ATOMS, batch);
-    kk::combine<<<grid, kk::COMBINE_THREADS, 0, h->stream>>>(h->xdiag, h->part, h->nparts, h->w[0], h->w[1],
-                                                  h->wsum, h->t, h->nb, np, h->offsets, N, q1, stop, vsub, ft);
-    LAUNCH_CHECK("combine");
-  }
-  return KK_OK;
+  return launch_combine(h, batch, q1, stop, vsub, ft);
 }
 
 kk_status response_any(kk_handle h, int batch, const double* v, double* q1, const int* stop,

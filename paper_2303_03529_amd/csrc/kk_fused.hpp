@@ -56,101 +56,168 @@ __global__ void centre_vector(const double* __restrict__ gamma, int natoms, doub
   }
 }
 
+// Wave 0 of a block: the direction in sv (2N = n2 entries, LDS) orthonormalized against
+// V[0..rank) by two MGS passes, rows below `staged` read from vl (LDS), the rest from V; then
+// normalized, with the breakdown test ||w|| <= BREAKDOWN_TOL ||src||. On success sv holds
+// v_rank (block 0 also stores it as row `rank` of V), *cs = cvec . v (0 without cvec) and
+// *accepted = 1; otherwise *accepted = 0 and block 0 ends the expansion in the Krylov state.
+// Every block computes the same bits, so every block decides alike. PER >= n2 / WAVE.
+template <int PER>
+__device__ __forceinline__ void orth_wave0(double* sv, const double* vl, int staged, double* V, int n2, int rank,
+                                           KrylovState* st, const double* __restrict__ cvec, int* accepted,
+                                           double* cs) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  double w[PER], nn = 0.0;
+#pragma unroll
+  for (int e = 0; e < PER; ++e) {
+    const int i = lane + e * WAVE;
+    w[e] = i < n2 ? sv[i] : 0.0;
+    nn += w[e] * w[e];
+  }
+  const double start = sqrt(wave_sum_dpp(nn));
+  for (int t = 0; t < 2 * rank; ++t) {
+    const int j = t < rank ? t : t - rank;
+    double r[PER], d = 0.0;
+    if (j < staged) {  // the two sources in separate branches keep the LDS reads ds_read
+#pragma unroll
+      for (int e = 0; e < PER; ++e) {
+        const int i = lane + e * WAVE;
+        r[e] = i < n2 ? vl[j * n2 + i] : 0.0;
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < PER; ++e) {
+        const int i = lane + e * WAVE;
+        r[e] = i < n2 ? V[(size_t)j * n2 + i] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < PER; ++e) d += r[e] * w[e];
+    d = wave_sum_dpp(d);
+#pragma unroll
+    for (int e = 0; e < PER; ++e) w[e] -= d * r[e];
+  }
+  nn = 0.0;
+#pragma unroll
+  for (int e = 0; e < PER; ++e) nn += w[e] * w[e];
+  const double nrm = sqrt(wave_sum_dpp(nn));
+  const bool ok = nrm > BREAKDOWN_TOL * start && rank < MAX_RANK;
+  double cpart = 0.0;
+  if (ok) {
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int i = lane + e * WAVE;
+      if (i < n2) {
+        const double vi = w[e] / nrm;
+        sv[i] = vi;
+        if (blockIdx.x == 0) V[(size_t)rank * n2 + i] = vi;
+        if (cvec != nullptr) cpart += cvec[i] * vi;
+      }
+    }
+  }
+  cpart = wave_sum_dpp(cpart);
+  if (lane == 0) {
+    *accepted = ok ? 1 : 0;
+    *cs = cpart;
+    if (!ok && blockIdx.x == 0) {
+      st->stop = 1;
+      if (rank > 0) st->status = 1;
+    }
+  }
+}
+
 // One Krylov step's prologue: v_rank = MGS^2(src)/||.|| (two passes against V[0..rank);
 // or the end of the expansion on breakdown), then u^s_I = sum_J gamma_IJ v_q[J] + s W v_m[I]
 // on every orbital of the block's atoms (Sec. III.A). With cvec given (split forms) the
 // potentials are centred by c = cvec . v (the response to a common shift is zero) and
 // pmax[2 blockIdx.x + s] receives the block's largest |u^s - c|.
+// The block first issues all its global loads: src and the first rows of V (up to
+// FUSED_LDS_ROWS doubles) into LDS, its atoms' rows of gamma into registers. Wave 0 then
+// runs the 2 rank projections out of LDS (rows past the staged ones from global memory),
+// and every wave forms its atoms' potentials from the new direction in LDS.
 // Grid: ceil(N / FUSED_ATOMS) blocks of FUSED_THREADS; 2N <= FUSED_MAX_N2.
+constexpr int FUSED_LDS_ROWS = 8192;  // doubles of V staged in LDS (64 KB)
 __global__ void __launch_bounds__(FUSED_THREADS)
     orth_potentials(const double* __restrict__ src, double* __restrict__ V, int n2, KrylovState* st, int rank,
                     const double* __restrict__ gamma, int natoms, double W, const int* __restrict__ offsets, int np,
                     double* __restrict__ u, const double* __restrict__ cvec, double* __restrict__ pmax) {
   __shared__ double sv[FUSED_MAX_N2];
+  __shared__ double vl[FUSED_LDS_ROWS];
   __shared__ double mred[2][FUSED_THREADS / WAVE];
+  __shared__ double cvl[FUSED_MAX_N2];
   __shared__ double cshared;
   __shared__ int accepted;
-  if (st->stop) return;
-  if (threadIdx.x < WAVE) {
-    // Orthonormalization in wave 0 (shuffle reductions, no barriers); the next row of V is
-    // loaded before each projection's reduction.
-    constexpr int PER = FUSED_MAX_N2 / WAVE;
-    const int lane0 = threadIdx.x;
-    double w[PER], nn = 0.0;
+  // the stop flag is read with the other loads and tested once they are issued (all of
+  // them are in bounds either way), so that it costs no round trip of its own
+  const int stopped = st->stop;
+  constexpr int NW = FUSED_THREADS / WAVE, APW = FUSED_ATOMS / NW, GPER = FUSED_MAX_N2 / 2 / WAVE;
+  const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
+  const int a0 = blockIdx.x * FUSED_ATOMS, a1 = min(natoms, a0 + FUSED_ATOMS);
+  const int staged = min(rank, FUSED_LDS_ROWS / n2);
+  // every global load of the block first, into registers (a load and its LDS store per
+  // loop step would wait for each load in turn)
+  constexpr int SPT = FUSED_MAX_N2 / FUSED_THREADS, VPT = FUSED_LDS_ROWS / FUSED_THREADS;
+  const int nv = staged * n2;
+  double sr[SPT], vr[VPT], cr[SPT];
 #pragma unroll
-    for (int e = 0; e < PER; ++e) {
-      const int i = lane0 + e * WAVE;
-      w[e] = i < n2 ? src[i] : 0.0;
-      nn += w[e] * w[e];
+  for (int k = 0; k < SPT; ++k) {
+    const int i = threadIdx.x + k * FUSED_THREADS;
+    sr[k] = i < n2 ? src[i] : 0.0;
+    cr[k] = (cvec != nullptr && i < n2) ? cvec[i] : 0.0;
+  }
+#pragma unroll
+  for (int k = 0; k < VPT; ++k) {
+    const int i = threadIdx.x + k * FUSED_THREADS;
+    vr[k] = i < nv ? V[i] : 0.0;
+  }
+  double g[APW][GPER];
+  int ob[APW], oe[APW];
+#pragma unroll
+  for (int t = 0; t < APW; ++t) {
+    const int a = a0 + wave + t * NW;
+#pragma unroll
+    for (int e = 0; e < GPER; ++e) {
+      const int j = lane + e * WAVE;
+      g[t][e] = (a < a1 && j < natoms) ? gamma[(size_t)a * natoms + j] : 0.0;
     }
-    const double start = sqrt(wave_sum(nn));
-    auto load_row = [&](int j, double (&dst)[PER]) {
-      const double* vj = V + (size_t)j * n2;
+    ob[t] = a < a1 ? offsets[a] : 0;
+    oe[t] = a < a1 ? offsets[a + 1] : 0;
+  }
+  if (stopped) return;  // the same value in every thread: before the first barrier
 #pragma unroll
-      for (int e = 0; e < PER; ++e) {
-        const int i = lane0 + e * WAVE;
-        dst[e] = i < n2 ? vj[i] : 0.0;
-      }
-    };
-    const int steps = 2 * rank;
-    double cur[PER], nxt[PER] = {};
-    if (steps > 0) load_row(0, cur);
-    for (int t = 0; t < steps; ++t) {
-      if (t + 1 < steps) load_row((t + 1) % rank, nxt);
-      double d = 0.0;
-#pragma unroll
-      for (int e = 0; e < PER; ++e) d += cur[e] * w[e];
-      d = wave_sum(d);
-#pragma unroll
-      for (int e = 0; e < PER; ++e) {
-        w[e] -= d * cur[e];
-        cur[e] = nxt[e];
-      }
-    }
-    nn = 0.0;
-#pragma unroll
-    for (int e = 0; e < PER; ++e) nn += w[e] * w[e];
-    const double nrm = sqrt(wave_sum(nn));
-    const bool ok = nrm > BREAKDOWN_TOL * start && rank < MAX_RANK;  // every block decides alike
-    double cpart = 0.0;
-    if (ok) {
-#pragma unroll
-      for (int e = 0; e < PER; ++e) {
-        const int i = lane0 + e * WAVE;
-        if (i < n2) {
-          const double vi = w[e] / nrm;
-          sv[i] = vi;
-          if (blockIdx.x == 0) V[(size_t)rank * n2 + i] = vi;
-          if (cvec != nullptr) cpart += cvec[i] * vi;
-        }
-      }
-    }
-    cpart = wave_sum(cpart);
-    if (lane0 == 0) {
-      accepted = ok ? 1 : 0;
-      cshared = cpart;
-      if (!ok && blockIdx.x == 0) {
-        st->stop = 1;
-        if (rank > 0) st->status = 1;
-      }
+  for (int k = 0; k < SPT; ++k) {
+    const int i = threadIdx.x + k * FUSED_THREADS;
+    if (i < n2) {
+      sv[i] = sr[k];
+      cvl[i] = cr[k];
     }
   }
+#pragma unroll
+  for (int k = 0; k < VPT; ++k) {
+    const int i = threadIdx.x + k * FUSED_THREADS;
+    if (i < nv) vl[i] = vr[k];
+  }
+  __syncthreads();
+  if (wave == 0) orth_wave0<FUSED_MAX_N2 / WAVE>(sv, vl, staged, V, n2, rank, st, cvl, &accepted, &cshared);
   __syncthreads();
   if (!accepted) return;
   const double c = cvec != nullptr ? cshared : 0.0;
-  const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
-  constexpr int NW = FUSED_THREADS / WAVE;
-  const int a0 = blockIdx.x * FUSED_ATOMS, a1 = min(natoms, a0 + FUSED_ATOMS);
   double m0 = 0.0, m1 = 0.0;
-  for (int a = a0 + wave; a < a1; a += NW) {
-    const double* g = gamma + (size_t)a * natoms;
+#pragma unroll
+  for (int t = 0; t < APW; ++t) {
+    const int a = a0 + wave + t * NW;  // wave-uniform
+    if (a >= a1) break;
     double s = 0.0;
-    for (int j = lane; j < natoms; j += WAVE) s += g[j] * sv[j];
-    s = wave_sum(s);
+#pragma unroll
+    for (int e = 0; e < GPER; ++e) {
+      const int j = lane + e * WAVE;
+      if (j < natoms) s += g[t][e] * sv[j];
+    }
+    s = wave_sum_dpp(s);
     const double up = s + W * sv[natoms + a] - c, dn = s - W * sv[natoms + a] - c;
     m0 = fmax(m0, fabs(up));
     m1 = fmax(m1, fabs(dn));
-    for (int i = offsets[a] + lane; i < offsets[a + 1]; i += WAVE) {
+    for (int i = ob[t] + lane; i < oe[t]; i += WAVE) {
       u[i] = up;
       u[(size_t)np + i] = dn;
     }
@@ -177,34 +244,143 @@ __global__ void __launch_bounds__(FUSED_THREADS)
 // largest centred potentials (as mixed_scales computes them from the potentials; block
 // x = 0 of each item stores them for the products and the symmetrizing pass), then
 // (U~ C)^T split at s_C s_u. Grid (blocks, 2 items).
+// (U~ C)^T at scale s in NP 16-bit pieces, 8 consecutive columns of a row per thread and
+// step (16-byte loads and stores), grid-stride over the np x np operand: the same split as
+// split_scaled_columns_dev with the scale passed by value.
+template <bool BF16, int NP>
+__device__ __forceinline__ void split_columns_at(const double* __restrict__ src, int np,
+                                                 const double* __restrict__ u, double s, _Float16* __restrict__ hi,
+                                                 _Float16* __restrict__ lo, _Float16* __restrict__ re, int bx,
+                                                 int gdx) {
+  const unsigned per_row = (unsigned)np / 8u, total = per_row * (unsigned)np;
+  for (unsigned g = (unsigned)bx * blockDim.x + threadIdx.x; g < total; g += (unsigned)gdx * blockDim.x) {
+    const unsigned r = g / per_row, c0 = (g - r * per_row) * 8u;
+    const size_t base = (size_t)r * np + c0;
+    const d2* sv = reinterpret_cast<const d2*>(src + base);
+    const d2* uv = reinterpret_cast<const d2*>(u + c0);
+    h8 vp[NP];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const d2 v = sv[q], w = uv[q];
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        _Float16 pc[NP];
+        split_pieces<BF16, NP>(s * w[e] * v[e], pc);
+#pragma unroll
+        for (int k = 0; k < NP; ++k) vp[k][2 * q + e] = pc[k];
+      }
+    }
+    *reinterpret_cast<h8*>(hi + base) = vp[0];
+    *reinterpret_cast<h8*>(lo + base) = vp[1];
+    if constexpr (NP == 3) *reinterpret_cast<h8*>(re + base) = vp[2];
+  }
+}
+
 template <bool BF16, int NP>
 __global__ void split_operands_fused(const double* __restrict__ CT0, const double* __restrict__ CT1, int np,
                                      const double* __restrict__ u, const double* __restrict__ pmax, int nblk,
                                      const double* __restrict__ mconst, double beta, double* __restrict__ msc,
                                      _Float16* __restrict__ uct_h, _Float16* __restrict__ uct_l,
                                      _Float16* __restrict__ uct_r, const int* __restrict__ stop) {
-  __shared__ double scale;
-  if (stop != nullptr && *stop != 0) return;
+  const int stopped = stop != nullptr ? *stop : 0;  // tested once the scale loads are issued
   const int z = blockIdx.y;
-  if (threadIdx.x == 0) {
-    double umax = 0.0;
-    for (int b = 0; b < nblk; ++b) umax = fmax(umax, pmax[2 * b + z]);
-    const double sC = mconst[z * 4 + 0], sG = mconst[z * 4 + 1];
-    const double s_u = pow2_scale(umax, 0);
+  // every thread forms the scales itself (a few cached loads), so that no barrier holds
+  // back the loads of the operand
+  double umax = 0.0;
+  for (int b = 0; b < nblk; ++b) umax = fmax(umax, pmax[2 * b + z]);
+  const double sC = mconst[z * 4 + 0], sG = mconst[z * 4 + 1];
+  if (stopped) return;
+  const double s_u = pow2_scale(umax, 0);
+  const double scale = sC * s_u;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
     const double sY = pow2_scale(0.25 * beta * umax * mconst[z * 4 + 2] * mconst[z * 4 + 3], 14);
-    scale = sC * s_u;
-    if (blockIdx.x == 0) {
-      msc[z * 8 + 0] = 1.0 / (sC * sG * s_u);
-      msc[z * 8 + 1] = sY;
-      msc[z * 8 + 2] = 1.0 / (sC * sY);
-      msc[z * 8 + 3] = sC * s_u;
-      msc[z * 8 + 4] = sG * s_u;
+    msc[z * 8 + 0] = 1.0 / (sC * sG * s_u);
+    msc[z * 8 + 1] = sY;
+    msc[z * 8 + 2] = 1.0 / (sC * sY);
+    msc[z * 8 + 3] = sC * s_u;
+    msc[z * 8 + 4] = sG * s_u;
+  }
+  const size_t off = (size_t)z * np * np;
+  split_columns_at<BF16, NP>(z ? CT1 : CT0, np, u + (size_t)z * np, scale, uct_h + off, uct_l + off,
+                             NP == 3 ? uct_r + off : nullptr, blockIdx.x, gridDim.x);
+}
+
+// The combine of the fused small-system step: the same results as combine (dmu from
+// w . diag X of both spins, per-atom sums of the Mulliken partial rows, dmu t_s, the (q, m)
+// mix and, with ft, the preconditioned derivative -(q1 - vsub)), with every load of a block
+// issued before the first is used: the partial rows of an atom are read as flattened
+// (row, orbital) pairs, COMBINE_BATCH per lane and spin at once. One wave per atom,
+// COMBINE_THREADS threads; grid (ceil(N / COMBINE_ATOMS), directions).
+constexpr int COMBINE_BATCH = 8;
+__global__ void __launch_bounds__(COMBINE_THREADS)
+    combine_small(const double* __restrict__ xdiag, const double* __restrict__ part, int nparts,
+                  const double* __restrict__ w_up, const double* __restrict__ w_dn,
+                  const double* __restrict__ wsum_p, const double* __restrict__ t, int nb, int np,
+                  const int* __restrict__ offsets, int natoms, double* __restrict__ q1,
+                  const int* __restrict__ stop, const double* __restrict__ vsub, double* __restrict__ ft) {
+  __shared__ double sh[17];
+  const int b = blockIdx.y;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int a = blockIdx.x * (COMBINE_THREADS / WAVE) + (int)(threadIdx.x / WAVE);
+  const bool have = a < natoms;
+  // first round of loads: the stop flag, the atom's orbital range, its t_s, and the w . diag X
+  // terms of dmu; the partial rows (which need the range) follow in a second
+  const int stopped = stop != nullptr ? *stop : 0;
+  const int i0 = have ? offsets[a] : 0, i1 = have ? offsets[a + 1] : 0;
+  const double tu = have ? t[a] : 0.0, td = have ? t[natoms + a] : 0.0;
+  const double wsum = *wsum_p;
+  const double* xu = xdiag + ((size_t)b * 2 + 0) * np;
+  const double* xd = xdiag + ((size_t)b * 2 + 1) * np;
+  double s = 0.0;
+  for (int base = 0; base < nb; base += 4 * COMBINE_THREADS) {
+    double wu[4], xuv[4], wd[4], xdv[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int i = base + threadIdx.x + k * COMBINE_THREADS;
+      const bool ok = i < nb;
+      wu[k] = ok ? w_up[i] : 0.0;
+      xuv[k] = ok ? xu[i] : 0.0;
+      wd[k] = ok ? w_dn[i] : 0.0;
+      xdv[k] = ok ? xd[i] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s += wu[k] * xuv[k] + wd[k] * xdv[k];
+  }
+  if (stopped) return;  // the same value in every thread: before the first barrier
+  const int norb = i1 - i0, tot = nparts * norb;
+  const double* p0 = part + ((size_t)b * 2 + 0) * nparts * np + i0;
+  const double* p1 = part + ((size_t)b * 2 + 1) * nparts * np + i0;
+  double acc0 = 0.0, acc1 = 0.0;
+  for (int base = 0; base < tot; base += COMBINE_BATCH * WAVE) {
+    double v0[COMBINE_BATCH], v1[COMBINE_BATCH];
+#pragma unroll
+    for (int k = 0; k < COMBINE_BATCH; ++k) {
+      const int e = base + lane + k * WAVE;
+      const bool ok = e < tot;
+      const int p = ok ? e / norb : 0;
+      const size_t o = (size_t)p * np + (e - p * norb);
+      v0[k] = ok ? p0[o] : 0.0;
+      v1[k] = ok ? p1[o] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < COMBINE_BATCH; ++k) {
+      acc0 += v0[k];
+      acc1 += v1[k];
     }
   }
-  __syncthreads();
-  const size_t off = (size_t)z * np * np;
-  split_scaled_columns_dev<BF16, NP>(z ? CT1 : CT0, np, u + (size_t)z * np, &scale, uct_h + off, uct_l + off,
-                                     nullptr, blockIdx.x, gridDim.x, NP == 3 ? uct_r + off : nullptr);
+  s = block_sum(s, sh);
+  acc0 = wave_sum(acc0);
+  acc1 = wave_sum(acc1);
+  if (!have || lane != 0) return;
+  const double dmu = wsum > 0.0 ? s / wsum : 0.0;
+  const double d0 = acc0 + dmu * tu, d1 = acc1 + dmu * td;
+  const double qa = d0 + d1, ma = d0 - d1;
+  q1[(size_t)b * 2 * natoms + a] = qa;
+  q1[(size_t)b * 2 * natoms + natoms + a] = ma;
+  if (ft != nullptr) {  // the preconditioned directional derivative with K0 = -I: -(q1 - v)
+    ft[a] = -(qa - vsub[a]);
+    ft[natoms + a] = -(ma - vsub[natoms + a]);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -233,7 +409,7 @@ __device__ __forceinline__ int2 upper_pair(int pair, int nblk) {
 template <int B, int T, int NCH>
 __global__ __launch_bounds__(T) void fermi_symmetrize_f64_chunks(const GemmArgs args, size_t cstride) {
   static_assert(T % B == 0 && B % (T / B) == 0, "thread mapping");
-  if (args.stop != nullptr && *args.stop != 0) return;
+  const int stopped = args.stop != nullptr ? *args.stop : 0;  // tested once the loads are issued
   const GemmItem& it = args.item[blockIdx.y];
   const int n = args.n;
   const int2 ij = upper_pair(blockIdx.x, n / B);
@@ -257,6 +433,7 @@ __global__ __launch_bounds__(T) void fermi_symmetrize_f64_chunks(const GemmArgs 
     em[q] = it.eps[m]; fm[q] = it.f[m]; fcm[q] = it.fc[m]; wm[q] = it.w[m];
   }
   const double en = it.eps[c], fn = it.f[c], fcn = it.fc[c];
+  if (stopped) return;  // the same value in every thread: before the first barrier
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     double a = mir[0][q];
@@ -301,7 +478,7 @@ template <int B, int T, bool BF16, int NP, int NCH>
 __global__ __launch_bounds__(T) void fermi_symmetrize_chunks(const MixedArgs args, size_t cstride) {
   static_assert(T % B == 0 && B % (T / B) == 0, "thread mapping");
   static_assert(NP == 2 || NP == 3, "two or three pieces");
-  if (args.stop != nullptr && *args.stop != 0) return;
+  const int stopped = args.stop != nullptr ? *args.stop : 0;  // tested once the loads are issued
   const MixedItem& it = args.item[blockIdx.y];
   const int n = args.n;
   const int2 ij = upper_pair(blockIdx.x, n / B);
@@ -327,6 +504,7 @@ __global__ __launch_bounds__(T) void fermi_symmetrize_chunks(const MixedArgs arg
   }
   const double en = it.eps[c], fn = it.f[c], fcn = it.fc[c];
   const double inv = it.sc[0], sy = it.sc[1];
+  if (stopped) return;  // the same value in every thread: before the first barrier
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     double a = (double)mir[0][q];

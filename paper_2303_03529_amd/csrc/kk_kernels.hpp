@@ -17,6 +17,34 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Wave-wide sum of a double in a fixed order, the same bits in every lane, for serial
+// reduction chains (the orthonormalization, the m x m solve): within each row of 16 lanes by DPP moves
+// (rotate by 8 and 4, then exchange with lane ^ 2 and lane ^ 1: every step adds two values
+// that the partner lane adds in the other order, so all 16 lanes end with the same bits),
+// then the four row sums read from lanes 0, 16, 32 and 48 and added as (r0 + r1) + (r2 + r3).
+// The cross-lane moves stay in the VALU, where a shuffle through the LDS crossbar costs a
+// round trip per step.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double lane_f64(double v, int lane) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v += dpp_f64<0x128>(v);  // row_ror:8
+  v += dpp_f64<0x124>(v);  // row_ror:4
+  v += dpp_f64<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  v += dpp_f64<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
+}
+
 // Sum over a block of up to 1024 threads (multiple of 64); every thread gets
 // thread 0's total. sh must hold at least 17 doubles.
 __device__ double block_sum(double v, double* sh) {
@@ -421,16 +449,17 @@ __global__ void __launch_bounds__(1024) krylov_orthonormalize(const double* __re
 __device__ __forceinline__ void solve_dev(const double* __restrict__ V, const double* __restrict__ Ft,
                                           const double* __restrict__ ftilde, int n2, KrylovState* st,
                                           double* __restrict__ x, double stop_tol) {
-  __shared__ double sh[17];
+  __shared__ double sr[2][16];
   __shared__ double O[MAX_RANK][MAX_RANK + 1];
   __shared__ double c[MAX_RANK];
   __shared__ int ok;
   const int r = st->rank;
-  // The r (r + 1) / 2 entries of O and the r of the right-hand side, one wave
-  // each (fixed lane order and shuffle tree, so the result is deterministic).
+  const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+  // The r (r + 1) / 2 entries of O and the r of the right-hand side, one wave each (fixed
+  // lane order and reduction tree, so the result is deterministic); 4 loads per lane in flight.
   {
-    const int lane = threadIdx.x & (WAVE - 1), nw = blockDim.x / WAVE, npairs = r * (r + 1) / 2;
-    for (int p = threadIdx.x / WAVE; p < npairs + r; p += nw) {
+    const int npairs = r * (r + 1) / 2;
+    for (int p = wave; p < npairs + r; p += nw) {
       int a, b = -1;
       if (p < npairs) {
         a = 0;
@@ -441,9 +470,19 @@ __device__ __forceinline__ void solve_dev(const double* __restrict__ V, const do
       }
       const double* fa = Ft + (size_t)a * n2;
       const double* y = b >= 0 ? Ft + (size_t)b * n2 : ftilde;
-      double d = 0.0;
-      for (int i = lane; i < n2; i += WAVE) d += fa[i] * y[i];
-      d = wave_sum(d);
+      double d4[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int base = 0; base < n2; base += 4 * WAVE) {
+        double xa[4], xb[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int i = base + lane + k * WAVE;
+          xa[k] = i < n2 ? fa[i] : 0.0;
+          xb[k] = i < n2 ? y[i] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) d4[k] += xa[k] * xb[k];
+      }
+      const double d = wave_sum_dpp((d4[0] + d4[1]) + (d4[2] + d4[3]));
       if (lane == 0) {
         if (b >= 0) { O[a][b] = d; O[b][a] = d; }
         else c[a] = d;
@@ -451,61 +490,100 @@ __device__ __forceinline__ void solve_dev(const double* __restrict__ V, const do
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    ok = 1;
+  if (wave == 0) {
+    // Cholesky O = L L^T in wave 0, lane i owning row i (r <= MAX_RANK = WAVE): column j's
+    // entries l_ij = O_ij / l_jj, then the trailing update O_ik -= l_ij l_kj (k <= i), l_kj
+    // taken from lane k. One wave's LDS accesses complete in order.
+    int good = 1;
     double pmin = 0.0, pmax = 0.0;
-    // in-place Cholesky: lower triangle of O holds L
-    for (int j = 0; j < r && ok; ++j) {
-      double dj = O[j][j];
-      for (int k = 0; k < j; ++k) dj -= O[j][k] * O[j][k];
-      if (!(dj > 0.0)) { ok = 0; break; }
+    for (int j = 0; j < r; ++j) {
+      const double dj = O[j][j];
+      if (!(dj > 0.0)) {  // the same value in every lane
+        good = 0;
+        break;
+      }
       pmin = (j == 0) ? dj : fmin(pmin, dj);
       pmax = (j == 0) ? dj : fmax(pmax, dj);
       const double ljj = sqrt(dj);
-      O[j][j] = ljj;
-      for (int i = j + 1; i < r; ++i) {
-        double s = O[i][j];
-        for (int k = 0; k < j; ++k) s -= O[i][k] * O[j][k];
-        O[i][j] = s / ljj;
+      const bool below = lane > j && lane < r;
+      const double lij = below ? O[lane][j] / ljj : 0.0;
+      if (lane == j) O[j][j] = ljj;
+      if (below) O[lane][j] = lij;
+      for (int k = j + 1; k < r; ++k) {
+        const double lkj = lane_f64(lij, k);
+        if (below && k <= lane) O[lane][k] -= lij * lkj;
       }
+      __builtin_amdgcn_wave_barrier();
     }
-    if (ok) {
-      for (int i = 0; i < r; ++i) {  // L y = rhs
-        double s = c[i];
-        for (int k = 0; k < i; ++k) s -= O[i][k] * c[k];
-        c[i] = s / O[i][i];
+    if (good) {
+      double ci = lane < r ? c[lane] : 0.0;
+      for (int j = 0; j < r; ++j) {  // L y = rhs
+        const double yj = lane_f64(ci / O[j][j], j);
+        if (lane == j) ci = yj;
+        else if (lane > j && lane < r) ci -= O[lane][j] * yj;
       }
-      for (int i = r - 1; i >= 0; --i) {  // L^T c = y
-        double s = c[i];
-        for (int k = i + 1; k < r; ++k) s -= O[k][i] * c[k];
-        c[i] = s / O[i][i];
+      for (int j = r - 1; j >= 0; --j) {  // L^T c = y
+        const double xj = lane_f64(ci / O[j][j], j);
+        if (lane == j) ci = xj;
+        else if (lane < j) ci -= O[j][lane] * xj;
       }
-    } else {
-      st->status = -5;
+      if (lane < r) c[lane] = ci;
     }
-    st->min_pivot = pmin;
-    st->max_pivot = pmax;
+    if (lane == 0) {
+      ok = good;
+      if (!good) st->status = -5;
+      st->min_pivot = pmin;
+      st->max_pivot = pmax;
+    }
   }
   __syncthreads();
+  const int okv = ok;
   double rr = 0.0, ff = 0.0;
   for (int i = threadIdx.x; i < n2; i += blockDim.x) {
     double s = 0.0, fi = 0.0;
-    if (ok)
-      for (int k = 0; k < r; ++k) {
+    if (okv) {
+      int k = 0;
+      for (; k + 4 <= r; k += 4) {
+        double vv[4], fv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          vv[q] = V[(size_t)(k + q) * n2 + i];
+          fv[q] = Ft[(size_t)(k + q) * n2 + i];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          s += c[k + q] * vv[q];
+          fi += c[k + q] * fv[q];
+        }
+      }
+      for (; k < r; ++k) {
         s += c[k] * V[(size_t)k * n2 + i];
         fi += c[k] * Ft[(size_t)k * n2 + i];
       }
+    }
     x[i] = s;
-    const double e = fi - ftilde[i];
+    const double fti = ftilde[i];
+    const double e = fi - fti;
     rr += e * e;
-    ff += ftilde[i] * ftilde[i];
+    ff += fti * fti;
   }
-  rr = block_sum(rr, sh);
-  ff = block_sum(ff, sh);
+  rr = wave_sum_dpp(rr);
+  ff = wave_sum_dpp(ff);
+  if (lane == 0) {
+    sr[0][wave] = rr;
+    sr[1][wave] = ff;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
+    rr = 0.0;
+    ff = 0.0;
+    for (int q = 0; q < nw; ++q) {
+      rr += sr[0][q];
+      ff += sr[1][q];
+    }
     const double res = ff > 0.0 ? sqrt(rr / ff) : 0.0;
     st->ls_residual = res;
-    if (stop_tol > 0.0 && ok && res <= stop_tol) st->stop = 1;
+    if (stop_tol > 0.0 && okv && res <= stop_tol) st->stop = 1;
   }
 }
 

@@ -310,7 +310,11 @@ int cu_count() {
 // symmetrizing pass; back: by combine, as further Mulliken partial rows). c minimizes the
 // per-CU work ceil(2 tiles c / CUs) / c and is taken when that is at most 3/4 of the
 // unsplit figure. At Nb = 1152 (81 tiles of 128 x 128 per spin, 162 for 256 CUs) c = 3.
-constexpr int KSPLIT_MAX = 4, KSPLIT_MIN_K = 128;
+// -DKK_KSPLIT_MAX=1 turns the K-split off (for re-tuning).
+#ifndef KK_KSPLIT_MAX
+#define KK_KSPLIT_MAX 4
+#endif
+constexpr int KSPLIT_MAX = KK_KSPLIT_MAX, KSPLIT_MIN_K = 128;
 int choose_ksplit(int np, int kc, int tiles, int cus, int* chunk_rows) {
   *chunk_rows = kc;
   if (2 * tiles > cus) return 1;
@@ -1188,9 +1192,8 @@ kk_status enqueue_krylov(kk_handle h, const double* delta, int m, double tol, co
   // orthonormalization: one block just large enough for 8 entries per thread
   const int orth_threads = std::max(64, std::min(1024, ((n2 + 7) / 8 + 63) / 64 * 64));
 
-  kk::krylov_reset<<<1, 64, 0, h->stream>>>(h->kst);
-  LAUNCH_CHECK("krylov_reset");
-  kk::precondition<<<gv_blocks, gv_threads, 0, h->stream>>>(K0, delta, nullptr, h->ftilde, n2, nullptr);
+  // f~ = K0 delta (or -delta), and the Krylov state cleared, in one launch
+  kk::precondition<<<gv_blocks, gv_threads, 0, h->stream>>>(K0, delta, nullptr, h->ftilde, n2, nullptr, h->kst);
   LAUNCH_CHECK("precondition");
   // Small systems: one launch orthonormalizes and builds the potentials (kk_fused.hpp), and
   // with K0 = -I the combine also preconditions.

@@ -244,48 +244,58 @@ __global__ void __launch_bounds__(FUSED_THREADS)
 // largest centred potentials (as mixed_scales computes them from the potentials; block
 // x = 0 of each item stores them for the products and the symmetrizing pass), then
 // (U~ C)^T split at s_C s_u. Grid (blocks, 2 items).
-// (U~ C)^T at scale s in NP 16-bit pieces, 8 consecutive columns of a row per thread and
-// step (16-byte loads and stores), grid-stride over the np x np operand: the same split as
-// split_scaled_columns_dev with the scale passed by value.
+// (U~ C)^T at scale s in NP 16-bit pieces for one group of 8 consecutive columns of row r
+// (16-byte loads and stores): the arithmetic of split_scaled_columns_dev.
 template <bool BF16, int NP>
-__device__ __forceinline__ void split_columns_at(const double* __restrict__ src, int np,
-                                                 const double* __restrict__ u, double s, _Float16* __restrict__ hi,
-                                                 _Float16* __restrict__ lo, _Float16* __restrict__ re, int bx,
-                                                 int gdx) {
-  const unsigned per_row = (unsigned)np / 8u, total = per_row * (unsigned)np;
-  for (unsigned g = (unsigned)bx * blockDim.x + threadIdx.x; g < total; g += (unsigned)gdx * blockDim.x) {
-    const unsigned r = g / per_row, c0 = (g - r * per_row) * 8u;
-    const size_t base = (size_t)r * np + c0;
-    const d2* sv = reinterpret_cast<const d2*>(src + base);
-    const d2* uv = reinterpret_cast<const d2*>(u + c0);
-    h8 vp[NP];
+__device__ __forceinline__ void split_group8(const d2 (&v)[4], const d2 (&w)[4], double s, size_t base,
+                                             _Float16* __restrict__ hi, _Float16* __restrict__ lo,
+                                             _Float16* __restrict__ re) {
+  h8 vp[NP];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const d2 v = sv[q], w = uv[q];
+  for (int q = 0; q < 4; ++q)
 #pragma unroll
-      for (int e = 0; e < 2; ++e) {
-        _Float16 pc[NP];
-        split_pieces<BF16, NP>(s * w[e] * v[e], pc);
+    for (int e = 0; e < 2; ++e) {
+      _Float16 pc[NP];
+      split_pieces<BF16, NP>(s * w[q][e] * v[q][e], pc);
 #pragma unroll
-        for (int k = 0; k < NP; ++k) vp[k][2 * q + e] = pc[k];
-      }
+      for (int k = 0; k < NP; ++k) vp[k][2 * q + e] = pc[k];
     }
-    *reinterpret_cast<h8*>(hi + base) = vp[0];
-    *reinterpret_cast<h8*>(lo + base) = vp[1];
-    if constexpr (NP == 3) *reinterpret_cast<h8*>(re + base) = vp[2];
-  }
+  *reinterpret_cast<h8*>(hi + base) = vp[0];
+  *reinterpret_cast<h8*>(lo + base) = vp[1];
+  if constexpr (NP == 3) *reinterpret_cast<h8*>(re + base) = vp[2];
 }
 
+// The split forms' operand split after orth_potentials: the item scales from the blocks'
+// largest centred potentials (as mixed_scales computes them from the potentials; block
+// x = 0 of each item stores them for the products and the symmetrizing pass), then
+// (U~ C)^T split at s_C s_u, grid-stride over 8-column groups. Every thread forms the
+// scales itself (a few cached loads), and its first group's operand and potentials are
+// loaded together with them, so that the block waits for memory once before it computes.
+// Grid (blocks, 2 items).
 template <bool BF16, int NP>
 __global__ void split_operands_fused(const double* __restrict__ CT0, const double* __restrict__ CT1, int np,
                                      const double* __restrict__ u, const double* __restrict__ pmax, int nblk,
                                      const double* __restrict__ mconst, double beta, double* __restrict__ msc,
                                      _Float16* __restrict__ uct_h, _Float16* __restrict__ uct_l,
                                      _Float16* __restrict__ uct_r, const int* __restrict__ stop) {
-  const int stopped = stop != nullptr ? *stop : 0;  // tested once the scale loads are issued
   const int z = blockIdx.y;
-  // every thread forms the scales itself (a few cached loads), so that no barrier holds
-  // back the loads of the operand
+  const double* src = z ? CT1 : CT0;
+  const double* uz = u + (size_t)z * np;
+  const size_t off = (size_t)z * np * np;
+  const unsigned per_row = (unsigned)np / 8u, total = per_row * (unsigned)np;
+  const unsigned g0 = (unsigned)blockIdx.x * blockDim.x + threadIdx.x, gs = (unsigned)gridDim.x * blockDim.x;
+  d2 v[4], w[4];
+  size_t base = 0;
+  if (g0 < total) {
+    const unsigned r = g0 / per_row, c0 = (g0 - r * per_row) * 8u;
+    base = (size_t)r * np + c0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      v[q] = reinterpret_cast<const d2*>(src + base)[q];
+      w[q] = reinterpret_cast<const d2*>(uz + c0)[q];
+    }
+  }
+  const int stopped = stop != nullptr ? *stop : 0;
   double umax = 0.0;
   for (int b = 0; b < nblk; ++b) umax = fmax(umax, pmax[2 * b + z]);
   const double sC = mconst[z * 4 + 0], sG = mconst[z * 4 + 1];
@@ -300,9 +310,18 @@ __global__ void split_operands_fused(const double* __restrict__ CT0, const doubl
     msc[z * 8 + 3] = sC * s_u;
     msc[z * 8 + 4] = sG * s_u;
   }
-  const size_t off = (size_t)z * np * np;
-  split_columns_at<BF16, NP>(z ? CT1 : CT0, np, u + (size_t)z * np, scale, uct_h + off, uct_l + off,
-                             NP == 3 ? uct_r + off : nullptr, blockIdx.x, gridDim.x);
+  _Float16* re = NP == 3 ? uct_r + off : nullptr;
+  if (g0 < total) split_group8<BF16, NP>(v, w, scale, base, uct_h + off, uct_l + off, re);
+  for (unsigned g = g0 + gs; g < total; g += gs) {
+    const unsigned r = g / per_row, c0 = (g - r * per_row) * 8u;
+    const size_t bg = (size_t)r * np + c0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      v[q] = reinterpret_cast<const d2*>(src + bg)[q];
+      w[q] = reinterpret_cast<const d2*>(uz + c0)[q];
+    }
+    split_group8<BF16, NP>(v, w, scale, bg, uct_h + off, uct_l + off, re);
+  }
 }
 
 // The combine of the fused small-system step: the same results as combine (dmu from
@@ -405,146 +424,155 @@ __device__ __forceinline__ int2 upper_pair(int pair, int nblk) {
 
 // FP64: A_j at it.out + j cstride; X_ii goes to xdiag, Y_ii = -w_i X_ii, Y = F o X
 // elsewhere, written over A_0 (block (I, J) by the thread that read it, block (J, I)
-// through LDS after the whole pair was read). B x B blocks, T threads.
+// through LDS after the whole pair was read). B x B blocks of T = B * B / 4 threads: thread
+// (r, q) takes columns 4q..4q+3 of row r of both blocks (16-byte loads and stores).
 template <int B, int T, int NCH>
 __global__ __launch_bounds__(T) void fermi_symmetrize_f64_chunks(const GemmArgs args, size_t cstride) {
-  static_assert(T % B == 0 && B % (T / B) == 0, "thread mapping");
+  static_assert(T * 4 == B * B, "4 elements per thread");
   const int stopped = args.stop != nullptr ? *args.stop : 0;  // tested once the loads are issued
   const GemmItem& it = args.item[blockIdx.y];
   const int n = args.n;
   const int2 ij = upper_pair(blockIdx.x, n / B);
   const int I = ij.x, J = ij.y;
-  constexpr int RS = T / B, Q = B / RS;
   __shared__ double At[B][B + 1];
-  const int tx = threadIdx.x % B, ty = threadIdx.x / B;
+  const int r = threadIdx.x / (B / 4), c4 = (threadIdx.x % (B / 4)) * 4;
   double* const Y = it.out;
-  const int c = J * B + tx;
-  double own[NCH][Q], mir[NCH][Q], em[Q], fm[Q], fcm[Q], wm[Q];
+  const int m = I * B + r, cb = J * B + c4;
+  const size_t oo = (size_t)m * n + cb, om = (size_t)(J * B + r) * n + I * B + c4;
+  d2 own[NCH][2], mir[NCH][2];
 #pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int r = ty + q * RS;
-    const size_t oo = (size_t)(I * B + r) * n + c, om = (size_t)(J * B + r) * n + I * B + tx;
+  for (int j = 0; j < NCH; ++j)
 #pragma unroll
-    for (int j = 0; j < NCH; ++j) {
-      own[j][q] = Y[oo + j * cstride];
-      mir[j][q] = Y[om + j * cstride];
+    for (int h = 0; h < 2; ++h) {
+      own[j][h] = reinterpret_cast<const d2*>(Y + oo + j * cstride)[h];
+      mir[j][h] = reinterpret_cast<const d2*>(Y + om + j * cstride)[h];
     }
-    const int m = I * B + r;
-    em[q] = it.eps[m]; fm[q] = it.f[m]; fcm[q] = it.fc[m]; wm[q] = it.w[m];
+  const double em = it.eps[m], fm = it.f[m], fcm = it.fc[m], wm = it.w[m];
+  d2 en[2], fn[2], fcn[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    en[h] = reinterpret_cast<const d2*>(it.eps + cb)[h];
+    fn[h] = reinterpret_cast<const d2*>(it.f + cb)[h];
+    fcn[h] = reinterpret_cast<const d2*>(it.fc + cb)[h];
   }
-  const double en = it.eps[c], fn = it.f[c], fcn = it.fc[c];
   if (stopped) return;  // the same value in every thread: before the first barrier
 #pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    double a = mir[0][q];
+  for (int e = 0; e < 4; ++e) {
+    double a = mir[0][e >> 1][e & 1];
 #pragma unroll
-    for (int j = 1; j < NCH; ++j) a += mir[j][q];
-    At[ty + q * RS][tx] = a;
+    for (int j = 1; j < NCH; ++j) a += mir[j][e >> 1][e & 1];
+    At[r][c4 + e] = a;
   }
   __syncthreads();
-  double yv[Q];
+  double yv[4];
 #pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int r = ty + q * RS, m = I * B + r;
-    double a = own[0][q];
+  for (int e = 0; e < 4; ++e) {
+    const int c = c4 + e;
+    double a = own[0][e >> 1][e & 1];
 #pragma unroll
-    for (int j = 1; j < NCH; ++j) a += own[j][q];
-    const double x = 0.5 * (a + At[tx][r]);
+    for (int j = 1; j < NCH; ++j) a += own[j][e >> 1][e & 1];
+    const double x = 0.5 * (a + At[c][r]);
     double y;
-    if (m == c) {
+    if (m == cb + e) {
       it.xdiag[m] = x;
-      y = -wm[q] * x;
+      y = -wm * x;
     } else {
-      y = fermi_divided_difference(em[q], fm[q], fcm[q], en, fn, fcn, args.beta) * x;
+      y = fermi_divided_difference(em, fm, fcm, en[e >> 1][e & 1], fn[e >> 1][e & 1], fcn[e >> 1][e & 1],
+                                   args.beta) * x;
     }
-    yv[q] = y;
-    Y[(size_t)m * n + c] = y;  // only this thread read this element, and it read all chunks of it
+    yv[e] = y;
   }
+  // only this thread read these elements of block (I, J), all chunks of them
+  reinterpret_cast<d2*>(Y + oo)[0] = d2{yv[0], yv[1]};
+  reinterpret_cast<d2*>(Y + oo)[1] = d2{yv[2], yv[3]};
   if (I == J) return;  // a diagonal block is symmetric by construction
   __syncthreads();     // every read of At is done
 #pragma unroll
-  for (int q = 0; q < Q; ++q) At[tx][ty + q * RS] = yv[q];
+  for (int e = 0; e < 4; ++e) At[c4 + e][r] = yv[e];
   __syncthreads();
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int r = ty + q * RS;
-    Y[(size_t)(J * B + r) * n + I * B + tx] = At[r][tx];
-  }
+  reinterpret_cast<d2*>(Y + om)[0] = d2{At[r][c4], At[r][c4 + 1]};
+  reinterpret_cast<d2*>(Y + om)[1] = d2{At[r][c4 + 2], At[r][c4 + 3]};
 }
 
 // Split forms: the FP32 partial products at it.x32 + j cstride, X scaled by 1 / the
 // product scale, Y written as NP 16-bit pieces at the Y scale (as fermi_symmetrize does).
+// Same thread layout, 16-byte loads and 8-byte stores.
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef _Float16 h4v __attribute__((ext_vector_type(4)));
 template <int B, int T, bool BF16, int NP, int NCH>
 __global__ __launch_bounds__(T) void fermi_symmetrize_chunks(const MixedArgs args, size_t cstride) {
-  static_assert(T % B == 0 && B % (T / B) == 0, "thread mapping");
+  static_assert(T * 4 == B * B, "4 elements per thread");
   static_assert(NP == 2 || NP == 3, "two or three pieces");
   const int stopped = args.stop != nullptr ? *args.stop : 0;  // tested once the loads are issued
   const MixedItem& it = args.item[blockIdx.y];
   const int n = args.n;
   const int2 ij = upper_pair(blockIdx.x, n / B);
   const int I = ij.x, J = ij.y;
-  constexpr int RS = T / B, Q = B / RS;
   __shared__ double At[B][B + 1];
-  __shared__ _Float16 Tp[NP][B][B + 2];
-  const int tx = threadIdx.x % B, ty = threadIdx.x / B;
-  const int c = J * B + tx;
-  float own[NCH][Q], mir[NCH][Q];
-  double em[Q], fm[Q], fcm[Q], wm[Q];
+  __shared__ _Float16 Tp[NP][B][B + 4];
+  const int r = threadIdx.x / (B / 4), c4 = (threadIdx.x % (B / 4)) * 4;
+  const int m = I * B + r, cb = J * B + c4;
+  const size_t oo = (size_t)m * n + cb, om = (size_t)(J * B + r) * n + I * B + c4;
+  f4v own[NCH], mir[NCH];
 #pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int r = ty + q * RS;
-    const size_t oo = (size_t)(I * B + r) * n + c, om = (size_t)(J * B + r) * n + I * B + tx;
-#pragma unroll
-    for (int j = 0; j < NCH; ++j) {
-      own[j][q] = it.x32[oo + j * cstride];
-      mir[j][q] = it.x32[om + j * cstride];
-    }
-    const int m = I * B + r;
-    em[q] = it.eps[m]; fm[q] = it.f[m]; fcm[q] = it.fc[m]; wm[q] = it.w[m];
+  for (int j = 0; j < NCH; ++j) {
+    own[j] = *reinterpret_cast<const f4v*>(it.x32 + oo + j * cstride);
+    mir[j] = *reinterpret_cast<const f4v*>(it.x32 + om + j * cstride);
   }
-  const double en = it.eps[c], fn = it.f[c], fcn = it.fc[c];
+  const double em = it.eps[m], fm = it.f[m], fcm = it.fc[m], wm = it.w[m];
+  d2 en[2], fn[2], fcn[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    en[h] = reinterpret_cast<const d2*>(it.eps + cb)[h];
+    fn[h] = reinterpret_cast<const d2*>(it.f + cb)[h];
+    fcn[h] = reinterpret_cast<const d2*>(it.fc + cb)[h];
+  }
   const double inv = it.sc[0], sy = it.sc[1];
   if (stopped) return;  // the same value in every thread: before the first barrier
 #pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    double a = (double)mir[0][q];
+  for (int e = 0; e < 4; ++e) {
+    double a = (double)mir[0][e];
 #pragma unroll
-    for (int j = 1; j < NCH; ++j) a += (double)mir[j][q];
-    At[ty + q * RS][tx] = a;
+    for (int j = 1; j < NCH; ++j) a += (double)mir[j][e];
+    At[r][c4 + e] = a;
   }
   __syncthreads();
+  h4v pv[NP];
 #pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int r = ty + q * RS, m = I * B + r;
-    const size_t o = (size_t)m * n + c;
-    double a = (double)own[0][q];
+  for (int e = 0; e < 4; ++e) {
+    const int c = c4 + e;
+    double a = (double)own[0][e];
 #pragma unroll
-    for (int j = 1; j < NCH; ++j) a += (double)own[j][q];
-    const double x = 0.5 * inv * (a + At[tx][r]);
+    for (int j = 1; j < NCH; ++j) a += (double)own[j][e];
+    const double x = 0.5 * inv * (a + At[c][r]);
     double y;
-    if (m == c) {
+    if (m == cb + e) {
       it.xdiag[m] = x;
-      y = -wm[q] * x * sy;
+      y = -wm * x * sy;
     } else {
-      y = fermi_divided_difference(em[q], fm[q], fcm[q], en, fn, fcn, args.beta) * x * sy;
+      y = fermi_divided_difference(em, fm, fcm, en[e >> 1][e & 1], fn[e >> 1][e & 1], fcn[e >> 1][e & 1],
+                                   args.beta) * x * sy;
     }
     _Float16 pc[NP];
     split_pieces<BF16, NP>(y, pc);
-    it.yh[o] = pc[0];
-    it.yl[o] = pc[1];
-    if constexpr (NP == 3) it.yr[o] = pc[2];
 #pragma unroll
-    for (int p = 0; p < NP; ++p) Tp[p][tx][r] = pc[p];
+    for (int p = 0; p < NP; ++p) {
+      pv[p][e] = pc[p];
+      Tp[p][c][r] = pc[p];
+    }
   }
+  *reinterpret_cast<h4v*>(it.yh + oo) = pv[0];
+  *reinterpret_cast<h4v*>(it.yl + oo) = pv[1];
+  if constexpr (NP == 3) *reinterpret_cast<h4v*>(it.yr + oo) = pv[2];
   if (I == J) return;
   __syncthreads();
 #pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int r = ty + q * RS;
-    const size_t o = (size_t)(J * B + r) * n + I * B + tx;
-    it.yh[o] = Tp[0][r][tx];
-    it.yl[o] = Tp[1][r][tx];
-    if constexpr (NP == 3) it.yr[o] = Tp[2][r][tx];
+  for (int p = 0; p < NP; ++p) {
+    h4v t;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) t[e] = Tp[p][r][c4 + e];
+    _Float16* dst = p == 0 ? it.yh : (p == 1 ? it.yl : it.yr);
+    *reinterpret_cast<h4v*>(dst + om) = t;
   }
 }
 

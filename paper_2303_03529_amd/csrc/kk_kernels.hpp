@@ -343,18 +343,16 @@ struct KrylovState {
   double ls_residual;  // ||F~ c - f~|| / ||f~|| of the last solve
 };
 
-__global__ void krylov_reset(KrylovState* st) {
-  if (threadIdx.x == 0) {
-    st->rank = 0; st->stop = 0; st->status = 0; st->pad = 0;
-    st->min_pivot = 0.0; st->max_pivot = 0.0; st->ls_residual = 1.0;
-  }
-}
-
 // y = K0 (x - sub) (sub may be null), or -(x - sub) when K0 is null.
-// One wave per row. Skipped after a breakdown when stop is given.
+// One wave per row. Skipped after a breakdown when stop is given. With reset given (the
+// first launch of an update, stop null) thread 0 also clears that Krylov state.
 __global__ void precondition(const double* __restrict__ K0, const double* __restrict__ x,
                              const double* __restrict__ sub, double* __restrict__ y, int n2,
-                             const int* __restrict__ stop) {
+                             const int* __restrict__ stop, KrylovState* reset = nullptr) {
+  if (reset != nullptr && blockIdx.x == 0 && threadIdx.x == 0) {
+    reset->rank = 0; reset->stop = 0; reset->status = 0; reset->pad = 0;
+    reset->min_pivot = 0.0; reset->max_pivot = 0.0; reset->ls_residual = 1.0;
+  }
   if (stop != nullptr && *stop != 0) return;
   const int row = (blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
   const int lane = threadIdx.x & (WAVE - 1);

@@ -1,0 +1,56 @@
+"""K-split transforms of small single systems against the FP64 oracle, at the sizes
+where the split count differs from the 128-atom case (three chunks): open clusters of
+56 atoms (Nb = 504, padded 512: four chunks of 128 rows) and 113 atoms (Nb = 1017,
+padded 1024, contraction 1024: two chunks of 512 rows), in all three precisions.
+
+Checked: five responses in one call (the workspace holds two directions at a time
+with four chunks, so the call runs in three batches), each against the oracle's
+response, and the rank-6 kernel against the oracle's kernel. Bounds: 1e-10 (FP64) and
+1e-6 (split forms), relative 2-norm per output.
+"""
+
+import numpy as np
+import pytest
+
+from tests.gpu_helpers import handle_from_expansion, rel, t
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from oracle.expansion import expansion_point  # noqa: E402
+from oracle.krylov import kernel_apply  # noqa: E402
+from oracle.response import response  # noqa: E402
+from paper_2303_03529_amd import krylov  # noqa: E402
+from synth import make_system  # noqa: E402
+
+TOL = {krylov.KK_FP64: 1e-10, krylov.KK_MIXED_F16: 1e-6, krylov.KK_MIXED_BF16: 1e-6}
+PRECISIONS = [krylov.KK_FP64, krylov.KK_MIXED_F16, krylov.KK_MIXED_BF16]
+
+
+@pytest.fixture(scope="module", params=[56, 113], ids=["fe56", "fe113"])
+def system(request):
+    n = request.param
+    sysd = make_system(n_atoms=n, seed=20_000 + n)
+    return sysd, expansion_point(sysd)
+
+
+@pytest.mark.parametrize("precision", PRECISIONS, ids=["fp64", "f16x3", "bf16"])
+def test_ksplit_responses_and_kernel(system, precision):
+    sysd, ep = system
+    n = sysd["n_atoms"]
+    h = handle_from_expansion(sysd, ep, precision)
+    try:
+        vs = np.random.default_rng(n).standard_normal((5, 2 * n))
+        got = h.density_response_batch(t(vs)).cpu().numpy()
+        errs = [rel(got[i], response(sysd, ep, vs[i])) for i in range(len(vs))]
+        kd, info = h.krylov_kernel_apply(t(sysd["delta"]), 6)
+        ek = rel(kd.cpu().numpy(), kernel_apply(sysd, ep, sysd["delta"], 6))
+        print(f"{n} atoms (Nb {sysd['n_basis']}), precision {precision}: responses max {max(errs):.2e}, "
+              f"kernel {ek:.2e}, rank {info.rank_used}", flush=True)
+        assert max(errs) < TOL[precision], errs
+        assert ek < TOL[precision], ek
+    finally:
+        h.close()

@@ -307,31 +307,36 @@ int cu_count() {
 // is cut into c chunks of kck rows (a multiple of KSTEP, at least KSPLIT_MIN_K, all c chunks
 // inside the padding, whose rows past kc are zero); every chunk is a GEMM item of its own
 // and the partial results are summed in a fixed order afterwards (forward: by the
-// symmetrizing pass; back: by combine, as further Mulliken partial rows). c minimizes the
-// per-CU work ceil(2 tiles c / CUs) / c and is taken when that is at most 3/4 of the
-// unsplit figure. At Nb = 1152 (81 tiles of 128 x 128 per spin, 162 for 256 CUs) c = 3.
+// symmetrizing pass; back: by combine, as further Mulliken partial rows).
+// FP64 (two workgroups per CU): c minimizes the per-CU work ceil(2 tiles c / CUs) / c and is
+// taken when that is at most 3/4 of the unsplit figure (Nb = 1152: c = 3, 486 workgroups).
+// Split forms (one workgroup per CU, whose blocks pay a fixed prologue and epilogue and
+// whose partial products cost the symmetrizing pass more): the largest c whose 2 tiles c
+// workgroups still fit one per CU (Nb = 1152: none; 1017: 2; 504: 4). Measured updates/s,
+// split off / on, FP64 | FP16 x 3 | BF16: 128 atoms 417 / 504 | 1138 / 1052 | 700 / 650 (the
+// split forms' c = 3 there is what this rule now avoids), 113 atoms 605 / 665 | 1255 / 1333 |
+// 778 / 842, 56 atoms 1366 / 1555 | 1794 / 1948 | 1145 / 1289.
 // -DKK_KSPLIT_MAX=1 turns the K-split off (for re-tuning).
 #ifndef KK_KSPLIT_MAX
 #define KK_KSPLIT_MAX 4
 #endif
 constexpr int KSPLIT_MAX = KK_KSPLIT_MAX, KSPLIT_MIN_K = 128;
-int choose_ksplit(int np, int kc, int tiles, int cus, int* chunk_rows) {
+int choose_ksplit(int np, int kc, int tiles, int cus, bool one_per_cu, int* chunk_rows) {
   *chunk_rows = kc;
   if (2 * tiles > cus) return 1;
   auto load = [&](int c) { return (double)((2 * tiles * c + cus - 1) / cus) / c; };
-  int best = 1;
+  int best = 1, best_ck = kc;
   for (int c = 2; c <= KSPLIT_MAX; ++c) {
     const int ck = ((kc + c - 1) / c + KSTEP - 1) / KSTEP * KSTEP;
     if (ck < KSPLIT_MIN_K || c * ck > np) continue;
-    if (load(c) < load(best)) {
+    const bool better = one_per_cu ? 2 * tiles * c <= cus : load(c) < load(best);
+    if (better) {
       best = c;
-      *chunk_rows = ck;
+      best_ck = ck;
     }
   }
-  if (load(best) > 0.75 * load(1)) {
-    *chunk_rows = kc;
-    return 1;
-  }
+  if (!one_per_cu && load(best) > 0.75 * load(1)) return 1;
+  *chunk_rows = best_ck;
   return best;
 }
 
@@ -1017,7 +1022,7 @@ kk_status prepare_impl(kk_handle h, int n_atoms, const int* atom_offsets, int n_
     if (!split_large && !mx_large) {
       const int tiles = mixed ? (np / kk::MSmallCfg::BM) * (np / kk::MSmallCfg::BN)
                               : (np / kk::BackCfg::BM) * (np / kk::BackCfg::BN);
-      h->kch = choose_ksplit(np, h->kc, tiles, cu_count(), &h->kck);
+      h->kch = choose_ksplit(np, h->kc, tiles, cu_count(), mixed, &h->kck);
     }
     // The split back-transform ran slower split (Nb = 1152: 37.4 against 35.1 us): its
     // epilogue (the Mulliken product with G, per tile) is repeated per chunk.

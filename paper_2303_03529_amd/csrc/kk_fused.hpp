@@ -22,7 +22,6 @@ namespace kk {
 
 constexpr int FUSED_MAX_N2 = 1024;   // 2N up to this uses the fused step (N <= 512)
 constexpr int FUSED_THREADS = 256;
-constexpr int FUSED_PER = FUSED_MAX_N2 / FUSED_THREADS;
 constexpr int FUSED_ATOMS = 16;      // atoms per block
 constexpr int FUSED_MAX_BLOCKS = (FUSED_MAX_N2 / 2 + FUSED_ATOMS - 1) / FUSED_ATOMS;
 
@@ -131,8 +130,9 @@ __device__ __forceinline__ void orth_wave0(double* sv, const double* vl, int sta
 // on every orbital of the block's atoms (Sec. III.A). With cvec given (split forms) the
 // potentials are centred by c = cvec . v (the response to a common shift is zero) and
 // pmax[2 blockIdx.x + s] receives the block's largest |u^s - c|.
-// The block first issues all its global loads: src and the first rows of V (up to
-// FUSED_LDS_ROWS doubles) into LDS, its atoms' rows of gamma into registers. Wave 0 then
+// The block first issues all its global loads (the stop flag, src, the centring vector and
+// the first rows of V, up to FUSED_LDS_ROWS doubles, for LDS; its atoms' rows of gamma and
+// orbital ranges into registers) and tests the flag afterwards. Wave 0 then
 // runs the 2 rank projections out of LDS (rows past the staged ones from global memory),
 // and every wave forms its atoms' potentials from the new direction in LDS.
 // Grid: ceil(N / FUSED_ATOMS) blocks of FUSED_THREADS; 2N <= FUSED_MAX_N2.
@@ -240,10 +240,6 @@ __global__ void __launch_bounds__(FUSED_THREADS)
   }
 }
 
-// The split forms' operand split after orth_potentials: the item scales from the blocks'
-// largest centred potentials (as mixed_scales computes them from the potentials; block
-// x = 0 of each item stores them for the products and the symmetrizing pass), then
-// (U~ C)^T split at s_C s_u. Grid (blocks, 2 items).
 // (U~ C)^T at scale s in NP 16-bit pieces for one group of 8 consecutive columns of row r
 // (16-byte loads and stores): the arithmetic of split_scaled_columns_dev.
 template <bool BF16, int NP>

@@ -84,6 +84,13 @@ constexpr int SPLIT_LARGE_NB = KK_SPLIT_LARGE_NB;
 // shapes for its small-tile class (SmallMx in the split form).
 constexpr int SMALL_NP_F64 = 2304;
 using SmallF64 = kk::Cfg64x64;
+// Tiny systems (padded size up to TINY_NP_F64): the same 64 x 64 tiles with a K stage of 32,
+// half the stages of the latency-bound K loop (16 atoms, Nb = 144: 12.2 us per transform on
+// K stages of 16).
+constexpr int TINY_NP_F64 = 256;
+using TinyF64 = kk::TileCfg<64, 64, 32, 2, 2, 2>;
+static_assert(TinyF64::BM == SmallF64::BM && TinyF64::BN == SmallF64::BN && TinyF64::WAVES_N == SmallF64::WAVES_N,
+              "the tiny class shares the small class's tile tables and partial rows");
 using SmallMx = kk::MCfg64x64f8;
 static_assert(kk::PAD % SmallF64::BM == 0 && SPLIT_PAD_LARGE % SmallMx::BM == 0, "small tiles must divide the padding");
 // Rows nb..np-1 of every operand a response transform or a setup product
@@ -92,7 +99,7 @@ static_assert(kk::PAD % SmallF64::BM == 0 && SPLIT_PAD_LARGE % SmallMx::BM == 0,
 // to KSTEP, which every K stage divides. The reverse pass keeps the full np.
 constexpr int KSTEP = 32;
 static_assert(KSTEP % kk::FwdCfg::BK == 0 && KSTEP % kk::BackCfg::BK == 0 && KSTEP % kk::StoreCfg::BK == 0 &&
-                  KSTEP % SmallF64::BK == 0 && KSTEP % kk::MLargeCfg::BK == 0 && KSTEP % kk::MSmallCfg::BK == 0 &&
+                  KSTEP % SmallF64::BK == 0 && KSTEP % TinyF64::BK == 0 && KSTEP % kk::MLargeCfg::BK == 0 && KSTEP % kk::MSmallCfg::BK == 0 &&
                   KSTEP % SmallMx::BK == 0 && kk::PAD % KSTEP == 0,
               "KSTEP must be a multiple of every K stage and divide the padding");
 constexpr size_t WORKSPACE_BUDGET = size_t(12) << 30;  // bytes of Y workspace per handle
@@ -122,6 +129,7 @@ struct kk_handle_s {
   int n_upper = 0, n_full = 0, n_store = 0;
   // small systems: 64 x 64 tiles for the FP64 response transforms
   bool small_f64 = false;
+  bool tiny_f64 = false;  // small_f64 with np <= TINY_NP_F64: TinyF64 kernels
   bool mx_large = false;  // split products on MLargeCfg (else MSmallCfg)
   bool full_fwd = false;  // FP64 forward as full tiles + fermi_symmetrize_f64 (see full_forward)
   int2 *stiles_upper = nullptr, *stiles_full = nullptr;
@@ -431,21 +439,27 @@ kk_status launch_sym_mixed(kk_handle h, const kk::MixedArgs& sa, int nch, size_t
                  : launch_sym_mixed_t<false, 2>(h, sa, nch, cstride);
 }
 
-kk_status launch_gemm(kk_handle h, int epi, kk::GemmArgs& a, bool small = false) {
+// cls: 0 the large tiles (FwdCfg / BackCfg), 1 SmallF64, 2 TinyF64.
+kk_status launch_gemm(kk_handle h, int epi, kk::GemmArgs& a, int cls = 0) {
   const int grid = a.ntiles * a.nitems;
   if (grid <= 0) return KK_OK;
   if (a.nitems > kk::MAX_GEMM_BATCH) return fail(KK_EINVAL, "internal: too many GEMM items");
+  const bool small = cls != 0;
   if (epi == kk::EPI_STORE) {
     kk::gemm_f64<kk::EPI_STORE, kk::StoreCfg><<<grid, kk::StoreCfg::THREADS, 0, h->stream>>>(a);
   } else if (epi == kk::EPI_FERMI) {
     ProfileScope ps(h, 0);
-    if (small)
+    if (cls == 2)
+      kk::gemm_f64<kk::EPI_FERMI, TinyF64><<<grid, TinyF64::THREADS, 0, h->stream>>>(a);
+    else if (cls == 1)
       kk::gemm_f64<kk::EPI_FERMI, SmallF64><<<grid, SmallF64::THREADS, 0, h->stream>>>(a);
     else
       kk::gemm_f64<kk::EPI_FERMI, kk::FwdCfg><<<grid, kk::FwdCfg::THREADS, 0, h->stream>>>(a);
   } else if (epi == kk::EPI_XSTORE) {  // forward: full-tile product into Y, then Y = F o X in place
     ProfileScope ps(h, 0);
-    if (small)
+    if (cls == 2)
+      kk::gemm_f64<kk::EPI_XSTORE, TinyF64><<<grid, TinyF64::THREADS, 0, h->stream>>>(a);
+    else if (cls == 1)
       kk::gemm_f64<kk::EPI_XSTORE, SmallF64><<<grid, SmallF64::THREADS, 0, h->stream>>>(a);
     else
       kk::gemm_f64<kk::EPI_XSTORE, kk::BackCfg><<<grid, kk::BackCfg::THREADS, 0, h->stream>>>(a);
@@ -466,7 +480,9 @@ kk_status launch_gemm(kk_handle h, int epi, kk::GemmArgs& a, bool small = false)
     kk::gemm_f64<kk::EPI_ACCUM, kk::BackCfg><<<grid, kk::BackCfg::THREADS, 0, h->stream>>>(a);
   } else {
     ProfileScope ps(h, 1);
-    if (small)
+    if (cls == 2)
+      kk::gemm_f64<kk::EPI_MULLIKEN, TinyF64><<<grid, TinyF64::THREADS, 0, h->stream>>>(a);
+    else if (cls == 1)
       kk::gemm_f64<kk::EPI_MULLIKEN, SmallF64><<<grid, SmallF64::THREADS, 0, h->stream>>>(a);
     else
       kk::gemm_f64<kk::EPI_MULLIKEN, kk::BackCfg><<<grid, kk::BackCfg::THREADS, 0, h->stream>>>(a);
@@ -607,8 +623,9 @@ kk_status transforms_f64(kk_handle h, int batch, const int* stop) {
       bi.part = h->part + (size_t)z * h->nparts * np;
     }
   kk_status st;
-  if ((st = launch_gemm(h, full ? kk::EPI_XSTORE : kk::EPI_FERMI, fa, small))) return st;
-  if ((st = launch_gemm(h, kk::EPI_MULLIKEN, ba, small))) return st;
+  const int cls = h->tiny_f64 ? 2 : small ? 1 : 0;
+  if ((st = launch_gemm(h, full ? kk::EPI_XSTORE : kk::EPI_FERMI, fa, cls))) return st;
+  if ((st = launch_gemm(h, kk::EPI_MULLIKEN, ba, cls))) return st;
   return KK_OK;
 }
 
@@ -865,7 +882,8 @@ kk_status allocate_prepared(kk_handle h) {
   h->n_store = (int)stt.size();
   static_assert(kk::FwdCfg::MIN_BLOCKS == kk::BackCfg::MIN_BLOCKS, "one slot count for both forward forms");
   h->full_fwd = h->kch > 1 ||
-                (h->small_f64 ? full_forward(h->n_supper, h->n_sfull, cu_count() * SmallF64::MIN_BLOCKS)
+                (h->small_f64 ? full_forward(h->n_supper, h->n_sfull,
+                                            cu_count() * (h->tiny_f64 ? TinyF64::MIN_BLOCKS : SmallF64::MIN_BLOCKS))
                               : full_forward(h->n_upper, h->n_full, cu_count() * kk::BackCfg::MIN_BLOCKS));
   if ((st = dalloc_t(h, &h->tiles_upper, up.size()))) return st;
   if ((st = dalloc_t(h, &h->tiles_full, full.size()))) return st;
@@ -1028,6 +1046,7 @@ kk_status prepare_impl(kk_handle h, int n_atoms, const int* atom_offsets, int n_
     // epilogue (the Mulliken product with G, per tile) is repeated per chunk.
     h->kchb = mixed ? 1 : h->kch;
     h->small_f64 = !mixed && np <= SMALL_NP_F64 && h->kch == 1;
+    h->tiny_f64 = h->small_f64 && np <= TINY_NP_F64;
     h->mx_large = mx_large;
     h->nbase = mixed ? (mx_large ? (np / kk::MLargeCfg::BN) * kk::MLargeCfg::WAVES_N
                                  : (np / kk::MSmallCfg::BN) * kk::MSmallCfg::WAVES_N)

@@ -54,3 +54,26 @@ def test_ksplit_responses_and_kernel(system, precision):
         assert ek < TOL[precision], ek
     finally:
         h.close()
+
+
+def test_ksplit_breakdown_fp64():
+    """delta in a 2-dimensional invariant subspace of K0 J on the 56-atom cluster (four
+    chunks): the expansion stops at rank 2 with KK_BREAKDOWN, every later kernel of the
+    update returns at once, and the result is the oracle's (which stops there too)."""
+    from oracle.krylov import jacobian_exact
+    sysd = make_system(n_atoms=56, seed=20_056)
+    ep = expansion_point(sysd)
+    J = jacobian_exact(sysd, ep)
+    lam, vec = np.linalg.eig(-J)
+    real = np.argsort(np.abs(lam.imag))[:2]
+    delta = np.real(vec[:, real[0]]) * 0.01 + np.real(vec[:, real[1]]) * 0.02
+    h = handle_from_expansion(sysd, ep)
+    try:
+        x, info = h.krylov_kernel_apply(t(delta), 6)
+        ref = kernel_apply(sysd, ep, delta, 6)
+        err = rel(x.cpu().numpy(), ref)
+        print(f"56 atoms breakdown: rank {info.rank_used}, status {info.status}, error {err:.2e}", flush=True)
+        assert info.rank_used == 2 and info.status == krylov.KK_BREAKDOWN
+        assert err < 1e-10
+    finally:
+        h.close()

@@ -92,3 +92,30 @@ def test_U_gradient_terms_sum_to_the_U_gradient(fe16):
     terms = U_gradient_terms(sysd, 4)
     assert abs(terms.sum() - g["U"]) < 1e-10 * np.abs(terms).sum()
     assert np.abs(terms).sum() > 10 * abs(g["U"])
+
+
+def test_U_gradient_terms_entry_by_entry(fe16):
+    """Single terms dL/dgamma_IJ dgamma_IJ/dU, each factor by central differences on the
+    plain numpy forward (one gamma entry perturbed at a time; gamma(U) from the input
+    generator's formula), for the largest off-diagonal and diagonal terms."""
+    sysd, _ = fe16
+    m = 4
+    terms = U_gradient_terms(sysd, m)
+    N = terms.shape[0]
+    off = np.abs(terms) * (1 - np.eye(N))
+    picks = [np.unravel_index(np.argmax(off), off.shape), (int(np.argmax(np.abs(np.diag(terms)))),) * 2]
+    U = float(sysd["U"])
+    gp = gamma_of_U(sysd["r2_bohr"], torch.tensor(U + H, dtype=torch.float64), sysd["hartree_ev"]).numpy()
+    gm = gamma_of_U(sysd["r2_bohr"], torch.tensor(U - H, dtype=torch.float64), sysd["hartree_ev"]).numpy()
+    for I, J in picks:
+        dg = (gp[I, J] - gm[I, J]) / (2 * H)
+        hg = 1e-5 * abs(sysd["gamma"][I, J])
+        Ls = []
+        for sgn in (1, -1):
+            s = dict(sysd)
+            s["gamma"] = sysd["gamma"].copy()
+            s["gamma"][I, J] += sgn * hg
+            x = kernel_apply(s, expansion_point(s), sysd["delta"], m)
+            Ls.append(x @ x)
+        dL = (Ls[0] - Ls[1]) / (2 * hg)
+        assert abs(dL * dg - terms[I, J]) < 1e-5 * abs(terms[I, J]), (I, J, dL * dg, terms[I, J])

@@ -77,3 +77,30 @@ def test_ksplit_breakdown_fp64():
         assert err < 1e-10
     finally:
         h.close()
+
+
+@pytest.mark.parametrize("precision", PRECISIONS, ids=["fp64", "f16x3", "bf16"])
+def test_ksplit_dense_preconditioner(system, precision):
+    """A dense K0 (the fused step then leaves the preconditioning to its own launch after
+    each response) at the two K-split sizes, and for FP64 also the adaptive-rank call (a
+    solve after each direction; at tolerance 0.1 it stops at rank 6 and 8 here, and the
+    split forms' rounding could move a stopping rank across the tolerance), against the
+    oracle."""
+    sysd, ep = system
+    n2 = 2 * sysd["n_atoms"]
+    K0 = -np.eye(n2) + 0.05 * np.random.default_rng(13).standard_normal((n2, n2))
+    h = handle_from_expansion(sysd, ep, precision)
+    try:
+        got, info = h.krylov_kernel_apply(t(sysd["delta"]), 5, K0=t(K0))
+        e1 = rel(got.cpu().numpy(), kernel_apply(sysd, ep, sysd["delta"], 5, K0))
+        print(f"{sysd['n_atoms']} atoms, precision {precision}: dense K0 {e1:.2e} (rank {info.rank_used})",
+              flush=True)
+        assert e1 < TOL[precision]
+        if precision == krylov.KK_FP64:
+            ga, ia = h.krylov_kernel_apply_adaptive(t(sysd["delta"]), 10, 0.1)
+            ra, pa = kernel_apply(sysd, ep, sysd["delta"], 10, tol=0.1, return_parts=True)
+            e2 = rel(ga.cpu().numpy(), ra)
+            print(f"  adaptive {e2:.2e} (rank {ia.rank_used}, oracle {pa['rank']})", flush=True)
+            assert ia.rank_used == pa["rank"] and e2 < TOL[precision]
+    finally:
+        h.close()

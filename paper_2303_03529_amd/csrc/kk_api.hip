@@ -691,6 +691,25 @@ kk_status launch_bf16_step(kk_handle h, bool forward, kk::MixedArgs& a, const _F
 // Split-precision transform step: the forward (full-tile product into the FP32
 // workspace, then the symmetrizing pass that writes the split Y) or the back-transform.
 // a2, b2 (BF16 form only): per item the third pieces of At and Bt for the refinement pass.
+// BF16 form on the small product configuration: one pass over the three pieces of both
+// operands (the four hi/lo products and the two with the third pieces, PROD_ALL6), so that
+// each stage streams the six operand pieces once instead of four in a first pass and four
+// again in the refinement pass. a2, b2, sym, kch as for launch_bf16_step.
+kk_status launch_bf16_single(kk_handle h, bool forward, kk::MixedArgs& a, const _Float16* const* a2,
+                             const _Float16* const* b2, const kk::MixedArgs* sym, int kch) {
+  using Cfg = kk::MSmallBf6;
+  const int grid = a.ntiles * a.nitems;
+  for (int z = 0; z < a.nitems; ++z) { a.item[z].a0r = a2[z]; a.item[z].b0r = b2[z]; }
+  if (forward) {
+    kk::gemm_mixed<kk::EPI_STORE, Cfg><<<grid, Cfg::THREADS, 0, h->stream>>>(a);
+    LAUNCH_CHECK("gemm_mixed bf16 one pass");
+    return launch_sym_mixed(h, sym != nullptr ? *sym : a, kch, (size_t)a.n * a.n);
+  }
+  kk::gemm_mixed<kk::EPI_MULLIKEN, Cfg><<<grid, Cfg::THREADS, 0, h->stream>>>(a);
+  LAUNCH_CHECK("gemm_mixed bf16 one pass");
+  return KK_OK;
+}
+
 // sym, kch: the K-split form, as for launch_bf16_step (small product configuration only).
 kk_status launch_mixed(kk_handle h, bool forward, kk::MixedArgs& a, const _Float16* const* a2 = nullptr,
                        const _Float16* const* b2 = nullptr, const kk::MixedArgs* sym = nullptr, int kch = 1) {
@@ -701,7 +720,7 @@ kk_status launch_mixed(kk_handle h, bool forward, kk::MixedArgs& a, const _Float
   if (h->bf16) {
     ProfileScope ps(h, forward ? 0 : 1);
     return h->mx_large ? launch_bf16_step<kk::MLargeBf1, kk::MLargeBf2>(h, forward, a, a2, b2, sym, kch)
-                       : launch_bf16_step<kk::MSmallBf1, kk::MSmallBf2>(h, forward, a, a2, b2, sym, kch);
+                       : launch_bf16_single(h, forward, a, a2, b2, sym, kch);
   }
   if (forward) {
     ProfileScope ps(h, 0);

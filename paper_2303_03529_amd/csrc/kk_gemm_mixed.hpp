@@ -33,10 +33,13 @@ typedef float f16x __attribute__((ext_vector_type(16)));
 enum { EPI_STORE_ADD = 6, EPI_MULLIKEN_ADD = 7 };
 
 // Products of a split pass, as a mask over the operand pairs (At piece, Bt piece) of a stage:
-// bit 0 (1, 0), bit 1 (0, 1), bit 2 (0, 0), bit 3 (1, 1).
+// bit 0 (1, 0), bit 1 (0, 1), bit 2 (0, 0), bit 3 (1, 1), bit 4 (0, 2), bit 5 (2, 0); bits 4
+// and 5 stream a third piece of each operand (direct-to-LDS loop only).
 constexpr int PROD_F16X3 = 0x7;   // FP16: hi lo, lo hi, hi hi
 constexpr int PROD_ALL4 = 0xF;    // BF16 first pass: hi hi, hi lo, lo hi, lo lo
 constexpr int PROD_CROSS = 0x3;   // BF16 refinement pass on (hi, residual): hi res, res hi
+constexpr int PROD_RES = 0x30;    // hi res and res hi on the third pieces
+constexpr int PROD_ALL6 = 0x3F;   // BF16 in one pass over three pieces: the four of PROD_ALL4 and PROD_RES
 
 // One 32 x 32 x 16 MFMA on 16-bit operands held as raw 8-element registers.
 template <bool BF16>
@@ -66,6 +69,7 @@ __device__ __forceinline__ double from16(_Float16 x) {
 
 struct MixedItem {
   const _Float16 *a0h, *a0l, *b0h, *b0l;  // At, Bt as two 16-bit pieces each, [n][n], k contiguous
+  const _Float16 *a0r, *b0r;              // their third pieces (products with PROD_RES bits)
   _Float16 *yh, *yl, *yr;                 // forward: Y split at scale sc[1] (yr: third BF16 piece)
   const double* g;                        // back: G (FP64)
   const double *eps, *f, *fc, *w;         // forward: spectrum
@@ -104,6 +108,7 @@ struct MixedCfg {
   static_assert(64 % (BK / 8) == 0 && 16 % (BK / 8) == 0, "piece mapping");
   static_assert(BM % (32 * WAVES_M) == 0 && BN % (32 * WAVES_N) == 0, "wave tiling");
   static_assert(BK % 16 == 0, "BK");
+  static_assert((PROD & PROD_RES) == 0, "third pieces need the direct-to-LDS loop");
 };
 
 // Configuration of the direct-to-LDS main loop: BM x BN tile, K stage 32, a ring
@@ -120,7 +125,8 @@ struct MixedDlCfg {
   static constexpr int WTM = BM / WAVES_M / 32, WTN = BN / WAVES_N / 32;
   static constexpr int MIN_BLOCKS = 1;
   static constexpr int A_BLK = BM / 16, B_BLK = BN / 16;     // 1 KB blocks of 16 rows
-  static constexpr int STAGE_BLK = 2 * (A_BLK + B_BLK);        // hi and lo of A and B
+  static constexpr int NPC = (PROD & PROD_RES) ? 3 : 2;        // pieces of each operand streamed
+  static constexpr int STAGE_BLK = NPC * (A_BLK + B_BLK);      // hi, lo (and the third piece) of A and B
   static constexpr int PER_WAVE = STAGE_BLK / WAVES;
   static constexpr int STAGE_BYTES = STAGE_BLK * 1024;
   static constexpr int SMEM_BYTES = NS * STAGE_BYTES;
@@ -383,7 +389,8 @@ __device__ __forceinline__ void wait_vmcnt() {
 // Main loop with direct-to-LDS loads (gfx950 LDS DMA). Each wave instruction
 // global_load_lds_dwordx4 copies 16 bytes per lane into 1 KB of LDS at lane
 // order, i.e. 16 rows x 32 halves of one operand; a stage (K = 32) of A_hi,
-// A_lo, B_hi, B_lo is 2 (BM + BN) / 16 such blocks, shared out over the waves.
+// A_lo, B_hi, B_lo is 2 (BM + BN) / 16 such blocks (with third pieces A_r and B_r,
+// 3 (BM + BN) / 16, in the order A pieces, B pieces), shared out over the waves.
 // Stages go into a ring of NS slots and are issued NS - 1 stages ahead, with no
 // staging registers. Within a block, row r (0..15) holds its four 16-byte
 // k-chunks c at slot 4 r + (c ^ f(r)), f(r) = (((r >> 1) ^ (r >> 3)) & 1) |
@@ -403,7 +410,7 @@ __device__ __forceinline__ void mixed_mainloop_dl(const MixedItem& it, const int
                                                   const int n0, f16x (&acc)[Cfg::WTM][Cfg::WTN]) {
   constexpr int BM = Cfg::BM, BN = Cfg::BN, BK = 32, NS = Cfg::NS, PW = Cfg::PER_WAVE;
   constexpr int WTM = Cfg::WTM, WTN = Cfg::WTN;
-  constexpr int A_BLK = Cfg::A_BLK, B_BLK = Cfg::B_BLK, SB = Cfg::STAGE_BYTES;
+  constexpr int A_BLK = Cfg::A_BLK, B_BLK = Cfg::B_BLK, SB = Cfg::STAGE_BYTES, NPC = Cfg::NPC;
   static_assert(NS >= 3, "the pipelined loop refills a slot one stage after reading it");
   unsigned char* const ring = mixed_smem<Cfg>();
 
@@ -449,20 +456,25 @@ __device__ __forceinline__ void mixed_mainloop_dl(const MixedItem& it, const int
 
   // operand pointers read from the kernel arguments once (scalar loads inside the loop
   // would force lgkmcnt(0) waits and serialize the pipelined LDS reads)
-  const _Float16 *const p0[4] = {it.a0h, it.a0l, it.b0h, it.b0l};
+  const _Float16 *const pa0[3] = {it.a0h, it.a0l, NPC == 3 ? it.a0r : nullptr};
+  const _Float16 *const pb0[3] = {it.b0h, it.b0l, NPC == 3 ? it.b0r : nullptr};
   auto issue = [&](int kt) __attribute__((always_inline)) {
     const int k0 = kt * BK;
-    const _Float16 *ah = p0[0], *al = p0[1], *bh = p0[2], *bl = p0[3];
     unsigned char* slot = ring + (kt % NS) * SB;
 #pragma unroll
     for (int j = 0; j < PW; ++j) {
       const int blk = wave * PW + j;  // wave-uniform
       const _Float16* src;
       int row0;
-      if (blk < A_BLK) { src = ah; row0 = m0 + blk * 16; }
-      else if (blk < 2 * A_BLK) { src = al; row0 = m0 + (blk - A_BLK) * 16; }
-      else if (blk < 2 * A_BLK + B_BLK) { src = bh; row0 = n0 + (blk - 2 * A_BLK) * 16; }
-      else { src = bl; row0 = n0 + (blk - 2 * A_BLK - B_BLK) * 16; }
+      if (blk < NPC * A_BLK) {
+        const int p = blk / A_BLK;
+        src = p == 0 ? pa0[0] : (p == 1 ? pa0[1] : pa0[2]);
+        row0 = m0 + (blk - p * A_BLK) * 16;
+      } else {
+        const int b = blk - NPC * A_BLK, p = b / B_BLK;
+        src = p == 0 ? pb0[0] : (p == 1 ? pb0[1] : pb0[2]);
+        row0 = n0 + (b - p * B_BLK) * 16;
+      }
       const _Float16* g = src + (size_t)(row0 + rr) * n + k0 + gch * 8;
       __builtin_amdgcn_global_load_lds((const void*)g,
                                        (void __attribute__((address_space(3)))*)(slot + blk * 1024), 16, 0, 0);
@@ -479,24 +491,38 @@ __device__ __forceinline__ void mixed_mainloop_dl(const MixedItem& it, const int
     __builtin_amdgcn_s_barrier();
     if (s + NS - 1 < nk) issue(s + NS - 1);
   };
-  auto load = [&](h8 (&xa)[WTM][2], h8 (&xb)[WTN][2], int s, int ks) __attribute__((always_inline)) {
+  auto load = [&](h8 (&xa)[WTM][NPC], h8 (&xb)[WTN][NPC], int s, int ks) __attribute__((always_inline)) {
     const unsigned char* slot = ring + (s % NS) * SB;
     const int c = ks * 2 + lh;
 #pragma unroll
     for (int i = 0; i < WTM; ++i) {
       const int off = aoff[i] + ((c ^ af[i]) << 4);
-      xa[i][0] = *reinterpret_cast<const h8*>(slot + off);
-      xa[i][1] = *reinterpret_cast<const h8*>(slot + A_BLK * 1024 + off);
+#pragma unroll
+      for (int p = 0; p < NPC; ++p) xa[i][p] = *reinterpret_cast<const h8*>(slot + p * A_BLK * 1024 + off);
     }
 #pragma unroll
     for (int j = 0; j < WTN; ++j) {
       const int off = boff[j] + ((c ^ bf[j]) << 4);
-      xb[j][0] = *reinterpret_cast<const h8*>(slot + 2 * A_BLK * 1024 + off);
-      xb[j][1] = *reinterpret_cast<const h8*>(slot + (2 * A_BLK + B_BLK) * 1024 + off);
+#pragma unroll
+      for (int p = 0; p < NPC; ++p)
+        xb[j][p] = *reinterpret_cast<const h8*>(slot + (NPC * A_BLK + p * B_BLK) * 1024 + off);
     }
   };
-  auto mfma = [&](const h8 (&xa)[WTM][2], const h8 (&xb)[WTN][2]) __attribute__((always_inline)) {
+  auto mfma = [&](const h8 (&xa)[WTM][NPC], const h8 (&xb)[WTN][NPC]) __attribute__((always_inline)) {
     constexpr bool BF = Cfg::BF16;
+    // the smallest products first: third-piece products, lo lo, the cross terms, hi hi
+    if constexpr (Cfg::PROD & 32) {
+#pragma unroll
+      for (int i = 0; i < WTM; ++i)
+#pragma unroll
+        for (int j = 0; j < WTN; ++j) acc[i][j] = mfma16<BF>(xa[i][NPC - 1], xb[j][0], acc[i][j]);
+    }
+    if constexpr (Cfg::PROD & 16) {
+#pragma unroll
+      for (int i = 0; i < WTM; ++i)
+#pragma unroll
+        for (int j = 0; j < WTN; ++j) acc[i][j] = mfma16<BF>(xa[i][0], xb[j][NPC - 1], acc[i][j]);
+    }
     if constexpr (Cfg::PROD & 8) {
 #pragma unroll
       for (int i = 0; i < WTM; ++i)
@@ -523,7 +549,7 @@ __device__ __forceinline__ void mixed_mainloop_dl(const MixedItem& it, const int
     }
   };
 
-  h8 pa[WTM][2], pb[WTN][2], qa[WTM][2], qb[WTN][2];
+  h8 pa[WTM][NPC], pb[WTN][NPC], qa[WTM][NPC], qb[WTN][NPC];
 #pragma unroll
   for (int s = 0; s < NS - 1; ++s)
     if (s < nk) issue(s);
@@ -722,6 +748,9 @@ using MLargeBf1 = WithProducts<MLargeCfg, true, PROD_ALL4>::type;
 using MLargeBf2 = WithProducts<MLargeCfg, true, PROD_CROSS>::type;
 using MSmallBf1 = WithProducts<MSmallCfg, true, PROD_ALL4>::type;
 using MSmallBf2 = WithProducts<MSmallCfg, true, PROD_CROSS>::type;
+// The small shape streams three pieces in one pass (144 KB of ring at 128 x 128), the large
+// one cannot (216 KB at 256 x 128) and keeps the two passes.
+using MSmallBf6 = WithProducts<MSmallCfg, true, PROD_ALL6>::type;
 
 // Padded dimension of a split-precision handle: the larger tile side of its product
 // configuration, so that the tiles cover the padded matrices exactly.

@@ -40,8 +40,8 @@ DTYPE = {"fp64": "f64", "mixed": "f16x3+f64", "bf16": "bf16x6+f64"}
 FORM = {"fp64": "FP64 transforms",
         "mixed": "split FP16 x 3 transforms (FP32 accumulation), FP64 divided differences, mu shift, Mulliken "
                  "sums and m x m solve",
-        "bf16": "BF16 transforms: hi/lo products (4) plus a refinement pass over the residual pieces (2), FP32 "
-                "accumulation; FP64 elsewhere"}
+        "bf16": "BF16 transforms: hi/lo products (4) plus the refinement products over the residual pieces (2; a "
+                "second pass above Nb = 2304, the same pass below), FP32 accumulation; FP64 elsewhere"}
 
 
 def parse():

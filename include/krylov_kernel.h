@@ -63,7 +63,9 @@ typedef enum {
  *                 residual pieces, hi*res + res*hi, and adds them to what the
  *                 first pass stored (the forward product before its Fermi
  *                 Hadamard step; the back-transform's Mulliken sums, which are
- *                 linear in the product). Six products per transform instead of
+ *                 linear in the product). Up to Nb = 2304 both sets of products
+ *                 run in one pass over the three pieces (same products, one
+ *                 FP32 accumulation). Six products per transform instead of
  *                 KK_MIXED_F16's three; BF16's exponent range needs no scaling.
  *                 FP64 elsewhere as above; agreement with FP64 ~1e-7 relative.
  *                 Single-system handles only (not in kk_batch_prepare).

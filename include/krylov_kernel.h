@@ -152,13 +152,12 @@ kk_status mulliken_project(kk_handle h, int batch, const double *dD_up, const do
  * If O is not positive definite, Kdelta is set to zero and info->status (and
  * the return value when info is given) is KK_ESINGULAR.
  * Unless kernel timing is on (kk_profile_enable), the update runs as one graph
- * launch on a private stream of the handle, ordered after the work already on
- * the handle's stream and before work enqueued there after the call (events);
- * the graph is captured on first use and again when K0 (the pointer), m, the
- * tolerance, the handle's buffers or the prepared W or kT change (a re-prepare
- * of the same shape, W and kT replays the existing graph on the new data).
- * delta is copied in and Kdelta out on device, so the caller's buffers may
- * change from call to call.
+ * launch on the handle's stream; the graph is captured on first use and again
+ * when K0 (the pointer), m, the tolerance, the handle's buffers or the prepared
+ * W or kT change (a re-prepare of the same shape, W and kT replays the existing
+ * graph on the new data). The graph reads delta and writes Kdelta where they
+ * are; a call whose delta or Kdelta pointer differs from the previous call's
+ * first synchronizes the handle's stream and then points the graph at them.
  */
 kk_status krylov_kernel_apply(kk_handle h, const double *delta, int m, const double *K0,
                               double *Kdelta, kk_info *info);

@@ -175,17 +175,25 @@ struct kk_handle_s {
   long prepare_gen = 0;  // bumped by every successful kk_prepare
   long alloc_gen = 0;    // bumped by every device allocation of the handle
 
-  // Captured single-system update (krylov_run without profiling): launched on a private
-  // stream joined to the caller's by events, reading delta from and writing K delta to
-  // handle-owned buffers so that the graph's pointers stay fixed; replayed while its key
-  // (K0, m, tol, allocation generation, W, beta) holds.
+  // Captured single-system update (krylov_run without profiling): captured on a private
+  // stream (the caller's may be the null stream, which cannot capture) and replayed on the
+  // handle's stream while its key (K0, m, tol, allocation generation, W, beta) holds. The
+  // caller's delta and K delta are arguments of two kinds of kernel node (the first
+  // precondition reads delta, every krylov_solve writes K delta); a call with other
+  // pointers rewrites those nodes' arguments in the executable graph.
   hipStream_t gstream = nullptr;
-  hipEvent_t g_in = nullptr, g_out = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
-  std::vector<void*> g_owned;
-  double *gdelta = nullptr, *gkd = nullptr;
-  int g_cap = 0;
+  struct GraphArgNode {
+    hipGraphNode_t node;
+    hipKernelNodeParams p;
+  };
+  GraphArgNode g_pre{};                // precondition(K0, delta, sub, y, n2, stop, reset)
+  kk::PreconditionArgs g_pre_args{};
+  std::vector<GraphArgNode> g_solve;   // krylov_solve(V, Ft, ftilde, n2, st, Kdelta, tol)
+  std::vector<kk::SolveArgs> g_solve_args;
+  const double* g_delta = nullptr;
+  double* g_kd = nullptr;
   const double* g_K0 = nullptr;
   int g_m = -1;
   double g_tol = -1.0;
@@ -199,6 +207,8 @@ struct kk_handle_s {
     gexec = nullptr;
     graph = nullptr;
     g_m = -1;
+    g_solve.clear();
+    g_solve_args.clear();
   }
 
   // reverse-pass workspace (krylov_kernel_adjoint), allocated on first use
@@ -1000,11 +1010,9 @@ kk_status kk_destroy(kk_handle h) {
   if (!h) return fail(KK_EINVAL, "kk_destroy: handle is NULL");
   h->release();
   for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+  (void)hipStreamSynchronize(h->stream);
   if (h->gstream) (void)hipStreamSynchronize(h->gstream);
   h->drop_graph();
-  for (void* p : h->g_owned) (void)hipFree(p);
-  if (h->g_in) (void)hipEventDestroy(h->g_in);
-  if (h->g_out) (void)hipEventDestroy(h->g_out);
   if (h->gstream) (void)hipStreamDestroy(h->gstream);
   delete h;
   return KK_OK;
@@ -1273,46 +1281,27 @@ kk_status enqueue_krylov(kk_handle h, const double* delta, int m, double tol, co
 }
 
 // One update as a graph launch: capture on first use and whenever the key changes.
+kk_status find_graph_args(kk_handle h, const double* delta, double* Kdelta);
+kk_status set_graph_args(kk_handle h, const double* delta, double* Kdelta);
+
 kk_status krylov_graph(kk_handle h, const double* delta, int m, double tol, const double* K0, double* Kdelta) {
-  const int n2 = 2 * h->natoms;
-  if (!h->gstream) {
-    HIP_OR_FAIL(hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking));
-    HIP_OR_FAIL(hipEventCreateWithFlags(&h->g_in, hipEventDisableTiming));
-    HIP_OR_FAIL(hipEventCreateWithFlags(&h->g_out, hipEventDisableTiming));
-  }
-  if (n2 > h->g_cap) {
-    HIP_OR_FAIL(hipStreamSynchronize(h->gstream));
-    h->drop_graph();
-    for (void* p : h->g_owned) (void)hipFree(p);
-    h->g_owned.clear();
-    h->gdelta = h->gkd = nullptr;
-    h->g_cap = 0;
-    void *a = nullptr, *b = nullptr;
-    kk_status st;
-    if ((st = dalloc(h->g_owned, &a, sizeof(double) * n2))) return st;
-    if ((st = dalloc(h->g_owned, &b, sizeof(double) * n2))) return st;
-    h->gdelta = static_cast<double*>(a);
-    h->gkd = static_cast<double*>(b);
-    h->g_cap = n2;
-  }
+  if (!h->gstream) HIP_OR_FAIL(hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking));
   hipStream_t user = h->stream;
-  HIP_OR_FAIL(hipEventRecord(h->g_in, user));
-  HIP_OR_FAIL(hipStreamWaitEvent(h->gstream, h->g_in, 0));
-  HIP_OR_FAIL(hipMemcpyAsync(h->gdelta, delta, sizeof(double) * n2, hipMemcpyDeviceToDevice, h->gstream));
   // The graph bakes in buffer pointers and two prepared scalars (W and beta = 1/kT); a
   // prepare of the same shape rewrites the buffers in place, so it keeps the graph unless
   // one of those scalars changed.
   if (!h->gexec || h->g_K0 != K0 || h->g_m != m || h->g_tol != tol || h->g_gen != h->alloc_gen ||
       h->g_W != h->W || h->g_beta != h->beta) {
-    // the last replay may still be running on gstream: let it finish before its exec goes
-    HIP_OR_FAIL(hipStreamSynchronize(h->gstream));
+    // the last replay may still be running on the handle's stream: let it finish before its
+    // exec goes
+    HIP_OR_FAIL(hipStreamSynchronize(user));
     h->drop_graph();
     h->stream = h->gstream;
     hipError_t e = hipStreamBeginCapture(h->gstream, hipStreamCaptureModeThreadLocal);
     kk_status st = KK_OK;
     hipGraph_t g = nullptr;
     if (e == hipSuccess) {
-      st = enqueue_krylov(h, h->gdelta, m, tol, K0, h->gkd);
+      st = enqueue_krylov(h, delta, m, tol, K0, Kdelta);
       e = hipStreamEndCapture(h->gstream, &g);
     }
     h->stream = user;
@@ -1331,6 +1320,11 @@ kk_status krylov_graph(kk_handle h, const double* delta, int m, double tol, cons
       return fail(KK_EHIP, "graph instantiation failed: %s", hipGetErrorString(e));
     }
     h->graph = g;
+    if ((st = find_graph_args(h, delta, Kdelta))) {
+      h->drop_graph();
+      h->no_graph = true;
+      return st;
+    }
     h->g_K0 = K0;
     h->g_m = m;
     h->g_tol = tol;
@@ -1338,10 +1332,80 @@ kk_status krylov_graph(kk_handle h, const double* delta, int m, double tol, cons
     h->g_W = h->W;
     h->g_beta = h->beta;
   }
-  HIP_OR_FAIL(hipGraphLaunch(h->gexec, h->gstream));
-  HIP_OR_FAIL(hipMemcpyAsync(Kdelta, h->gkd, sizeof(double) * n2, hipMemcpyDeviceToDevice, h->gstream));
-  HIP_OR_FAIL(hipEventRecord(h->g_out, h->gstream));
-  HIP_OR_FAIL(hipStreamWaitEvent(user, h->g_out, 0));
+  if (delta != h->g_delta || Kdelta != h->g_kd) {
+    // an executable graph's node is not rewritten under a replay that may still run
+    HIP_OR_FAIL(hipStreamSynchronize(user));
+    kk_status st = set_graph_args(h, delta, Kdelta);
+    if (st) return st;
+  }
+  HIP_OR_FAIL(hipGraphLaunch(h->gexec, user));
+  return KK_OK;
+}
+
+// The kernel nodes of a freshly captured update that take the caller's pointers: the
+// precondition whose input is delta (the first launch) and every krylov_solve, which
+// writes K delta. Their arguments are kept so that set_graph_args can rebuild them.
+kk_status find_graph_args(kk_handle h, const double* delta, double* Kdelta) {
+  size_t n = 0;
+  HIP_OR_FAIL(hipGraphGetNodes(h->graph, nullptr, &n));
+  std::vector<hipGraphNode_t> nodes(n);
+  HIP_OR_FAIL(hipGraphGetNodes(h->graph, nodes.data(), &n));
+  int npre = 0;
+  for (hipGraphNode_t nd : nodes) {
+    hipGraphNodeType type;
+    HIP_OR_FAIL(hipGraphNodeGetType(nd, &type));
+    if (type != hipGraphNodeTypeKernel) continue;
+    hipKernelNodeParams p{};
+    HIP_OR_FAIL(hipGraphKernelNodeGetParams(nd, &p));
+    if (p.kernelParams == nullptr) continue;
+    if (p.func == reinterpret_cast<void*>(&kk::precondition)) {
+      const kk::PreconditionArgs a = kk::PreconditionArgs::from(p.kernelParams);
+      if (a.x != delta || a.reset == nullptr) continue;
+      h->g_pre = {nd, p};
+      h->g_pre_args = a;
+      ++npre;
+    } else if (p.func == reinterpret_cast<void*>(&kk::krylov_solve)) {
+      const kk::SolveArgs a = kk::SolveArgs::from(p.kernelParams);
+      if (a.out != Kdelta) continue;
+      h->g_solve.push_back({nd, p});
+      h->g_solve_args.push_back(a);
+    }
+  }
+  if (npre != 1 || h->g_solve.empty())
+    return fail(KK_EHIP, "graph: found %d input and %zu output nodes in the captured update", npre,
+                h->g_solve.size());
+  h->g_delta = delta;
+  h->g_kd = Kdelta;
+  return KK_OK;
+}
+
+kk_status set_graph_args(kk_handle h, const double* delta, double* Kdelta) {
+  if (delta != h->g_delta) {
+    kk::PreconditionArgs a = h->g_pre_args;
+    a.x = delta;
+    void* args[kk::PreconditionArgs::COUNT];
+    a.pointers(args);
+    hipKernelNodeParams p = h->g_pre.p;
+    p.kernelParams = args;
+    p.extra = nullptr;
+    HIP_OR_FAIL(hipGraphExecKernelNodeSetParams(h->gexec, h->g_pre.node, &p));
+    h->g_pre_args = a;
+    h->g_delta = delta;
+  }
+  if (Kdelta != h->g_kd) {
+    for (size_t i = 0; i < h->g_solve.size(); ++i) {
+      kk::SolveArgs a = h->g_solve_args[i];
+      a.out = Kdelta;
+      void* args[kk::SolveArgs::COUNT];
+      a.pointers(args);
+      hipKernelNodeParams p = h->g_solve[i].p;
+      p.kernelParams = args;
+      p.extra = nullptr;
+      HIP_OR_FAIL(hipGraphExecKernelNodeSetParams(h->gexec, h->g_solve[i].node, &p));
+      h->g_solve_args[i] = a;
+    }
+    h->g_kd = Kdelta;
+  }
   return KK_OK;
 }
 

@@ -593,6 +593,50 @@ __global__ void __launch_bounds__(1024) krylov_solve(const double* __restrict__ 
   solve_dev(V, Ft, ftilde, n2, st, x, stop_tol);
 }
 
+// Host-side copies of the argument lists of precondition and krylov_solve (declaration
+// order), read from and written back to a kernel node of a captured graph so that a replay
+// can take other input and output pointers.
+template <class T>
+inline T kernel_arg(void** kp, int i) {
+  T v;
+  __builtin_memcpy(&v, kp[i], sizeof v);
+  return v;
+}
+
+struct PreconditionArgs {
+  static constexpr int COUNT = 7;
+  const double *K0, *x, *sub;
+  double* y;
+  int n2;
+  const int* stop;
+  KrylovState* reset;
+  static PreconditionArgs from(void** kp) {
+    return {kernel_arg<const double*>(kp, 0), kernel_arg<const double*>(kp, 1), kernel_arg<const double*>(kp, 2),
+            kernel_arg<double*>(kp, 3),       kernel_arg<int>(kp, 4),           kernel_arg<const int*>(kp, 5),
+            kernel_arg<KrylovState*>(kp, 6)};
+  }
+  void pointers(void** out) {
+    out[0] = &K0; out[1] = &x; out[2] = &sub; out[3] = &y; out[4] = &n2; out[5] = &stop; out[6] = &reset;
+  }
+};
+
+struct SolveArgs {
+  static constexpr int COUNT = 7;
+  const double *V, *Ft, *ftilde;
+  int n2;
+  KrylovState* st;
+  double* out;
+  double tol;
+  static SolveArgs from(void** kp) {
+    return {kernel_arg<const double*>(kp, 0), kernel_arg<const double*>(kp, 1), kernel_arg<const double*>(kp, 2),
+            kernel_arg<int>(kp, 3),           kernel_arg<KrylovState*>(kp, 4),  kernel_arg<double*>(kp, 5),
+            kernel_arg<double>(kp, 6)};
+  }
+  void pointers(void** o) {
+    o[0] = &V; o[1] = &Ft; o[2] = &ftilde; o[3] = &n2; o[4] = &st; o[5] = &out; o[6] = &tol;
+  }
+};
+
 // (q, m) Mulliken vector of per-spin atom populations: out = (p_up + p_dn - ref, p_up - p_dn),
 // ref = neutral-atom populations (may be null).
 __global__ void mix_spins(const double* __restrict__ p, const double* __restrict__ ref, int natoms,

@@ -2,7 +2,8 @@
 launch-by-launch path: the same handle with kernel timing on, which takes the
 launch-by-launch path, and off, which replays the graph. Covered: several
 replays with other GPU work between them, new inputs in the same and in new
-buffers, a change of rank and of tolerance, a reverse pass that reuses the
+buffers, input and output pointers that change between back-to-back replays, a
+change of rank and of tolerance, a reverse pass that reuses the
 forward's expansion, and a second prepare of the same handle."""
 
 import numpy as np
@@ -128,5 +129,35 @@ def test_graph_recapture_without_host_sync():
             h.prepare(*args, sysd["W"] * wscale, sysd["kT"], sysd["n_electrons"], krylov.KK_FP64)
             ref, _ = launch_by_launch(h, delta, m)
             assert close(o, ref), (m, wscale)
+    finally:
+        h.close()
+
+
+@pytest.mark.parametrize("precision", [krylov.KK_FP64, krylov.KK_MIXED_F16], ids=["fp64", "split"])
+def test_graph_pointer_changes_back_to_back(precision):
+    """Replays of one captured update (same key) whose input and output pointers change
+    from call to call (input only, output only, both, neither), issued back to back with no
+    host synchronization: the graph reads each call's delta and writes each call's K delta
+    where they are, and every output buffer ends up holding the launch-by-launch result of
+    the last call that wrote it."""
+    sysd = make_system(4, seed=128)
+    ep = expansion_point(sysd)
+    h = handle_from_expansion(sysd, ep, precision)
+    try:
+        n2 = 2 * h.n_atoms
+        rng = np.random.default_rng(55)
+        ins = [t(sysd["delta"])] + [t(1e-2 * rng.standard_normal(n2)) for _ in range(2)]
+        outs = [torch.empty_like(ins[0]) for _ in range(4)]
+        plan = [(0, 0), (0, 0), (1, 0), (1, 1), (2, 2), (0, 3), (2, 1), (2, 1)]
+        last = {}
+        for i, o in plan:
+            h.krylov_kernel_apply(ins[i], 8, out=outs[o], info=False)
+            last[o] = i
+        torch.cuda.synchronize()
+        got = {o: outs[o].clone() for o in last}
+        for o, i in last.items():
+            ref, _ = launch_by_launch(h, ins[i], 8)
+            assert close(got[o], ref), (o, i)
+        assert rel(got[3].cpu().numpy(), kernel_apply(sysd, ep, sysd["delta"], 8)) < TOL[precision]
     finally:
         h.close()

@@ -1,5 +1,5 @@
 """Split-precision paths against the FP64 oracle: FP16 x 3 MFMA products, and
-BF16 products with their refinement pass (every test runs for both forms).
+BF16 products with their refinement products (every test runs for both forms).
 
 Bound: 1e-6 relative (2-norm) on every response and on the Krylov kernel
 result, the accuracy the mixed-precision forms are held to; the measured

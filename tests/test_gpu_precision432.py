@@ -1,5 +1,5 @@
 """Precision form at 432 atoms (6x6x6 bcc Fe, Nb = 3888, rank 8): the FP64, the
-split FP16 x 3 and the BF16 (with its refinement pass) transforms against the
+split FP16 x 3 and the BF16 (with its refinement products) transforms against the
 FP64 oracle, error per output.
 
 Both handles are prepared from the device eigensolve (independent of the

@@ -113,8 +113,8 @@ struct kk_handle_s {
   int natoms = 0, nb = 0, np = 0, nparts = 0;
   int kc = 0;  // contraction length of the transforms: nb rounded up to KSTEP (<= np)
   // K-split of the response transforms (choose_ksplit): the forward in kch chunks of kck rows,
-  // the back-transform in kchb (FP64: kch; split forms: 1), nbase Mulliken partial rows per
-  // back chunk (nparts = kchb nbase)
+  // the back-transform in kchb (= kch), nbase Mulliken partial rows per back chunk
+  // (nparts = kchb nbase)
   int kch = 1, kchb = 1, kck = 0, nbase = 0;
   double W = 0, kT = 0, beta = 0, n_e = 0;
   std::vector<void*> owned;  // every device allocation of the prepared state
@@ -799,11 +799,11 @@ kk_status response_chunk_mixed(kk_handle h, int batch, const double* v, double* 
     LAUNCH_CHECK("split_operands");
   }
   // forward: A = C^T U~ G over full tiles (At = (U~ C)^T, Bt = G^T), X = (A + A^T) / 2.
-  // K-split (kch > 1, forward only): item z's chunk j is GEMM item z kch + j over contraction
-  // rows [j kck, (j + 1) kck) (operands k-contiguous: a column offset) with its FP32 partial
+  // K-split (kch > 1): item z's forward chunk j is GEMM item z kch + j over contraction rows
+  // [j kck, (j + 1) kck) (operands k-contiguous: a column offset) with its FP32 partial
   // product at x32 + (z kch + j) np^2; sa holds the unsplit items for the symmetrizing pass,
-  // which sums the partials. (A split back-transform, kchb > 1, would write chunk j's Mulliken
-  // partials at rows j nbase.. of the item's partials.)
+  // which sums the partials. Back chunk j (kchb = kch) writes its Mulliken partials at rows
+  // j nbase.. of the item's partials, which the combine sums with the rest.
   const int kch = h->kch, kchb = h->kchb;
   const size_t ck = kch > 1 ? h->kck : 0, ckb = kchb > 1 ? h->kck : 0;
   kk::MixedArgs fa{};
@@ -1069,9 +1069,12 @@ kk_status prepare_impl(kk_handle h, int n_atoms, const int* atom_offsets, int n_
                               : (np / kk::BackCfg::BM) * (np / kk::BackCfg::BN);
       h->kch = choose_ksplit(np, h->kc, tiles, cu_count(), mixed, &h->kck);
     }
-    // The split back-transform ran slower split (Nb = 1152: 37.4 against 35.1 us): its
-    // epilogue (the Mulliken product with G, per tile) is repeated per chunk.
-    h->kchb = mixed ? 1 : h->kch;
+    // Both transforms split alike. (The split back-transform repeats its epilogue, the
+    // Mulliken product with G, per chunk; split into two rounds of workgroups, as the FP64
+    // rule would have it at Nb = 1152, it ran slower, 37.4 against 35.1 us, but in the one
+    // round the split forms' rule allows it is faster: 113 atoms, m = 8, FP16 x 3 1480 ->
+    // 1627 updates/s, BF16 1169 -> 1320; 56 atoms 2241 -> 2575 and 1916 -> 2370.)
+    h->kchb = h->kch;
     h->small_f64 = !mixed && np <= SMALL_NP_F64 && h->kch == 1;
     h->tiny_f64 = h->small_f64 && np <= TINY_NP_F64;
     h->mx_large = mx_large;

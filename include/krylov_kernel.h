@@ -168,12 +168,12 @@ kk_status krylov_kernel_apply(kk_handle h, const double *delta, int m, const dou
  * harnesses that forbid hipMalloc). Same arguments, result and errors as
  * krylov_kernel_apply on a prepared handle, but the call itself allocates
  * nothing (no hipMalloc or hipFree, no library routine that allocates, no graph
- * of its own): the one-direction response workspace comes from a fixed 64 MiB
+ * of its own): the one-direction response workspace comes from a fixed 96 MiB
  * device array of the library, which every GPU holds until the process ends,
  * and the launches go straight onto the handle's stream. A handle whose
  * workspace does not fit is refused with KK_EINVAL before anything is enqueued
- * (handles of Nb <= 1408, e.g. 128-atom bcc Fe at Nb = 1152, fit in every
- * precision; FP64 up to Nb = 1920, KK_MIXED_F16 up to 1536). kk_prepare still
+ * (handles of Nb <= 1664, e.g. 128-atom bcc Fe at Nb = 1152, fit in every
+ * precision; FP64 up to Nb = 2432, KK_MIXED_F16 up to 1920). kk_prepare still
  * allocates the handle's prepared state.
  * All calls on one GPU share that array and it keeps the last call's contents:
  * calls that overlap on one GPU (two streams, or two threads) race, so the

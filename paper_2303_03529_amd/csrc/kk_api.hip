@@ -116,6 +116,10 @@ struct kk_handle_s {
   // the back-transform in kchb (= kch), nbase Mulliken partial rows per back chunk
   // (nparts = kchb nbase)
   int kch = 1, kchb = 1, kck = 0, nbase = 0;
+  // Stream-K products (split forms, small shape; choose_stream_k): kch = kchb = the slots
+  // of partial results per item, sk_grid workgroups per product launch
+  bool sk = false;
+  int sk_grid = 0;
   double W = 0, kT = 0, beta = 0, n_e = 0;
   std::vector<void*> owned;  // every device allocation of the prepared state
 
@@ -358,6 +362,33 @@ int choose_ksplit(int np, int kc, int tiles, int cus, bool one_per_cu, int* chun
   return best;
 }
 
+// Stream-K products for the split forms' small shape (gemm_mixed_sk), taken where no
+// one-round K-split applies and one workgroup per tile would leave the workgroup rounds
+// on the chip's CUs less than SK_FILL full. Returns the most segments of any tile of a
+// one-direction launch (the slots per item; launches of more directions need no more), or
+// 1 for no stream-K. The products stream their operands at about the same aggregate rate
+// whether 162 or 256 CUs run them (the clock drops as more of them run), so stream-K gains
+// only where a round is mostly empty: measured in one process, m = 8, FP16 x 3 / BF16
+// updates/s without / with it, 170 atoms (Nb = 1530, 288 tiles, 2 rounds 56 % full)
+// 608 / 676 and 412 / 460, but 128 atoms (162 tiles, 63 %) 1240 / 1152 and 940 / 911, 250
+// atoms (648 tiles, 84 %) 289 / 246 and 189 / 161.
+#ifndef KK_STREAM_K
+#define KK_STREAM_K 1
+#endif
+constexpr double SK_FILL = 0.6;
+int choose_stream_k(int tiles_per_item, int nk, int cus) {
+  if (!KK_STREAM_K) return 1;
+  const int tiles = 2 * tiles_per_item, rounds = (tiles + cus - 1) / cus;
+  // fewer tiles are the one-round K-split's; the slot of a segment counts the workgroups
+  // between it and its tile's first, which needs every range non-empty (stages >= grid)
+  if (2 * tiles < cus || (long)tiles * nk < cus) return 1;
+  if ((double)tiles / ((double)rounds * cus) >= SK_FILL) return 1;
+  const long total = (long)tiles * nk;
+  int slots = 1;
+  for (int t = 0; t < tiles; ++t) slots = std::max(slots, kk::sk_segments(t, nk, cus, total));
+  return slots;
+}
+
 // Form of the FP64 forward transform of one direction (both spins): the upper
 // tiles over two K halves with the Fermi product in the epilogue, or all tiles
 // over one half (half the cost each) followed by fermi_symmetrize_f64. The full
@@ -380,7 +411,7 @@ bool full_forward(int n_upper, int n_full, int slots) {
 std::vector<int2> tile_order(int np, int bm, int bn, bool upper) {
   std::vector<int2> v;
   const int TM = np / bm, TN = np / bn;
-  const int GROUP = 4;
+  const int GROUP = kk::TILE_GROUP;  // the order kk::tile_table_pos computes
   for (int g0 = 0; g0 < TM; g0 += GROUP)
     for (int tn = 0; tn < TN; ++tn)
       for (int tm = g0; tm < std::min(TM, g0 + GROUP); ++tm)
@@ -711,11 +742,17 @@ kk_status launch_bf16_single(kk_handle h, bool forward, kk::MixedArgs& a, const 
   const int grid = a.ntiles * a.nitems;
   for (int z = 0; z < a.nitems; ++z) { a.item[z].a0r = a2[z]; a.item[z].b0r = b2[z]; }
   if (forward) {
-    kk::gemm_mixed<kk::EPI_STORE, Cfg><<<grid, Cfg::THREADS, 0, h->stream>>>(a);
+    if (a.sk_grid > 0)
+      kk::gemm_mixed_sk<kk::EPI_STORE, Cfg><<<a.sk_grid, Cfg::THREADS, 0, h->stream>>>(a);
+    else
+      kk::gemm_mixed<kk::EPI_STORE, Cfg><<<grid, Cfg::THREADS, 0, h->stream>>>(a);
     LAUNCH_CHECK("gemm_mixed bf16 one pass");
     return launch_sym_mixed(h, sym != nullptr ? *sym : a, kch, (size_t)a.n * a.n);
   }
-  kk::gemm_mixed<kk::EPI_MULLIKEN, Cfg><<<grid, Cfg::THREADS, 0, h->stream>>>(a);
+  if (a.sk_grid > 0)
+    kk::gemm_mixed_sk<kk::EPI_MULLIKEN, Cfg><<<a.sk_grid, Cfg::THREADS, 0, h->stream>>>(a);
+  else
+    kk::gemm_mixed<kk::EPI_MULLIKEN, Cfg><<<grid, Cfg::THREADS, 0, h->stream>>>(a);
   LAUNCH_CHECK("gemm_mixed bf16 one pass");
   return KK_OK;
 }
@@ -726,7 +763,7 @@ kk_status launch_mixed(kk_handle h, bool forward, kk::MixedArgs& a, const _Float
   const int grid = a.ntiles * a.nitems;
   if (grid <= 0) return KK_OK;
   if (a.nitems > kk::MAX_GEMM_BATCH) return fail(KK_EINVAL, "internal: too many GEMM items");
-  if (kch > 1 && h->mx_large) return fail(KK_EINVAL, "internal: K-split on the large split tiles");
+  if ((kch > 1 || a.sk_grid > 0) && h->mx_large) return fail(KK_EINVAL, "internal: K-split on the large split tiles");
   if (h->bf16) {
     ProfileScope ps(h, forward ? 0 : 1);
     return h->mx_large ? launch_bf16_step<kk::MLargeBf1, kk::MLargeBf2>(h, forward, a, a2, b2, sym, kch)
@@ -736,6 +773,8 @@ kk_status launch_mixed(kk_handle h, bool forward, kk::MixedArgs& a, const _Float
     ProfileScope ps(h, 0);
     if (h->mx_large)
       kk::gemm_mixed<kk::EPI_STORE, kk::MLargeCfg><<<grid, kk::MLargeCfg::THREADS, 0, h->stream>>>(a);
+    else if (a.sk_grid > 0)
+      kk::gemm_mixed_sk<kk::EPI_STORE, kk::MSmallCfg><<<a.sk_grid, kk::MSmallCfg::THREADS, 0, h->stream>>>(a);
     else
       kk::gemm_mixed<kk::EPI_STORE, kk::MSmallCfg><<<grid, kk::MSmallCfg::THREADS, 0, h->stream>>>(a);
     LAUNCH_CHECK("gemm_mixed");
@@ -752,6 +791,8 @@ kk_status launch_mixed(kk_handle h, bool forward, kk::MixedArgs& a, const _Float
     ProfileScope ps(h, 1);
     if (h->mx_large)
       kk::gemm_mixed<kk::EPI_MULLIKEN, kk::MLargeCfg><<<grid, kk::MLargeCfg::THREADS, 0, h->stream>>>(a);
+    else if (a.sk_grid > 0)
+      kk::gemm_mixed_sk<kk::EPI_MULLIKEN, kk::MSmallCfg><<<a.sk_grid, kk::MSmallCfg::THREADS, 0, h->stream>>>(a);
     else
       kk::gemm_mixed<kk::EPI_MULLIKEN, kk::MSmallCfg><<<grid, kk::MSmallCfg::THREADS, 0, h->stream>>>(a);
   }
@@ -804,14 +845,26 @@ kk_status response_chunk_mixed(kk_handle h, int batch, const double* v, double* 
   // product at x32 + (z kch + j) np^2; sa holds the unsplit items for the symmetrizing pass,
   // which sums the partials. Back chunk j (kchb = kch) writes its Mulliken partials at rows
   // j nbase.. of the item's partials, which the combine sums with the rest.
-  const int kch = h->kch, kchb = h->kchb;
+  // Stream-K (h->sk): one GEMM item per spin and direction over the whole contraction; the
+  // kch = kchb partial slots of each are filled by the segments of gemm_mixed_sk.
+  const int kch = h->sk ? 1 : h->kch, kchb = h->sk ? 1 : h->kchb;
   const size_t ck = kch > 1 ? h->kck : 0, ckb = kchb > 1 ? h->kck : 0;
   kk::MixedArgs fa{};
   fa.n = np; fa.k = kch > 1 ? h->kck : h->kc; fa.ntiles = h->n_mfull; fa.nitems = 2 * batch * kch;
   fa.tiles = h->mtiles_full; fa.stop = stop; fa.beta = h->beta;
+  if (h->sk) {
+    fa.sk_grid = h->sk_grid;
+    fa.sk_slots = h->kch;
+    fa.sk_side = kk::MSmallCfg::BM;
+    fa.sk_stride = np2;
+  }
   kk::MixedArgs ba = fa;
   ba.k = kchb > 1 ? h->kck : h->kc;
   ba.nitems = 2 * batch * kchb;
+  if (h->sk) {
+    ba.sk_slots = h->kchb;
+    ba.sk_stride = (size_t)h->nbase * np;
+  }
   kk::MixedArgs sa = fa;
   sa.nitems = 2 * batch;
   if (fa.nitems > kk::MAX_GEMM_BATCH || ba.nitems > kk::MAX_GEMM_BATCH)
@@ -823,7 +876,7 @@ kk_status response_chunk_mixed(kk_handle h, int batch, const double* v, double* 
     const int s = z & 1;
     kk::MixedItem& si = sa.item[z];
     si = kk::MixedItem{};
-    si.x32 = h->x32 + (size_t)z * kch * np2;
+    si.x32 = h->x32 + (size_t)z * h->kch * np2;
     si.yh = h->yh + z * np2; si.yl = h->yl + z * np2; si.yr = h->bf16 ? h->yr + z * np2 : nullptr;
     si.eps = h->eps[s]; si.f = h->f[s]; si.fc = h->fc[s]; si.w = h->w[s];
     si.xdiag = h->xdiag + (size_t)z * np;
@@ -851,7 +904,7 @@ kk_status response_chunk_mixed(kk_handle h, int batch, const double* v, double* 
     }
   }
   kk_status st;
-  if ((st = launch_mixed(h, true, fa, fa2, fb2, kch > 1 ? &sa : nullptr, kch))) return st;
+  if ((st = launch_mixed(h, true, fa, fa2, fb2, kch > 1 ? &sa : nullptr, h->kch))) return st;
   if ((st = launch_mixed(h, false, ba, ba2, bb2))) return st;
   return launch_combine(h, batch, q1, stop, vsub, ft);
 }
@@ -945,6 +998,12 @@ kk_status allocate_prepared(kk_handle h) {
     mfull = h->mx_large ? tile_order(np, kk::MLargeCfg::BM, kk::MLargeCfg::BN, false)
                         : tile_order(np, kk::MSmallCfg::BM, kk::MSmallCfg::BN, false);
     h->n_mfull = (int)mfull.size();
+    if (h->sk) {  // the symmetrizing pass of a stream-K product finds tiles by kk::tile_table_pos
+      const int T = np / kk::MSmallCfg::BM;
+      for (int i = 0; i < h->n_mfull; ++i)
+        if (kk::tile_table_pos(mfull[i].x, mfull[i].y, T, T) != i)
+          return fail(KK_EINVAL, "internal: tile table order differs from tile_table_pos");
+    }
     if ((st = dalloc_t(h, &h->mtiles_full, mfull.size()))) return st;
     HIP_OR_FAIL(hipMemcpyAsync(h->mtiles_full, mfull.data(), sizeof(int2) * mfull.size(),
                                hipMemcpyHostToDevice, h->stream));
@@ -1064,10 +1123,20 @@ kk_status prepare_impl(kk_handle h, int n_atoms, const int* atom_offsets, int n_
     // the K-split runs on the 128 x 128 tiles of either form (a batch's systems never split)
     h->kch = 1;
     h->kck = h->kc;
+    h->sk = false;
+    h->sk_grid = 0;
     if (!split_large && !mx_large) {
       const int tiles = mixed ? (np / kk::MSmallCfg::BM) * (np / kk::MSmallCfg::BN)
                               : (np / kk::BackCfg::BM) * (np / kk::BackCfg::BN);
       h->kch = choose_ksplit(np, h->kc, tiles, cu_count(), mixed, &h->kck);
+      if (mixed && h->kch == 1) {
+        const int slots = choose_stream_k(tiles, h->kc / kk::MSmallCfg::BK, cu_count());
+        if (slots > 1) {
+          h->sk = true;
+          h->sk_grid = cu_count();
+          h->kch = slots;
+        }
+      }
     }
     // Both transforms split alike. (The split back-transform repeats its epilogue, the
     // Mulliken product with G, per chunk; split into two rounds of workgroups, as the FP64
@@ -1504,7 +1573,7 @@ kk_status kk_profile_read(kk_handle h, int kernel_id, double* total_ms, int* lau
 
 namespace {
 
-constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(64) << 20;
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(96) << 20;
 constexpr int NOALLOC_MAX_DEVICES = 64;
 
 }  // namespace

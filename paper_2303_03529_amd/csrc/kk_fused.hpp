@@ -492,7 +492,9 @@ __global__ __launch_bounds__(T) void fermi_symmetrize_f64_chunks(const GemmArgs 
 
 // Split forms: the FP32 partial products at it.x32 + j cstride, X scaled by 1 / the
 // product scale, Y written as NP 16-bit pieces at the Y scale (as fermi_symmetrize does).
-// Same thread layout, 16-byte loads and 8-byte stores.
+// Same thread layout, 16-byte loads and 8-byte stores. After a stream-K product
+// (args.sk_grid > 0) each of the two blocks sums only the slots its product tile filled
+// (NCH = the most segments of any tile).
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef _Float16 h4v __attribute__((ext_vector_type(4)));
 template <int B, int T, bool BF16, int NP, int NCH>
@@ -509,11 +511,19 @@ __global__ __launch_bounds__(T) void fermi_symmetrize_chunks(const MixedArgs arg
   const int r = threadIdx.x / (B / 4), c4 = (threadIdx.x % (B / 4)) * 4;
   const int m = I * B + r, cb = J * B + c4;
   const size_t oo = (size_t)m * n + cb, om = (size_t)(J * B + r) * n + I * B + c4;
+  int nown = NCH, nmir = NCH;
+  if (args.sk_grid > 0) {
+    const int nk = args.k / 32, nt = n / args.sk_side, ti = I * B / args.sk_side, tj = J * B / args.sk_side;
+    const long total = (long)args.nitems * args.ntiles * nk;
+    const int t0 = blockIdx.y * args.ntiles;
+    nown = sk_segments(t0 + tile_table_pos(ti, tj, nt, nt), nk, args.sk_grid, total);
+    nmir = sk_segments(t0 + tile_table_pos(tj, ti, nt, nt), nk, args.sk_grid, total);
+  }
   f4v own[NCH], mir[NCH];
 #pragma unroll
   for (int j = 0; j < NCH; ++j) {
-    own[j] = *reinterpret_cast<const f4v*>(it.x32 + oo + j * cstride);
-    mir[j] = *reinterpret_cast<const f4v*>(it.x32 + om + j * cstride);
+    own[j] = j < nown ? *reinterpret_cast<const f4v*>(it.x32 + oo + j * cstride) : f4v{0.f, 0.f, 0.f, 0.f};
+    mir[j] = j < nmir ? *reinterpret_cast<const f4v*>(it.x32 + om + j * cstride) : f4v{0.f, 0.f, 0.f, 0.f};
   }
   const double em = it.eps[m], fm = it.f[m], fcm = it.fc[m], wm = it.w[m];
   d2 en[2], fn[2], fcn[2];

@@ -84,8 +84,34 @@ struct MixedArgs {
   const int2* tiles;
   const int* stop;
   double beta;
+  // Stream-K schedule (gemm_mixed_sk; sk_grid = 0 for one workgroup per tile): the
+  // nitems x ntiles x (k / 32) K stages of a launch, in the order (item, tile of the table,
+  // stage), are cut into sk_grid equal ranges, one per workgroup. The j-th segment of a tile
+  // (along K) stores its partial result in slot j of the item's output, sk_stride elements
+  // after slot j - 1; slots past a tile's last segment, up to sk_slots, are cleared
+  // (Mulliken partials) or not read (the symmetrizing pass, which finds the segment count of
+  // each sk_side x sk_side tile from its table position, tile_table_pos).
+  int sk_grid, sk_slots, sk_side;
+  size_t sk_stride;
   MixedItem item[MAX_GEMM_BATCH];
 };
+
+// Position of tile (tm, tn) of a TM x TN grid in the tile table: groups of TILE_GROUP tile
+// rows, each group walked column by column (within a column, row by row).
+constexpr int TILE_GROUP = 4;
+__host__ __device__ inline int tile_table_pos(int tm, int tn, int TM, int TN) {
+  const int g0 = tm - tm % TILE_GROUP, gr = TM - g0 < TILE_GROUP ? TM - g0 : TILE_GROUP;
+  return g0 * TN + tn * gr + (tm - g0);
+}
+
+// Stream-K: the workgroup whose range [w total / grid, (w + 1) total / grid) holds stage x,
+// and the number of segments of launch tile t (nk stages each).
+__host__ __device__ inline int sk_owner(long x, int grid, long total) {
+  return (int)(((x + 1) * grid - 1) / total);
+}
+__host__ __device__ inline int sk_segments(int t, int nk, int grid, long total) {
+  return sk_owner((long)(t + 1) * nk - 1, grid, total) - sk_owner((long)t * nk, grid, total) + 1;
+}
 
 template <int BM_, int BN_, int BK_, int WAVES_M_, int WAVES_N_, int MINB_, int FLUSH_ = 0, bool BF16_ = false,
           int PROD_ = PROD_F16X3>
@@ -611,6 +637,53 @@ __global__ __launch_bounds__(Cfg::THREADS, Cfg::MIN_BLOCKS) void gemm_mixed(cons
   const int logical = xcd_remap(blockIdx.x, total);
   const int z = logical / args.ntiles;
   mixed_tile<EPI, Cfg>(args.item[z], args.n, args.k, args.tiles[logical - z * args.ntiles]);
+}
+
+// Stream-K form of gemm_mixed for launches with fewer tiles than CUs, or a last round of
+// workgroups far from full (MixedArgs): every workgroup takes an equal share of the launch's
+// K stages, in one or a few segments of consecutive tiles, and runs each segment as the
+// product over that part of the contraction (operands k-contiguous: a column offset) into
+// the segment's partial slot. A workgroup holding the first segment of a Mulliken tile also
+// clears the tile's slots past its last segment, so that the combine can sum every slot.
+template <int EPI, class Cfg>
+__global__ __launch_bounds__(Cfg::THREADS, Cfg::MIN_BLOCKS) void gemm_mixed_sk(const MixedArgs args) {
+  static_assert(Cfg::DL && Cfg::BK == 32, "stream-K runs the direct-to-LDS main loop");
+  static_assert(EPI == EPI_STORE || EPI == EPI_MULLIKEN, "partial slots, no accumulation");
+  if (args.stop != nullptr && *args.stop != 0) return;
+  const int grid = gridDim.x, nk = args.k / Cfg::BK;
+  const long total = (long)args.nitems * args.ntiles * nk;
+  const int w = xcd_remap(blockIdx.x, grid);
+  long s = (long)w * total / grid;
+  const long e = (long)(w + 1) * total / grid;
+  while (s < e) {
+    const int t = (int)(s / nk);
+    const int k0 = (int)(s - (long)t * nk);
+    const int k1 = (int)((long)nk < k0 + (e - s) ? (long)nk : k0 + (e - s));
+    const int z = t / args.ntiles;
+    const int2 tile = args.tiles[t - z * args.ntiles];
+    const int j = w - sk_owner((long)t * nk, grid, total);
+    MixedItem it = args.item[z];
+    const int ko = k0 * Cfg::BK;
+    it.a0h += ko; it.a0l += ko; it.b0h += ko; it.b0l += ko;
+    if constexpr ((Cfg::PROD & PROD_RES) != 0) { it.a0r += ko; it.b0r += ko; }
+    if constexpr (EPI == EPI_STORE)
+      it.x32 += j * args.sk_stride;
+    else
+      it.part += j * args.sk_stride;
+    mixed_tile<EPI, Cfg>(it, args.n, (k1 - k0) * Cfg::BK, tile);
+    if constexpr (EPI == EPI_MULLIKEN) {
+      if (j == 0) {
+        const int nseg = sk_segments(t, nk, grid, total);
+        double* const base = args.item[z].part;
+        for (int q = nseg; q < args.sk_slots; ++q)
+          for (int i = threadIdx.x; i < Cfg::BM * Cfg::WAVES_N; i += Cfg::THREADS) {
+            const int m = tile.x * Cfg::BM + i % Cfg::BM, p = tile.y * Cfg::WAVES_N + i / Cfg::BM;
+            base[q * args.sk_stride + (size_t)p * args.n + m] = 0.0;
+          }
+      }
+    }
+    s += k1 - k0;
+  }
 }
 
 // Second pass of the split forward transform in its full-tile form. For one

@@ -1,7 +1,9 @@
-"""K-split transforms of small single systems against the FP64 oracle, at the sizes
-where the split count differs from the 128-atom case (three chunks): open clusters of
-56 atoms (Nb = 504, padded 512: four chunks of 128 rows) and 113 atoms (Nb = 1017,
-padded 1024, contraction 1024: two chunks of 512 rows), in all three precisions.
+"""K-split and stream-K transforms of small single systems against the FP64 oracle, on
+open clusters in all three precisions: 56 atoms (Nb = 504, padded 512: four chunks of
+128 rows) and 113 atoms (Nb = 1017, padded 1024, contraction 1024: two chunks of 512
+rows); and 170 atoms (Nb = 1530, padded 1536), where the split forms' products run
+stream-K (288 tiles for 256 workgroups, two segments per tile at most; the batched
+responses' launch of five directions too) and FP64 runs unsplit on 64 x 64 tiles.
 
 Checked: five responses in one call (the workspace holds two directions at a time
 with four chunks, so the call runs in three batches), each against the oracle's
@@ -30,7 +32,7 @@ TOL = {krylov.KK_FP64: 1e-10, krylov.KK_MIXED_F16: 1e-6, krylov.KK_MIXED_BF16: 1
 PRECISIONS = [krylov.KK_FP64, krylov.KK_MIXED_F16, krylov.KK_MIXED_BF16]
 
 
-@pytest.fixture(scope="module", params=[56, 113], ids=["fe56", "fe113"])
+@pytest.fixture(scope="module", params=[56, 113, 170], ids=["fe56", "fe113", "fe170"])
 def system(request):
     n = request.param
     sysd = make_system(n_atoms=n, seed=20_000 + n)

@@ -62,7 +62,7 @@ def test_noalloc_matches_apply_on_two_calls(systems, precision):
 
 
 def test_noalloc_refuses_a_handle_that_does_not_fit():
-    sysd = make_system(n_atoms=250, seed=10_250)   # Nb = 2250, padded 2304: 85 MB of Y
+    sysd = make_system(n_atoms=290, seed=10_290)   # Nb = 2610, padded 2688: 116 MB of Y
     ep = expansion_point(sysd)
     h = handle_from_expansion(sysd, ep, krylov.KK_FP64)
     try:

@@ -40,8 +40,8 @@ DTYPE = {"fp64": "f64", "mixed": "f16x3+f64", "bf16": "bf16x6+f64"}
 FORM = {"fp64": "FP64 transforms",
         "mixed": "split FP16 x 3 transforms (FP32 accumulation), FP64 divided differences, mu shift, Mulliken "
                  "sums and m x m solve",
-        "bf16": "BF16 transforms: hi/lo products (4) plus the refinement products over the residual pieces (2; a "
-                "second pass above Nb = 2304, the same pass below), FP32 accumulation; FP64 elsewhere"}
+        "bf16": "BF16 transforms: hi/lo products (4) plus the refinement products over the residual pieces (2), "
+                "in one pass, FP32 accumulation; FP64 elsewhere"}
 
 
 def parse():
@@ -56,7 +56,7 @@ def parse():
     ap.add_argument("--precision", choices=["fp64", "mixed", "bf16"], default="fp64",
                     help="transform arithmetic of the headline: FP64 MFMA (the split forms are then timed too "
                          "and reported in the line's 'mixed' (FP16 x 3) and 'bf16' (BF16 with its refinement "
-                         "pass) objects), or one split form only")
+                         "products) objects), or one split form only")
     ap.add_argument("--fp64-only", action="store_true", help="do not time the split forms beside FP64")
     ap.add_argument("--prof-steps", type=int, default=2,
                     help="updates of the separate launch-by-launch pass that times the transform kernels")

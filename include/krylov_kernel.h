@@ -56,16 +56,14 @@ typedef enum {
  *                 Responses and kernel results agree with FP64 to ~1e-7
  *                 relative on the bcc-Fe workloads (not a guaranteed bound).
  *   KK_MIXED_BF16 the two transforms in BF16 MFMA products with FP32
- *                 accumulation and a refinement pass: every split operand is
- *                 kept as three BF16 pieces (hi, lo, residual; ~24 significant
- *                 bits). A first pass forms hi*hi + hi*lo + lo*hi + lo*lo (~16
- *                 bits); the refinement pass runs the same products over the
- *                 residual pieces, hi*res + res*hi, and adds them to what the
- *                 first pass stored (the forward product before its Fermi
- *                 Hadamard step; the back-transform's Mulliken sums, which are
- *                 linear in the product). Up to Nb = 2304 both sets of products
- *                 run in one pass over the three pieces (same products, one
- *                 FP32 accumulation). Six products per transform instead of
+ *                 accumulation and a refinement: every split operand is kept
+ *                 as three BF16 pieces (hi, lo, residual; ~24 significant
+ *                 bits). The hi/lo products hi*hi + hi*lo + lo*hi + lo*lo
+ *                 carry ~16 bits; the refinement products over the residual
+ *                 pieces, hi*res + res*hi, add the rest. All six accumulate in
+ *                 one pass over the three pieces (FP32, in two levels), before
+ *                 the forward's Fermi Hadamard step and the back-transform's
+ *                 Mulliken sums. Six products per transform instead of
  *                 KK_MIXED_F16's three; BF16's exponent range needs no scaling.
  *                 FP64 elsewhere as above; agreement with FP64 ~1e-7 relative.
  *                 Single-system handles only (not in kk_batch_prepare).

@@ -140,7 +140,7 @@ struct kk_handle_s {
   int n_supper = 0, n_sfull = 0;
 
   // split-precision state (precision KK_MIXED_F16 or KK_MIXED_BF16; the BF16 form keeps a
-  // third piece of every split operand, *r, for its refinement pass)
+  // third piece of every split operand, *r, for its refinement products)
   int precision = KK_FP64;
   bool bf16 = false;
   double* GT[2] = {nullptr, nullptr};
@@ -692,53 +692,15 @@ kk_status response_chunk(kk_handle h, int batch, const double* v, double* q1, co
   return launch_combine(h, batch, q1, stop, vsub, ft);
 }
 
-// BF16 form, one transform step: the first pass (four products of the hi/lo pieces), then
-// the refinement pass over the residual pieces (a2 = the third piece of At, b2 of Bt: products
-// hi res + res hi, added to what the first pass stored), then for the forward the symmetrizing
-// pass that writes Y as three BF16 pieces.
-// K-split (sym != nullptr): a's items are the kch chunks of each of sym's items, whose
-// symmetrizing pass sums their partial products.
-template <class Cfg1, class Cfg2>
-kk_status launch_bf16_step(kk_handle h, bool forward, kk::MixedArgs& a, const _Float16* const* a2,
-                           const _Float16* const* b2, const kk::MixedArgs* sym, int kch) {
-  const int grid = a.ntiles * a.nitems;
-  if (forward) {
-    kk::gemm_mixed<kk::EPI_STORE, Cfg1><<<grid, Cfg1::THREADS, 0, h->stream>>>(a);
-    LAUNCH_CHECK("gemm_mixed bf16");
-    kk::MixedArgs r = a;  // same items, the lo pieces replaced by the residual pieces
-    for (int z = 0; z < a.nitems; ++z) { r.item[z].a0l = a2[z]; r.item[z].b0l = b2[z]; }
-    kk::gemm_mixed<kk::EPI_STORE_ADD, Cfg2><<<grid, Cfg2::THREADS, 0, h->stream>>>(r);
-    LAUNCH_CHECK("gemm_mixed bf16 refinement");
-    if (!h->mx_large) {
-      kk_status st = launch_sym_mixed(h, sym != nullptr ? *sym : a, kch, (size_t)a.n * a.n);
-      if (st) return st;
-    } else {
-      const int nblk = a.n / kk::SYM_B_LARGE;
-      kk::fermi_symmetrize<kk::SYM_B_LARGE, kk::SYM_T_LARGE, true, 3>
-          <<<dim3(nblk * (nblk + 1) / 2, a.nitems), kk::SYM_T_LARGE, 0, h->stream>>>(a);
-    }
-    LAUNCH_CHECK("fermi_symmetrize bf16");
-  } else {
-    kk::gemm_mixed<kk::EPI_MULLIKEN, Cfg1><<<grid, Cfg1::THREADS, 0, h->stream>>>(a);
-    LAUNCH_CHECK("gemm_mixed bf16");
-    kk::MixedArgs r = a;
-    for (int z = 0; z < a.nitems; ++z) { r.item[z].a0l = a2[z]; r.item[z].b0l = b2[z]; }
-    kk::gemm_mixed<kk::EPI_MULLIKEN_ADD, Cfg2><<<grid, Cfg2::THREADS, 0, h->stream>>>(r);
-    LAUNCH_CHECK("gemm_mixed bf16 refinement");
-  }
-  return KK_OK;
-}
-
 // Split-precision transform step: the forward (full-tile product into the FP32
 // workspace, then the symmetrizing pass that writes the split Y) or the back-transform.
-// a2, b2 (BF16 form only): per item the third pieces of At and Bt for the refinement pass.
-// BF16 form on the small product configuration: one pass over the three pieces of both
-// operands (the four hi/lo products and the two with the third pieces, PROD_ALL6), so that
-// each stage streams the six operand pieces once instead of four in a first pass and four
-// again in the refinement pass. a2, b2, sym, kch as for launch_bf16_step.
+// a2, b2 (BF16 form only): per item the third pieces of At and Bt, whose products with the
+// hi pieces (the refinement) run in the same pass as the four hi/lo products (PROD_ALL6).
+// K-split (sym != nullptr): a's items are the kch chunks of each of sym's items, whose
+// symmetrizing pass sums their partial products.
+template <class Cfg>
 kk_status launch_bf16_single(kk_handle h, bool forward, kk::MixedArgs& a, const _Float16* const* a2,
                              const _Float16* const* b2, const kk::MixedArgs* sym, int kch) {
-  using Cfg = kk::MSmallBf6;
   const int grid = a.ntiles * a.nitems;
   for (int z = 0; z < a.nitems; ++z) { a.item[z].a0r = a2[z]; a.item[z].b0r = b2[z]; }
   if (forward) {
@@ -747,6 +709,13 @@ kk_status launch_bf16_single(kk_handle h, bool forward, kk::MixedArgs& a, const 
     else
       kk::gemm_mixed<kk::EPI_STORE, Cfg><<<grid, Cfg::THREADS, 0, h->stream>>>(a);
     LAUNCH_CHECK("gemm_mixed bf16 one pass");
+    if (h->mx_large) {
+      const int nblk = a.n / kk::SYM_B_LARGE;
+      kk::fermi_symmetrize<kk::SYM_B_LARGE, kk::SYM_T_LARGE, true, 3>
+          <<<dim3(nblk * (nblk + 1) / 2, a.nitems), kk::SYM_T_LARGE, 0, h->stream>>>(a);
+      LAUNCH_CHECK("fermi_symmetrize bf16");
+      return KK_OK;
+    }
     return launch_sym_mixed(h, sym != nullptr ? *sym : a, kch, (size_t)a.n * a.n);
   }
   if (a.sk_grid > 0)
@@ -757,7 +726,7 @@ kk_status launch_bf16_single(kk_handle h, bool forward, kk::MixedArgs& a, const 
   return KK_OK;
 }
 
-// sym, kch: the K-split form, as for launch_bf16_step (small product configuration only).
+// sym, kch: the K-split form, as for launch_bf16_single (small product configuration only).
 kk_status launch_mixed(kk_handle h, bool forward, kk::MixedArgs& a, const _Float16* const* a2 = nullptr,
                        const _Float16* const* b2 = nullptr, const kk::MixedArgs* sym = nullptr, int kch = 1) {
   const int grid = a.ntiles * a.nitems;
@@ -766,8 +735,8 @@ kk_status launch_mixed(kk_handle h, bool forward, kk::MixedArgs& a, const _Float
   if ((kch > 1 || a.sk_grid > 0) && h->mx_large) return fail(KK_EINVAL, "internal: K-split on the large split tiles");
   if (h->bf16) {
     ProfileScope ps(h, forward ? 0 : 1);
-    return h->mx_large ? launch_bf16_step<kk::MLargeBf1, kk::MLargeBf2>(h, forward, a, a2, b2, sym, kch)
-                       : launch_bf16_single(h, forward, a, a2, b2, sym, kch);
+    return h->mx_large ? launch_bf16_single<kk::MLargeBf6>(h, forward, a, a2, b2, sym, kch)
+                       : launch_bf16_single<kk::MSmallBf6>(h, forward, a, a2, b2, sym, kch);
   }
   if (forward) {
     ProfileScope ps(h, 0);
@@ -869,7 +838,7 @@ kk_status response_chunk_mixed(kk_handle h, int batch, const double* v, double* 
   sa.nitems = 2 * batch;
   if (fa.nitems > kk::MAX_GEMM_BATCH || ba.nitems > kk::MAX_GEMM_BATCH)
     return fail(KK_EINVAL, "internal: too many GEMM items");
-  // BF16 refinement pass operands: residual pieces of (U~ C)^T and G^T (forward), C and Y (back)
+  // BF16 refinement operands: residual pieces of (U~ C)^T and G^T (forward), C and Y (back)
   const _Float16 *fa2[kk::MAX_GEMM_BATCH], *fb2[kk::MAX_GEMM_BATCH], *ba2[kk::MAX_GEMM_BATCH],
       *bb2[kk::MAX_GEMM_BATCH];
   for (int z = 0; z < 2 * batch; ++z) {

@@ -28,18 +28,12 @@ typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef float f16x __attribute__((ext_vector_type(16)));
 
-// Epilogues of the split products beyond kk_gemm.hpp's: the second (refinement) pass of the
-// BF16 form adds its product to what the first pass stored.
-enum { EPI_STORE_ADD = 6, EPI_MULLIKEN_ADD = 7 };
-
 // Products of a split pass, as a mask over the operand pairs (At piece, Bt piece) of a stage:
 // bit 0 (1, 0), bit 1 (0, 1), bit 2 (0, 0), bit 3 (1, 1), bit 4 (0, 2), bit 5 (2, 0); bits 4
 // and 5 stream a third piece of each operand (direct-to-LDS loop only).
 constexpr int PROD_F16X3 = 0x7;   // FP16: hi lo, lo hi, hi hi
-constexpr int PROD_ALL4 = 0xF;    // BF16 first pass: hi hi, hi lo, lo hi, lo lo
-constexpr int PROD_CROSS = 0x3;   // BF16 refinement pass on (hi, residual): hi res, res hi
-constexpr int PROD_RES = 0x30;    // hi res and res hi on the third pieces
-constexpr int PROD_ALL6 = 0x3F;   // BF16 in one pass over three pieces: the four of PROD_ALL4 and PROD_RES
+constexpr int PROD_RES = 0x30;    // hi res and res hi on the third pieces (the BF16 refinement)
+constexpr int PROD_ALL6 = 0x3F;   // BF16: hi hi, hi lo, lo hi, lo lo and PROD_RES, in one pass
 
 // One 32 x 32 x 16 MFMA on 16-bit operands held as raw 8-element registers.
 template <bool BF16>
@@ -158,7 +152,7 @@ struct MixedDlCfg {
   static constexpr int SMEM_BYTES = NS * STAGE_BYTES;
   static_assert(STAGE_BLK % WAVES == 0, "DMA blocks per wave");
   static_assert(BM % (32 * WAVES_M) == 0 && BN % (32 * WAVES_N) == 0, "wave tiling");
-  static_assert(NS >= 3 && NS <= 5, "ring depth");
+  static_assert(NS >= 2 && NS <= 5, "ring depth");
   static_assert(NS * STAGE_BYTES <= 160 * 1024, "LDS");
 };
 
@@ -362,7 +356,7 @@ __device__ __forceinline__ void mixed_epilogue(const MixedItem& it, const int n,
   const double inv = it.sc[0];
   const int mw = m0 + wm * (BM / Cfg::WAVES_M) + 4 * lh;
   const int nw = n0 + wn * (BN / Cfg::WAVES_N) + l32;
-  if constexpr (EPI == EPI_STORE || EPI == EPI_STORE_ADD) {
+  if constexpr (EPI == EPI_STORE) {
     // 32 consecutive columns of one row per instruction and accumulator element
 #pragma unroll
     for (int i = 0; i < WTM; ++i)
@@ -372,13 +366,10 @@ __device__ __forceinline__ void mixed_epilogue(const MixedItem& it, const int n,
 #pragma unroll
         for (int j = 0; j < WTN; ++j) {
           float* o = it.x32 + (size_t)m * n + nw + j * 32;
-          if constexpr (EPI == EPI_STORE_ADD)
-            *o += acc[i][j][r];
-          else
-            *o = acc[i][j][r];
+          *o = acc[i][j][r];
         }
       }
-  } else {  // EPI_MULLIKEN, EPI_MULLIKEN_ADD
+  } else {  // EPI_MULLIKEN
     const int p = tile.y * Cfg::WAVES_N + wn;
 #pragma unroll
     for (int i = 0; i < WTM; ++i)
@@ -394,12 +385,7 @@ __device__ __forceinline__ void mixed_epilogue(const MixedItem& it, const int n,
         s += __shfl_xor(s, 4);
         s += __shfl_xor(s, 8);
         s += __shfl_xor(s, 16);
-        if (l32 == 0) {
-          if constexpr (EPI == EPI_MULLIKEN_ADD)
-            it.part[(size_t)p * n + m] += s;
-          else
-            it.part[(size_t)p * n + m] = s;
-        }
+        if (l32 == 0) it.part[(size_t)p * n + m] = s;
       }
   }
 }
@@ -437,12 +423,14 @@ __device__ __forceinline__ void mixed_mainloop_dl(const MixedItem& it, const int
   constexpr int BM = Cfg::BM, BN = Cfg::BN, BK = 32, NS = Cfg::NS, PW = Cfg::PER_WAVE;
   constexpr int WTM = Cfg::WTM, WTN = Cfg::WTN;
   constexpr int A_BLK = Cfg::A_BLK, B_BLK = Cfg::B_BLK, SB = Cfg::STAGE_BYTES, NPC = Cfg::NPC;
-  static_assert(NS >= 3, "the pipelined loop refills a slot one stage after reading it");
+  // enter_stage(s) refills the slot of stage s - 1, whose last fragment reads (its second
+  // half, read before its first half's products) every wave has finished by then
+  static_assert(NS >= 2, "ring depth");
   unsigned char* const ring = mixed_smem<Cfg>();
 
   const int tid = threadIdx.x;
   const int nk = kc / BK;
-  const int wave = tid >> 6, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;  // wave index in an SGPR
   const int wm = wave / Cfg::WAVES_N, wn = wave % Cfg::WAVES_N;
   const int l32 = lane & 31, lh = lane >> 5;
   const int rr = lane >> 2;
@@ -489,7 +477,11 @@ __device__ __forceinline__ void mixed_mainloop_dl(const MixedItem& it, const int
     unsigned char* slot = ring + (kt % NS) * SB;
 #pragma unroll
     for (int j = 0; j < PW; ++j) {
-      const int blk = wave * PW + j;  // wave-uniform
+      // block j WAVES + wave (wave-uniform): for a given j the waves' blocks lie in one or
+      // two pieces, so the piece's pointer is a scalar choice rather than an indexed array
+      // (interleaved against wave-contiguous blocks: 128 atoms FP16 x 3 1222 -> 1259
+      // updates/s, 432 atoms 71.3 -> 74.1, one process)
+      const int blk = j * Cfg::WAVES + wave;
       const _Float16* src;
       int row0;
       if (blk < NPC * A_BLK) {
@@ -619,8 +611,7 @@ __device__ __forceinline__ void mixed_mainloop_dl(const MixedItem& it, const int
 // One output tile over a contraction of length kc (see f64_tile); ends with a barrier.
 template <int EPI, class Cfg>
 __device__ __forceinline__ void mixed_tile(const MixedItem& it, const int n, const int kc, const int2 tile) {
-  static_assert(EPI == EPI_STORE || EPI == EPI_MULLIKEN || EPI == EPI_STORE_ADD || EPI == EPI_MULLIKEN_ADD,
-                "split-precision epilogues");
+  static_assert(EPI == EPI_STORE || EPI == EPI_MULLIKEN, "split-precision epilogues");
   const int m0 = tile.x * Cfg::BM, n0 = tile.y * Cfg::BN;
   f16x acc[Cfg::WTM][Cfg::WTN];
   if constexpr (Cfg::DL)
@@ -805,7 +796,7 @@ using MDl256x128w16 = MixedDlCfg<256, 128, 8, 2, 3, 8>;  // 16 waves of 32 x 64
 using MLargeCfg = KK_MLARGE_CFG;
 using MSmallCfg = KK_MSMALL_CFG;
 
-// The same tile shape with other split arithmetic (the BF16 form's two passes).
+// The same tile shape with other split arithmetic (the BF16 form's products).
 template <class Cfg, bool BF16, int PROD>
 struct WithProducts;
 template <int BM, int BN, int WM, int WN, int NS, int FL, bool B0, int P0, bool BF16, int PROD>
@@ -816,14 +807,18 @@ template <int BM, int BN, int BK, int WM, int WN, int MB, int FL, bool B0, int P
 struct WithProducts<MixedCfg<BM, BN, BK, WM, WN, MB, FL, B0, P0>, BF16, PROD> {
   using type = MixedCfg<BM, BN, BK, WM, WN, MB, FL, BF16, PROD>;
 };
-// BF16 form: first pass hi hi + hi lo + lo hi + lo lo, refinement pass hi res + res hi.
-using MLargeBf1 = WithProducts<MLargeCfg, true, PROD_ALL4>::type;
-using MLargeBf2 = WithProducts<MLargeCfg, true, PROD_CROSS>::type;
-using MSmallBf1 = WithProducts<MSmallCfg, true, PROD_ALL4>::type;
-using MSmallBf2 = WithProducts<MSmallCfg, true, PROD_CROSS>::type;
-// The small shape streams three pieces in one pass (144 KB of ring at 128 x 128), the large
-// one cannot (216 KB at 256 x 128) and keeps the two passes.
+// BF16 form: the six products (PROD_ALL6) in one pass over three pieces of each operand, so
+// that every piece crosses the CU's operand stream once. Small shape: 48 KB stages in a
+// 3-stage ring (144 KB). Large: the 72 KB stages of 256 x 128 leave room for a 2-stage ring
+// only (144 KB), and their 72 DMA blocks go to 8 waves (64 x 64 each; 16 do not divide them).
+// Against the earlier two passes (hi/lo products stored, then hi res + res hi added by a
+// second pass over the residual pieces) at 432 and 1024 atoms: 37.3 -> 42.8 and 2.0 -> 2.3
+// updates/s (one process), results 3-6e-8 apart (the summation order).
 using MSmallBf6 = WithProducts<MSmallCfg, true, PROD_ALL6>::type;
+using MLargeBf6 = MixedDlCfg<256, 128, 4, 2, 2, 8, true, PROD_ALL6>;
+static_assert(MLargeBf6::BM == MLargeCfg::BM && MLargeBf6::BN == MLargeCfg::BN &&
+                  MLargeBf6::WAVES_N == MLargeCfg::WAVES_N,
+              "the BF16 large products share the large shape's tile table and partial rows");
 
 // Padded dimension of a split-precision handle: the larger tile side of its product
 // configuration, so that the tiles cover the padded matrices exactly.

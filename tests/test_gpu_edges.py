@@ -154,3 +154,32 @@ def test_prepare_rejects_out_of_range_sizes():
         assert rel(x.cpu().numpy(), kernel_apply(sysd, ep, sysd["delta"], 4)) < 1e-10
     finally:
         h.close()
+
+
+@pytest.mark.parametrize("precision", [krylov.KK_FP64, krylov.KK_MIXED_F16, krylov.KK_MIXED_BF16],
+                         ids=["fp64", "split", "bf16"])
+def test_ragged_atoms_across_tile_rows(precision):
+    """54 atoms with 1-9 orbitals each (Nb = 325, padded 384): atoms 22 and 42 straddle the
+    128-row tiles of the products, so their Mulliken sums gather partial rows of two tiles.
+    Three responses and the rank-6 kernel against the oracle."""
+    base = make_system(3, seed=54)
+    pattern = [1, 4, 9, 9, 4, 1, 9, 2, 9, 9, 3, 9, 5, 9, 9, 7]
+    counts = np.array([pattern[i % len(pattern)] for i in range(base["n_atoms"])])
+    sysd = ragged_orbitals(base, counts)
+    off = sysd["offsets"]
+    straddling = [a for a in range(len(counts)) if off[a] // 128 != (off[a + 1] - 1) // 128]
+    assert straddling == [22, 42] and sysd["n_basis"] == 325
+    ep = expansion_point(sysd)
+    h = handle_from_expansion(sysd, ep, precision)
+    try:
+        v = krylov_vectors(base["n_atoms"], 3, 7)
+        q = h.density_response_batch(t(v)).cpu().numpy()
+        for i in range(3):
+            assert rel(q[i], response(sysd, ep, v[i])) < TOL[precision]
+        kd, info = h.krylov_kernel_apply(t(sysd["delta"]), 6)
+        err = rel(kd.cpu().numpy(), kernel_apply(sysd, ep, sysd["delta"], 6))
+        print(f"ragged 54 atoms (Nb {sysd['n_basis']}), precision {precision}: kernel {err:.2e}, "
+              f"rank {info.rank_used}", flush=True)
+        assert err < TOL[precision]
+    finally:
+        h.close()

@@ -2,8 +2,9 @@
 the C ABI, against krylov_kernel_apply on the same handles: two calls in a
 row (a 128-atom bcc cell, then a smaller 37-atom open cluster, so the second
 call reuses the fixed scratch array holding the first call's data), in FP64
-and in the split-precision form, plus the FP64 results against the oracle and
-the refusal of a handle whose workspace does not fit."""
+and in the split-precision forms, plus the FP64 results against the oracle, the
+split forms' stream-K products in the scratch array, and the refusal of a handle
+whose workspace does not fit."""
 
 import numpy as np
 import pytest
@@ -57,6 +58,28 @@ def test_noalloc_matches_apply_on_two_calls(systems, precision):
             # the entry point after a graph replay and before one: both keep agreeing
             again, _ = h.krylov_kernel_apply(d, m)
             assert rel(again.cpu().numpy(), ref.cpu().numpy()) < 1e-15
+        finally:
+            h.close()
+
+
+@pytest.mark.parametrize("precision", [krylov.KK_MIXED_F16, krylov.KK_MIXED_BF16], ids=["split_f16", "bf16"])
+def test_noalloc_stream_k_products(precision):
+    """The split forms' stream-K products (170-atom cluster, Nb = 1530: two partial slots per
+    item in the scratch array, BF16 91 MiB of it), then a 128-atom cell in the same array:
+    each against krylov_kernel_apply on the same handle."""
+    cases = [make_system(n_atoms=170, seed=20_170), make_system(4, seed=128)]
+    for call, sysd in enumerate(cases):
+        ep = expansion_point(sysd)
+        print(f"no-alloc stream-K call {call}: {sysd['n_atoms']} atoms, precision {precision}", flush=True)
+        h = handle_from_expansion(sysd, ep, precision)
+        try:
+            d = t(sysd["delta"])
+            ref, _ = h.krylov_kernel_apply(d, 6)
+            got, info = h.krylov_kernel_apply_noalloc(d, 6, out=torch.full_like(d, float("nan")))
+            torch.cuda.synchronize()
+            err = rel(got.cpu().numpy(), ref.cpu().numpy())
+            print(f"  vs krylov_kernel_apply: {err:.2e}; rank {info.rank_used}", flush=True)
+            assert info.rank_used == 6 and err < 1e-15
         finally:
             h.close()
 

@@ -826,6 +826,13 @@ kk_status response_chunk_mixed(kk_handle h, int batch, const double* v, double* 
     fa.sk_slots = h->kch;
     fa.sk_side = kk::MSmallCfg::BM;
     fa.sk_stride = np2;
+    // the item's partial slots (sized for one direction) must hold every tile's segments of
+    // this launch; longer launches cut fewer segments per tile, checked here all the same
+    const int nk = h->kc / kk::MSmallCfg::BK, tiles = 2 * batch * h->n_mfull;
+    const long total = (long)tiles * nk;
+    for (int t = 0; t < tiles; ++t)
+      if (kk::sk_segments(t, nk, h->sk_grid, total) > h->kch)
+        return fail(KK_EINVAL, "internal: stream-K tile %d needs more than %d slots", t, h->kch);
   }
   kk::MixedArgs ba = fa;
   ba.k = kchb > 1 ? h->kck : h->kc;

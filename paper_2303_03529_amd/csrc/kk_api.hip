@@ -326,8 +326,9 @@ int cu_count() {
 
 // K-split of the response transforms of one small system. When the two items of a
 // transform (one per spin) have fewer tiles than the chip has CUs, each item's contraction
-// is cut into c chunks of kck rows (a multiple of KSTEP, at least KSPLIT_MIN_K, all c chunks
-// inside the padding, whose rows past kc are zero); every chunk is a GEMM item of its own
+// is cut into c chunks of kck rows (a multiple of KSTEP, at least KSPLIT_MIN_K rows for FP64
+// and KSPLIT_MIN_K_SPLIT for the split forms, all c chunks inside the padding, whose rows past
+// kc are zero); every chunk is a GEMM item of its own
 // and the partial results are summed in a fixed order afterwards (forward: by the
 // symmetrizing pass; back: by combine, as further Mulliken partial rows).
 // FP64 (two workgroups per CU): c minimizes the per-CU work ceil(2 tiles c / CUs) / c and is
@@ -337,12 +338,16 @@ int cu_count() {
 // workgroups still fit one per CU (Nb = 1152: none; 1017: 2; 504: 4). Measured updates/s,
 // split off / on, FP64 | FP16 x 3 | BF16: 128 atoms 417 / 504 | 1138 / 1052 | 700 / 650 (the
 // split forms' c = 3 there is what this rule now avoids), 113 atoms 605 / 665 | 1255 / 1333 |
-// 778 / 842, 56 atoms 1366 / 1555 | 1794 / 1948 | 1145 / 1289.
+// 778 / 842, 56 atoms 1366 / 1555 | 1794 / 1948 | 1145 / 1289. The split forms' shorter
+// chunks reach the smallest systems (16 atoms, kc = 160: four chunks of 64 rows; FP16 x 3 /
+// BF16 6135 -> 6407 / 5605 -> 6237 updates/s, 17 atoms 6118 -> 6427 / 5606 -> 6262); FP64
+// chunks that short would leave its 64 x 64 tiles for the K-split's 128 x 128 ones and ran
+// 14 % slower there.
 // -DKK_KSPLIT_MAX=1 turns the K-split off (for re-tuning).
 #ifndef KK_KSPLIT_MAX
 #define KK_KSPLIT_MAX 4
 #endif
-constexpr int KSPLIT_MAX = KK_KSPLIT_MAX, KSPLIT_MIN_K = 128;
+constexpr int KSPLIT_MAX = KK_KSPLIT_MAX, KSPLIT_MIN_K = 128, KSPLIT_MIN_K_SPLIT = 64;
 int choose_ksplit(int np, int kc, int tiles, int cus, bool one_per_cu, int* chunk_rows) {
   *chunk_rows = kc;
   if (2 * tiles > cus) return 1;
@@ -350,7 +355,7 @@ int choose_ksplit(int np, int kc, int tiles, int cus, bool one_per_cu, int* chun
   int best = 1, best_ck = kc;
   for (int c = 2; c <= KSPLIT_MAX; ++c) {
     const int ck = ((kc + c - 1) / c + KSTEP - 1) / KSTEP * KSTEP;
-    if (ck < KSPLIT_MIN_K || c * ck > np) continue;
+    if (ck < (one_per_cu ? KSPLIT_MIN_K_SPLIT : KSPLIT_MIN_K) || c * ck > np) continue;
     const bool better = one_per_cu ? 2 * tiles * c <= cus : load(c) < load(best);
     if (better) {
       best = c;

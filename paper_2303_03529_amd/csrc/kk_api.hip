@@ -120,6 +120,7 @@ struct kk_handle_s {
   // of partial results per item, sk_grid workgroups per product launch
   bool sk = false;
   int sk_grid = 0;
+  bool ktiny = false;  // FP64 K-split on the tiny 64 x 64 tiles (small_f64 and tiny_f64 stay set)
   double W = 0, kT = 0, beta = 0, n_e = 0;
   std::vector<void*> owned;  // every device allocation of the prepared state
 
@@ -348,14 +349,15 @@ int cu_count() {
 #define KK_KSPLIT_MAX 4
 #endif
 constexpr int KSPLIT_MAX = KK_KSPLIT_MAX, KSPLIT_MIN_K = 128, KSPLIT_MIN_K_SPLIT = 64;
-int choose_ksplit(int np, int kc, int tiles, int cus, bool one_per_cu, int* chunk_rows) {
+int choose_ksplit(int np, int kc, int tiles, int cus, bool one_per_cu, int* chunk_rows, int min_k = 0) {
   *chunk_rows = kc;
   if (2 * tiles > cus) return 1;
+  if (min_k == 0) min_k = one_per_cu ? KSPLIT_MIN_K_SPLIT : KSPLIT_MIN_K;
   auto load = [&](int c) { return (double)((2 * tiles * c + cus - 1) / cus) / c; };
   int best = 1, best_ck = kc;
   for (int c = 2; c <= KSPLIT_MAX; ++c) {
     const int ck = ((kc + c - 1) / c + KSTEP - 1) / KSTEP * KSTEP;
-    if (ck < (one_per_cu ? KSPLIT_MIN_K_SPLIT : KSPLIT_MIN_K) || c * ck > np) continue;
+    if (ck < min_k || c * ck > np) continue;
     const bool better = one_per_cu ? 2 * tiles * c <= cus : load(c) < load(best);
     if (better) {
       best = c;
@@ -598,9 +600,11 @@ kk_status launch_combine(kk_handle h, int batch, double* q1, const int* stop, co
 kk_status ksplit_transforms_f64(kk_handle h, int batch, const int* stop) {
   const int np = h->np, kch = h->kch, ck = h->kck;
   const size_t np2 = (size_t)np * np;
+  const bool tiny = h->ktiny;  // chunks of the tiny 64 x 64 tiles, else of the 128 x 128 ones
   kk::GemmArgs fa{}, sa{}, ba{};
-  fa.n = np; fa.k_half = ck; fa.two_halves = 0; fa.ntiles = h->n_full; fa.nitems = 2 * batch * kch;
-  fa.tiles = h->tiles_full; fa.stop = stop; fa.beta = h->beta;
+  fa.n = np; fa.k_half = ck; fa.two_halves = 0; fa.ntiles = tiny ? h->n_sfull : h->n_full;
+  fa.nitems = 2 * batch * kch;
+  fa.tiles = tiny ? h->stiles_full : h->tiles_full; fa.stop = stop; fa.beta = h->beta;
   sa = fa;
   sa.nitems = 2 * batch;
   ba = fa;
@@ -626,14 +630,20 @@ kk_status ksplit_transforms_f64(kk_handle h, int batch, const int* stop) {
   if (fa.nitems > kk::MAX_GEMM_BATCH) return fail(KK_EINVAL, "internal: too many GEMM items");
   {
     ProfileScope ps(h, 0);
-    kk::gemm_f64<kk::EPI_XSTORE, kk::BackCfg><<<fa.ntiles * fa.nitems, kk::BackCfg::THREADS, 0, h->stream>>>(fa);
+    if (tiny)
+      kk::gemm_f64<kk::EPI_XSTORE, TinyF64><<<fa.ntiles * fa.nitems, TinyF64::THREADS, 0, h->stream>>>(fa);
+    else
+      kk::gemm_f64<kk::EPI_XSTORE, kk::BackCfg><<<fa.ntiles * fa.nitems, kk::BackCfg::THREADS, 0, h->stream>>>(fa);
     LAUNCH_CHECK("gemm_f64 k-split");
     kk_status st = launch_sym_f64(h, sa, kch, np2);
     if (st) return st;
   }
   {
     ProfileScope ps(h, 1);
-    kk::gemm_f64<kk::EPI_MULLIKEN, kk::BackCfg><<<ba.ntiles * ba.nitems, kk::BackCfg::THREADS, 0, h->stream>>>(ba);
+    if (tiny)
+      kk::gemm_f64<kk::EPI_MULLIKEN, TinyF64><<<ba.ntiles * ba.nitems, TinyF64::THREADS, 0, h->stream>>>(ba);
+    else
+      kk::gemm_f64<kk::EPI_MULLIKEN, kk::BackCfg><<<ba.ntiles * ba.nitems, kk::BackCfg::THREADS, 0, h->stream>>>(ba);
     LAUNCH_CHECK("gemm_f64 k-split");
   }
   return KK_OK;
@@ -1101,11 +1111,13 @@ kk_status prepare_impl(kk_handle h, int n_atoms, const int* atom_offsets, int n_
     h->bf16 = precision == KK_MIXED_BF16;
     h->natoms = n_atoms; h->nb = nb; h->np = np;
     h->kc = (nb + KSTEP - 1) / KSTEP * KSTEP;
-    // the K-split runs on the 128 x 128 tiles of either form (a batch's systems never split)
+    // the K-split runs on the 128 x 128 tiles of either form, for tiny FP64 systems on their
+    // 64 x 64 tiles (a batch's systems never split)
     h->kch = 1;
     h->kck = h->kc;
     h->sk = false;
     h->sk_grid = 0;
+    h->ktiny = false;
     if (!split_large && !mx_large) {
       const int tiles = mixed ? (np / kk::MSmallCfg::BM) * (np / kk::MSmallCfg::BN)
                               : (np / kk::BackCfg::BM) * (np / kk::BackCfg::BN);
@@ -1127,6 +1139,19 @@ kk_status prepare_impl(kk_handle h, int n_atoms, const int* atom_offsets, int n_
     h->kchb = h->kch;
     h->small_f64 = !mixed && np <= SMALL_NP_F64 && h->kch == 1;
     h->tiny_f64 = h->small_f64 && np <= TINY_NP_F64;
+#ifndef KK_TINY_KSPLIT
+#define KK_TINY_KSPLIT 1
+#endif
+    if (KK_TINY_KSPLIT && h->tiny_f64 && !split_large) {
+      // tiny FP64 systems split the contraction of their 64 x 64 tiles instead, in chunks
+      // down to two K stages (16 atoms, kc = 160: four chunks of 64 rows)
+      const int t64 = (np / TinyF64::BM) * (np / TinyF64::BN);
+      const int c = choose_ksplit(np, h->kc, t64, cu_count(), false, &h->kck, 2 * TinyF64::BK);
+      if (c > 1) {
+        h->kch = h->kchb = c;
+        h->ktiny = true;
+      }
+    }
     h->mx_large = mx_large;
     h->nbase = mixed ? (mx_large ? (np / kk::MLargeCfg::BN) * kk::MLargeCfg::WAVES_N
                                  : (np / kk::MSmallCfg::BN) * kk::MSmallCfg::WAVES_N)

@@ -120,7 +120,7 @@ struct kk_handle_s {
   // of partial results per item, sk_grid workgroups per product launch
   bool sk = false;
   int sk_grid = 0;
-  bool ktiny = false;  // FP64 K-split on the tiny 64 x 64 tiles (small_f64 and tiny_f64 stay set)
+  bool ktiny = false;  // FP64 K-split on 64 x 64 TinyF64 tiles (small_f64 and tiny_f64 then set)
   double W = 0, kT = 0, beta = 0, n_e = 0;
   std::vector<void*> owned;  // every device allocation of the prepared state
 
@@ -600,7 +600,7 @@ kk_status launch_combine(kk_handle h, int batch, double* q1, const int* stop, co
 kk_status ksplit_transforms_f64(kk_handle h, int batch, const int* stop) {
   const int np = h->np, kch = h->kch, ck = h->kck;
   const size_t np2 = (size_t)np * np;
-  const bool tiny = h->ktiny;  // chunks of the tiny 64 x 64 tiles, else of the 128 x 128 ones
+  const bool tiny = h->ktiny;  // chunks of 64 x 64 TinyF64 tiles, else of the 128 x 128 ones
   kk::GemmArgs fa{}, sa{}, ba{};
   fa.n = np; fa.k_half = ck; fa.two_halves = 0; fa.ntiles = tiny ? h->n_sfull : h->n_full;
   fa.nitems = 2 * batch * kch;
@@ -1111,8 +1111,8 @@ kk_status prepare_impl(kk_handle h, int n_atoms, const int* atom_offsets, int n_
     h->bf16 = precision == KK_MIXED_BF16;
     h->natoms = n_atoms; h->nb = nb; h->np = np;
     h->kc = (nb + KSTEP - 1) / KSTEP * KSTEP;
-    // the K-split runs on the 128 x 128 tiles of either form, for tiny FP64 systems on their
-    // 64 x 64 tiles (a batch's systems never split)
+    // the K-split runs on the 128 x 128 tiles of either form, for FP64 systems up to a padded
+    // size of 512 on 64 x 64 tiles (a batch's systems never split)
     h->kch = 1;
     h->kck = h->kc;
     h->sk = false;
@@ -1142,14 +1142,26 @@ kk_status prepare_impl(kk_handle h, int n_atoms, const int* atom_offsets, int n_
 #ifndef KK_TINY_KSPLIT
 #define KK_TINY_KSPLIT 1
 #endif
-    if (KK_TINY_KSPLIT && h->tiny_f64 && !split_large) {
-      // tiny FP64 systems split the contraction of their 64 x 64 tiles instead, in chunks
-      // down to two K stages (16 atoms, kc = 160: four chunks of 64 rows)
+#ifndef KK_KTINY_MAX_NP
+#define KK_KTINY_MAX_NP 512
+#endif
+    if (KK_TINY_KSPLIT && !mixed && np <= KK_KTINY_MAX_NP && !split_large) {
+      // FP64 systems up to a padded size of 512 split the contraction of 64 x 64 tiles
+      // (TinyF64, K stage 32) instead, in chunks down to two K stages, whenever the FP64 rule
+      // splits them at all (16 atoms, kc = 160: four chunks of 64 rows, 128 workgroups
+      // instead of 32; 37 atoms: three chunks of 128 rows, 216 workgroups instead of the
+      // 128 x 128 split's 54). Updates/s against the 128 x 128 split or the unsplit 64 x 64
+      // tiles, one process: 16 atoms m = 4 6048 -> 7082, 8 atoms 7187 -> 7795, 29 atoms m = 8
+      // 1680 -> 2977, 37 atoms 1816 -> 2747, 56 atoms 1734 -> 2100; from a padded size of 640
+      // the rule stops splitting these tiles (70 and 85 atoms: level).
       const int t64 = (np / TinyF64::BM) * (np / TinyF64::BN);
-      const int c = choose_ksplit(np, h->kc, t64, cu_count(), false, &h->kck, 2 * TinyF64::BK);
+      int ck = h->kc;
+      const int c = choose_ksplit(np, h->kc, t64, cu_count(), false, &ck, 2 * TinyF64::BK);
       if (c > 1) {
         h->kch = h->kchb = c;
+        h->kck = ck;
         h->ktiny = true;
+        h->small_f64 = h->tiny_f64 = true;
       }
     }
     h->mx_large = mx_large;

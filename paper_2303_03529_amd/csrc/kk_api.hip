@@ -92,6 +92,16 @@ using TinyF64 = kk::TileCfg<64, 64, 32, 2, 2, 2>;
 static_assert(TinyF64::BM == SmallF64::BM && TinyF64::BN == SmallF64::BN && TinyF64::WAVES_N == SmallF64::WAVES_N,
               "the tiny class shares the small class's tile tables and partial rows");
 using SmallMx = kk::MCfg64x64f8;
+// Split forms of small systems (padded size up to MTINY_MAX_NP): the direct-to-LDS loop on
+// 64 x 64 tiles of 4 waves (32 x 32 each), whose K-split fills the chip where the 128 x 128
+// tiles leave it mostly idle (37 atoms: 216 workgroups instead of 72).
+#ifndef KK_MTINY_MAX_NP
+#define KK_MTINY_MAX_NP 512
+#endif
+constexpr int MTINY_MAX_NP = KK_MTINY_MAX_NP;
+using MTinyCfg = kk::MixedDlCfg<64, 64, 2, 2, 3, 8>;
+using MTinyBf6 = kk::MixedDlCfg<64, 64, 2, 2, 3, 8, true, kk::PROD_ALL6>;
+static_assert(SPLIT_PAD_SMALL % MTinyCfg::BM == 0, "tiny split tiles must divide the padding");
 static_assert(kk::PAD % SmallF64::BM == 0 && SPLIT_PAD_LARGE % SmallMx::BM == 0, "small tiles must divide the padding");
 // Rows nb..np-1 of every operand a response transform or a setup product
 // contracts over are zero (the padded copies of S, Z, Q and the potentials are
@@ -136,6 +146,7 @@ struct kk_handle_s {
   bool small_f64 = false;
   bool tiny_f64 = false;  // small_f64 with np <= TINY_NP_F64: TinyF64 kernels
   bool mx_large = false;  // split products on MLargeCfg (else MSmallCfg)
+  bool mx_tiny = false;   // split products on MTinyCfg / MTinyBf6 (64 x 64 tiles)
   bool full_fwd = false;  // FP64 forward as full tiles + fermi_symmetrize_f64 (see full_forward)
   int2 *stiles_upper = nullptr, *stiles_full = nullptr;
   int n_supper = 0, n_sfull = 0;
@@ -750,13 +761,16 @@ kk_status launch_mixed(kk_handle h, bool forward, kk::MixedArgs& a, const _Float
   if ((kch > 1 || a.sk_grid > 0) && h->mx_large) return fail(KK_EINVAL, "internal: K-split on the large split tiles");
   if (h->bf16) {
     ProfileScope ps(h, forward ? 0 : 1);
-    return h->mx_large ? launch_bf16_single<kk::MLargeBf6>(h, forward, a, a2, b2, sym, kch)
-                       : launch_bf16_single<kk::MSmallBf6>(h, forward, a, a2, b2, sym, kch);
+    return h->mx_large  ? launch_bf16_single<kk::MLargeBf6>(h, forward, a, a2, b2, sym, kch)
+           : h->mx_tiny ? launch_bf16_single<MTinyBf6>(h, forward, a, a2, b2, sym, kch)
+                        : launch_bf16_single<kk::MSmallBf6>(h, forward, a, a2, b2, sym, kch);
   }
   if (forward) {
     ProfileScope ps(h, 0);
     if (h->mx_large)
       kk::gemm_mixed<kk::EPI_STORE, kk::MLargeCfg><<<grid, kk::MLargeCfg::THREADS, 0, h->stream>>>(a);
+    else if (h->mx_tiny)
+      kk::gemm_mixed<kk::EPI_STORE, MTinyCfg><<<grid, MTinyCfg::THREADS, 0, h->stream>>>(a);
     else if (a.sk_grid > 0)
       kk::gemm_mixed_sk<kk::EPI_STORE, kk::MSmallCfg><<<a.sk_grid, kk::MSmallCfg::THREADS, 0, h->stream>>>(a);
     else
@@ -775,6 +789,8 @@ kk_status launch_mixed(kk_handle h, bool forward, kk::MixedArgs& a, const _Float
     ProfileScope ps(h, 1);
     if (h->mx_large)
       kk::gemm_mixed<kk::EPI_MULLIKEN, kk::MLargeCfg><<<grid, kk::MLargeCfg::THREADS, 0, h->stream>>>(a);
+    else if (h->mx_tiny)
+      kk::gemm_mixed<kk::EPI_MULLIKEN, MTinyCfg><<<grid, MTinyCfg::THREADS, 0, h->stream>>>(a);
     else if (a.sk_grid > 0)
       kk::gemm_mixed_sk<kk::EPI_MULLIKEN, kk::MSmallCfg><<<a.sk_grid, kk::MSmallCfg::THREADS, 0, h->stream>>>(a);
     else
@@ -986,8 +1002,9 @@ kk_status allocate_prepared(kk_handle h) {
         for (_Float16** q : {&h->Cr[s], &h->GTr[s]})
           if ((st = dalloc_t(h, q, np2))) return st;
     }
-    mfull = h->mx_large ? tile_order(np, kk::MLargeCfg::BM, kk::MLargeCfg::BN, false)
-                        : tile_order(np, kk::MSmallCfg::BM, kk::MSmallCfg::BN, false);
+    mfull = h->mx_large  ? tile_order(np, kk::MLargeCfg::BM, kk::MLargeCfg::BN, false)
+            : h->mx_tiny ? tile_order(np, MTinyCfg::BM, MTinyCfg::BN, false)
+                         : tile_order(np, kk::MSmallCfg::BM, kk::MSmallCfg::BN, false);
     h->n_mfull = (int)mfull.size();
     if (h->sk) {  // the symmetrizing pass of a stream-K product finds tiles by kk::tile_table_pos
       const int T = np / kk::MSmallCfg::BM;
@@ -1118,11 +1135,13 @@ kk_status prepare_impl(kk_handle h, int n_atoms, const int* atom_offsets, int n_
     h->sk = false;
     h->sk_grid = 0;
     h->ktiny = false;
+    h->mx_tiny = mixed && !mx_large && !split_large && np <= MTINY_MAX_NP;
     if (!split_large && !mx_large) {
-      const int tiles = mixed ? (np / kk::MSmallCfg::BM) * (np / kk::MSmallCfg::BN)
-                              : (np / kk::BackCfg::BM) * (np / kk::BackCfg::BN);
+      const int tiles = h->mx_tiny ? (np / MTinyCfg::BM) * (np / MTinyCfg::BN)
+                        : mixed    ? (np / kk::MSmallCfg::BM) * (np / kk::MSmallCfg::BN)
+                                   : (np / kk::BackCfg::BM) * (np / kk::BackCfg::BN);
       h->kch = choose_ksplit(np, h->kc, tiles, cu_count(), mixed, &h->kck);
-      if (mixed && h->kch == 1) {
+      if (mixed && !h->mx_tiny && h->kch == 1) {
         const int slots = choose_stream_k(tiles, h->kc / kk::MSmallCfg::BK, cu_count());
         if (slots > 1) {
           h->sk = true;
@@ -1165,8 +1184,9 @@ kk_status prepare_impl(kk_handle h, int n_atoms, const int* atom_offsets, int n_
       }
     }
     h->mx_large = mx_large;
-    h->nbase = mixed ? (mx_large ? (np / kk::MLargeCfg::BN) * kk::MLargeCfg::WAVES_N
-                                 : (np / kk::MSmallCfg::BN) * kk::MSmallCfg::WAVES_N)
+    h->nbase = mixed ? (mx_large    ? (np / kk::MLargeCfg::BN) * kk::MLargeCfg::WAVES_N
+                        : h->mx_tiny ? (np / MTinyCfg::BN) * MTinyCfg::WAVES_N
+                                     : (np / kk::MSmallCfg::BN) * kk::MSmallCfg::WAVES_N)
                      : h->small_f64 ? (np / SmallF64::BN) * SmallF64::WAVES_N
                                     : (np / kk::BackCfg::BN) * kk::BackCfg::WAVES_N;
     h->nparts = h->kchb * h->nbase;

@@ -1,8 +1,7 @@
 """K-split and stream-K transforms of small single systems against the FP64 oracle, on
-open clusters in all three precisions: 56 atoms (Nb = 504, padded 512: the split forms
-in four chunks of 128 rows on 128 x 128 tiles, FP64 in two chunks of 256 rows on 64 x 64
-tiles) and 113 atoms (Nb = 1017, padded 1024, contraction 1024: two chunks of 512 rows on
-128 x 128 tiles); and 170 atoms (Nb = 1530, padded 1536), where the split forms' products
+open clusters in all three precisions: 56 atoms (Nb = 504, padded 512: two chunks of 256
+rows on 64 x 64 tiles in every form) and 113 atoms (Nb = 1017, padded 1024, contraction
+1024: two chunks of 512 rows on 128 x 128 tiles); and 170 atoms (Nb = 1530, padded 1536), where the split forms' products
 run stream-K (288 tiles for 256 workgroups, two segments per tile at most; the batched
 responses' launch of five directions too) and FP64 runs unsplit on 64 x 64 tiles.
 

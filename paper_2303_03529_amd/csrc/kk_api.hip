@@ -82,7 +82,21 @@ constexpr int SPLIT_LARGE_NB = KK_SPLIT_LARGE_NB;
 // and back 0.144 vs 0.169 ms at Nb = 1152, forward 1.08 vs 1.20 ms and back
 // equal at Nb = 2250, 64 x 64 slower from Nb = 3888. The batch uses the same
 // shapes for its small-tile class (SmallMx in the split form).
-constexpr int SMALL_NP_F64 = 2304;
+#ifndef KK_SMALL_NP_F64
+#define KK_SMALL_NP_F64 2304
+#endif
+constexpr int SMALL_NP_F64 = KK_SMALL_NP_F64;
+// ... unless the 128 x 128 tiles (one workgroup per tile and spin) fit one per CU, or fill two
+// rounds of the CUs to at least LARGE_TILE_FILL. Unsplit handles, one process, m = 8, FP64
+// updates/s on 64 x 64 / 128 x 128 tiles: 140 atoms (200 workgroups for 256 CUs) 297.5 /
+// 323.3, 150 (242) 276.8 / 301.7, 200 (450, two rounds 88 % full) 119.6 / 130.8, 220 (512)
+// 109.2 / 119.7; but 160 and 170 (288, 56 %) 204.9 / 165.7 and 193.4 / 156.2, 190 (392, 77 %)
+// 141.5 / 138.5, 230 (578, three rounds 75 %) 83.8 / 68.0, 250 (648, 84 %) 67.8 / 62.4.
+constexpr double LARGE_TILE_FILL = 0.85;
+bool f64_large_tiles_fill(int np, int cus) {
+  const int t = np / kk::BackCfg::BM, w = 2 * t * (np / kk::BackCfg::BN);
+  return w <= cus || (w <= 2 * cus && w >= LARGE_TILE_FILL * 2 * cus);
+}
 using SmallF64 = kk::Cfg64x64;
 // Tiny systems (padded size up to TINY_NP_F64): the same 64 x 64 tiles with a K stage of 32,
 // half the stages of the latency-bound K loop (16 atoms, Nb = 144: 12.2 us per transform on
@@ -1156,7 +1170,7 @@ kk_status prepare_impl(kk_handle h, int n_atoms, const int* atom_offsets, int n_
     // round the split forms' rule allows it is faster: 113 atoms, m = 8, FP16 x 3 1480 ->
     // 1627 updates/s, BF16 1169 -> 1320; 56 atoms 2241 -> 2575 and 1916 -> 2370.)
     h->kchb = h->kch;
-    h->small_f64 = !mixed && np <= SMALL_NP_F64 && h->kch == 1;
+    h->small_f64 = !mixed && np <= SMALL_NP_F64 && h->kch == 1 && !f64_large_tiles_fill(np, cu_count());
     h->tiny_f64 = h->small_f64 && np <= TINY_NP_F64;
 #ifndef KK_TINY_KSPLIT
 #define KK_TINY_KSPLIT 1

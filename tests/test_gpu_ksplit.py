@@ -3,7 +3,9 @@ open clusters in all three precisions: 56 atoms (Nb = 504, padded 512: two chunk
 rows on 64 x 64 tiles in every form) and 113 atoms (Nb = 1017, padded 1024, contraction
 1024: two chunks of 512 rows on 128 x 128 tiles); and 170 atoms (Nb = 1530, padded 1536), where the split forms' products
 run stream-K (288 tiles for 256 workgroups, two segments per tile at most; the batched
-responses' launch of five directions too) and FP64 runs unsplit on 64 x 64 tiles.
+responses' launch of five directions too) and FP64 runs unsplit on 64 x 64 tiles; and 140
+atoms (Nb = 1260, padded 1280), where FP64 runs unsplit on 128 x 128 tiles (200 workgroups,
+one per CU) and the split forms on theirs, unsplit.
 
 Checked: five responses in one call (the workspace holds two directions at a time
 with four chunks, so the call runs in three batches), each against the oracle's
@@ -32,7 +34,7 @@ TOL = {krylov.KK_FP64: 1e-10, krylov.KK_MIXED_F16: 1e-6, krylov.KK_MIXED_BF16: 1
 PRECISIONS = [krylov.KK_FP64, krylov.KK_MIXED_F16, krylov.KK_MIXED_BF16]
 
 
-@pytest.fixture(scope="module", params=[56, 113, 170], ids=["fe56", "fe113", "fe170"])
+@pytest.fixture(scope="module", params=[56, 113, 140, 170], ids=["fe56", "fe113", "fe140", "fe170"])
 def system(request):
     n = request.param
     sysd = make_system(n_atoms=n, seed=20_000 + n)

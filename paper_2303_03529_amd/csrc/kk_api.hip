@@ -86,16 +86,24 @@ constexpr int SPLIT_LARGE_NB = KK_SPLIT_LARGE_NB;
 #define KK_SMALL_NP_F64 2304
 #endif
 constexpr int SMALL_NP_F64 = KK_SMALL_NP_F64;
-// ... unless the 128 x 128 tiles (one workgroup per tile and spin) fit one per CU, or fill two
-// rounds of the CUs to at least LARGE_TILE_FILL. Unsplit handles, one process, m = 8, FP64
-// updates/s on 64 x 64 / 128 x 128 tiles: 140 atoms (200 workgroups for 256 CUs) 297.5 /
-// 323.3, 150 (242) 276.8 / 301.7, 200 (450, two rounds 88 % full) 119.6 / 130.8, 220 (512)
-// 109.2 / 119.7; but 160 and 170 (288, 56 %) 204.9 / 165.7 and 193.4 / 156.2, 190 (392, 77 %)
-// 141.5 / 138.5, 230 (578, three rounds 75 %) 83.8 / 68.0, 250 (648, 84 %) 67.8 / 62.4.
-constexpr double LARGE_TILE_FILL = 0.85;
+// ... unless the 128 x 128 tiles (one workgroup per tile and spin) fit one per CU, or fill
+// their rounds of one workgroup per CU to at least LARGE_TILE_FILL; those handles run the
+// full-tile forward (the rounds rule of full_forward, which counts two workgroup slots per
+// CU, would take the upper-tile form at 250 atoms). Unsplit handles, one process, m = 8, FP64
+// updates/s on 64 x 64 / 128 x 128 tiles: 140 atoms (200 workgroups for 256 CUs) 297.6 /
+// 324.2, 150 (242) 277.6 / 303.5, 200 (450, two rounds 88 % full) 119.6 / 131.0, 220 (512)
+// 108.8 / 120.0, 250 (648, three rounds 84 %) 67.8 / 71.8 (62.5 with the upper-tile forward);
+// but 160 and 170 (288, 56 %) 204.9 / 165.7 and 194.2 / 156.8, 190 (392, 77 %) 142.0 / 139.0,
+// 230 (578, 75 %) 84.1 / 78.5.
+// Measured from a padded size of 1280 up; smaller handles are K-split (128 x 128 or, up to
+// 512, 64 x 64 tiles) or run the tiny class.
+constexpr double LARGE_TILE_FILL = 0.8;
+constexpr int LARGE_FILL_MIN_NP = 1280;
 bool f64_large_tiles_fill(int np, int cus) {
-  const int t = np / kk::BackCfg::BM, w = 2 * t * (np / kk::BackCfg::BN);
-  return w <= cus || (w <= 2 * cus && w >= LARGE_TILE_FILL * 2 * cus);
+  if (np < LARGE_FILL_MIN_NP) return false;
+  const int w = 2 * (np / kk::BackCfg::BM) * (np / kk::BackCfg::BN);
+  const int rounds = (w + cus - 1) / cus;
+  return rounds == 1 || w >= LARGE_TILE_FILL * rounds * cus;
 }
 using SmallF64 = kk::Cfg64x64;
 // Tiny systems (padded size up to TINY_NP_F64): the same 64 x 64 tiles with a K stage of 32,
@@ -158,6 +166,7 @@ struct kk_handle_s {
   int n_upper = 0, n_full = 0, n_store = 0;
   // small systems: 64 x 64 tiles for the FP64 response transforms
   bool small_f64 = false;
+  bool large_fill = false;  // unsplit FP64 handle up to SMALL_NP_F64 on 128 x 128 tiles (f64_large_tiles_fill)
   bool tiny_f64 = false;  // small_f64 with np <= TINY_NP_F64: TinyF64 kernels
   bool mx_large = false;  // split products on MLargeCfg (else MSmallCfg)
   bool mx_tiny = false;   // split products on MTinyCfg / MTinyBf6 (64 x 64 tiles)
@@ -984,7 +993,7 @@ kk_status allocate_prepared(kk_handle h) {
   h->n_full = (int)full.size();
   h->n_store = (int)stt.size();
   static_assert(kk::FwdCfg::MIN_BLOCKS == kk::BackCfg::MIN_BLOCKS, "one slot count for both forward forms");
-  h->full_fwd = h->kch > 1 ||
+  h->full_fwd = h->kch > 1 || h->large_fill ||
                 (h->small_f64 ? full_forward(h->n_supper, h->n_sfull,
                                             cu_count() * (h->tiny_f64 ? TinyF64::MIN_BLOCKS : SmallF64::MIN_BLOCKS))
                               : full_forward(h->n_upper, h->n_full, cu_count() * kk::BackCfg::MIN_BLOCKS));
@@ -1170,7 +1179,8 @@ kk_status prepare_impl(kk_handle h, int n_atoms, const int* atom_offsets, int n_
     // round the split forms' rule allows it is faster: 113 atoms, m = 8, FP16 x 3 1480 ->
     // 1627 updates/s, BF16 1169 -> 1320; 56 atoms 2241 -> 2575 and 1916 -> 2370.)
     h->kchb = h->kch;
-    h->small_f64 = !mixed && np <= SMALL_NP_F64 && h->kch == 1 && !f64_large_tiles_fill(np, cu_count());
+    h->large_fill = !mixed && np <= SMALL_NP_F64 && h->kch == 1 && f64_large_tiles_fill(np, cu_count());
+    h->small_f64 = !mixed && np <= SMALL_NP_F64 && h->kch == 1 && !h->large_fill;
     h->tiny_f64 = h->small_f64 && np <= TINY_NP_F64;
 #ifndef KK_TINY_KSPLIT
 #define KK_TINY_KSPLIT 1

@@ -87,12 +87,10 @@ constexpr int SPLIT_LARGE_NB = KK_SPLIT_LARGE_NB;
 #endif
 constexpr int SMALL_NP_F64 = KK_SMALL_NP_F64;
 // ... unless the 128 x 128 tiles (one workgroup per tile and spin) fit one per CU, or fill
-// their rounds of one workgroup per CU to at least LARGE_TILE_FILL; those handles run the
-// full-tile forward (the rounds rule of full_forward, which counts two workgroup slots per
-// CU, would take the upper-tile form at 250 atoms). Unsplit handles, one process, m = 8, FP64
-// updates/s on 64 x 64 / 128 x 128 tiles: 140 atoms (200 workgroups for 256 CUs) 297.6 /
+// their rounds of one workgroup per CU to at least LARGE_TILE_FILL. Unsplit handles, one
+// process, m = 8, FP64 updates/s on 64 x 64 / 128 x 128 tiles (full-tile forward): 140 atoms (200 workgroups for 256 CUs) 297.6 /
 // 324.2, 150 (242) 277.6 / 303.5, 200 (450, two rounds 88 % full) 119.6 / 131.0, 220 (512)
-// 108.8 / 120.0, 250 (648, three rounds 84 %) 67.8 / 71.8 (62.5 with the upper-tile forward);
+// 108.8 / 120.0, 250 (648, three rounds 84 %) 67.8 / 71.8 (62.5 with the upper-tile form);
 // but 160 and 170 (288, 56 %) 204.9 / 165.7 and 194.2 / 156.8, 190 (392, 77 %) 142.0 / 139.0,
 // 230 (578, 75 %) 84.1 / 78.5.
 // Measured from a padded size of 1280 up; smaller handles are K-split (128 x 128 or, up to
@@ -166,7 +164,6 @@ struct kk_handle_s {
   int n_upper = 0, n_full = 0, n_store = 0;
   // small systems: 64 x 64 tiles for the FP64 response transforms
   bool small_f64 = false;
-  bool large_fill = false;  // unsplit FP64 handle up to SMALL_NP_F64 on 128 x 128 tiles (f64_large_tiles_fill)
   bool tiny_f64 = false;  // small_f64 with np <= TINY_NP_F64: TinyF64 kernels
   bool mx_large = false;  // split products on MLargeCfg (else MSmallCfg)
   bool mx_tiny = false;   // split products on MTinyCfg / MTinyBf6 (64 x 64 tiles)
@@ -433,14 +430,31 @@ int choose_stream_k(int tiles_per_item, int nk, int cus) {
 // Form of the FP64 forward transform of one direction (both spins): the upper
 // tiles over two K halves with the Fermi product in the epilogue, or all tiles
 // over one half (half the cost each) followed by fermi_symmetrize_f64. The full
-// form is taken when it needs fewer rounds of workgroup slots, a partial round
-// counted whole (ties go to the one-kernel form). On MI355X this picks the full
-// form at Nb = 1152 (forward 0.15 vs 0.20 ms) and 9216 (46.4 vs 47.2 ms) and the
-// upper form at 3888 (3.89 vs 3.95 ms).
+// form is taken when it needs fewer rounds of `slots` workgroups, a partial round
+// counted whole (ties go to the one-kernel form); the 64 x 64 tiles decide so. On MI355X
+// this picked the full form at Nb = 1152 (forward 0.15 vs 0.20 ms) and 9216 (46.4 vs
+// 47.2 ms) and the upper form at 3888 (3.89 vs 3.95 ms).
 bool full_forward(int n_upper, int n_full, int slots) {
   const int upper_rounds = (2 * n_upper + slots - 1) / slots;
   const int full_rounds = (2 * n_full + slots - 1) / slots;
   return full_rounds < 2 * upper_rounds;
+}
+// The 128 x 128 tiles (two co-resident workgroups per CU) compare modelled launch times
+// instead: w workgroups of `len` K-loop units on `cus` CUs run as whole rounds of two per CU,
+// then the rest one per CU (at most cus of them) or two; two co-resident workgroups take
+// PAIR_TIME of one alone, and the full form's symmetrizing pass SYM_TIME. Counting both slots
+// as whole rounds chose badly where a round of pairs meets a round of singles; FP64 updates/s
+// (m = 8, one process) with this choice against that one: 200 atoms (full form) 128.9 ->
+// 132.0, 250 atoms 67.5 -> 71.8, 270 atoms 58.4 -> 66.6, 398 atoms 18.6 -> 19.9, 512 atoms
+// 9.5 -> 9.9; 432 and 1024 atoms choose as before (upper form 3.89 against 3.95 ms, full form
+// 46.4 against 47.2 ms).
+constexpr double PAIR_TIME = 1.7, SYM_TIME = 0.1;
+double launch_time(int w, int cus, double len) {
+  const int p = w / (2 * cus), r = w - 2 * cus * p;
+  return len * (PAIR_TIME * p + (r == 0 ? 0.0 : r <= cus ? 1.0 : PAIR_TIME));
+}
+bool full_forward_pairs(int n_upper, int n_full, int cus) {
+  return launch_time(2 * n_full, cus, 1.0) + SYM_TIME < launch_time(2 * n_upper, cus, 2.0);
 }
 
 // Tile table order: groups of GROUP tile rows, each group walked column by column, so that
@@ -993,10 +1007,10 @@ kk_status allocate_prepared(kk_handle h) {
   h->n_full = (int)full.size();
   h->n_store = (int)stt.size();
   static_assert(kk::FwdCfg::MIN_BLOCKS == kk::BackCfg::MIN_BLOCKS, "one slot count for both forward forms");
-  h->full_fwd = h->kch > 1 || h->large_fill ||
+  h->full_fwd = h->kch > 1 ||
                 (h->small_f64 ? full_forward(h->n_supper, h->n_sfull,
                                             cu_count() * (h->tiny_f64 ? TinyF64::MIN_BLOCKS : SmallF64::MIN_BLOCKS))
-                              : full_forward(h->n_upper, h->n_full, cu_count() * kk::BackCfg::MIN_BLOCKS));
+                              : full_forward_pairs(h->n_upper, h->n_full, cu_count()));
   if ((st = dalloc_t(h, &h->tiles_upper, up.size()))) return st;
   if ((st = dalloc_t(h, &h->tiles_full, full.size()))) return st;
   if ((st = dalloc_t(h, &h->tiles_store, stt.size()))) return st;
@@ -1179,8 +1193,7 @@ kk_status prepare_impl(kk_handle h, int n_atoms, const int* atom_offsets, int n_
     // round the split forms' rule allows it is faster: 113 atoms, m = 8, FP16 x 3 1480 ->
     // 1627 updates/s, BF16 1169 -> 1320; 56 atoms 2241 -> 2575 and 1916 -> 2370.)
     h->kchb = h->kch;
-    h->large_fill = !mixed && np <= SMALL_NP_F64 && h->kch == 1 && f64_large_tiles_fill(np, cu_count());
-    h->small_f64 = !mixed && np <= SMALL_NP_F64 && h->kch == 1 && !h->large_fill;
+    h->small_f64 = !mixed && np <= SMALL_NP_F64 && h->kch == 1 && !f64_large_tiles_fill(np, cu_count());
     h->tiny_f64 = h->small_f64 && np <= TINY_NP_F64;
 #ifndef KK_TINY_KSPLIT
 #define KK_TINY_KSPLIT 1

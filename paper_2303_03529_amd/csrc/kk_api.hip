@@ -167,7 +167,7 @@ struct kk_handle_s {
   bool tiny_f64 = false;  // small_f64 with np <= TINY_NP_F64: TinyF64 kernels
   bool mx_large = false;  // split products on MLargeCfg (else MSmallCfg)
   bool mx_tiny = false;   // split products on MTinyCfg / MTinyBf6 (64 x 64 tiles)
-  bool full_fwd = false;  // FP64 forward as full tiles + fermi_symmetrize_f64 (see full_forward)
+  bool full_fwd = false;  // FP64 forward as full tiles + fermi_symmetrize_f64 (K-splits, 64 x 64 tiles, full_forward_pairs)
   int2 *stiles_upper = nullptr, *stiles_full = nullptr;
   int n_supper = 0, n_sfull = 0;
 
@@ -429,16 +429,11 @@ int choose_stream_k(int tiles_per_item, int nk, int cus) {
 
 // Form of the FP64 forward transform of one direction (both spins): the upper
 // tiles over two K halves with the Fermi product in the epilogue, or all tiles
-// over one half (half the cost each) followed by fermi_symmetrize_f64. The full
-// form is taken when it needs fewer rounds of `slots` workgroups, a partial round
-// counted whole (ties go to the one-kernel form); the 64 x 64 tiles decide so. On MI355X
-// this picked the full form at Nb = 1152 (forward 0.15 vs 0.20 ms) and 9216 (46.4 vs
-// 47.2 ms) and the upper form at 3888 (3.89 vs 3.95 ms).
-bool full_forward(int n_upper, int n_full, int slots) {
-  const int upper_rounds = (2 * n_upper + slots - 1) / slots;
-  const int full_rounds = (2 * n_full + slots - 1) / slots;
-  return full_rounds < 2 * upper_rounds;
-}
+// over one half (half the cost each) followed by fermi_symmetrize_f64. The 64 x 64 tiles
+// (unsplit handles of padded size 1536-2176 after f64_large_tiles_fill and the K-splits)
+// always take the full form: FP64 updates/s, m = 8, one process, upper / full form, 170
+// atoms 193.8 / 210.0, 165 atoms 197.9 / 215.2, 190 atoms 133.6 / 140.9, 230 atoms 84.1 /
+// 85.2.
 // The 128 x 128 tiles (two co-resident workgroups per CU) compare modelled launch times
 // instead: w workgroups of `len` K-loop units on `cus` CUs run as whole rounds of two per CU,
 // then the rest one per CU (at most cus of them) or two; two co-resident workgroups take
@@ -1007,10 +1002,7 @@ kk_status allocate_prepared(kk_handle h) {
   h->n_full = (int)full.size();
   h->n_store = (int)stt.size();
   static_assert(kk::FwdCfg::MIN_BLOCKS == kk::BackCfg::MIN_BLOCKS, "one slot count for both forward forms");
-  h->full_fwd = h->kch > 1 ||
-                (h->small_f64 ? full_forward(h->n_supper, h->n_sfull,
-                                            cu_count() * (h->tiny_f64 ? TinyF64::MIN_BLOCKS : SmallF64::MIN_BLOCKS))
-                              : full_forward_pairs(h->n_upper, h->n_full, cu_count()));
+  h->full_fwd = h->kch > 1 || h->small_f64 || full_forward_pairs(h->n_upper, h->n_full, cu_count());
   if ((st = dalloc_t(h, &h->tiles_upper, up.size()))) return st;
   if ((st = dalloc_t(h, &h->tiles_full, full.size()))) return st;
   if ((st = dalloc_t(h, &h->tiles_store, stt.size()))) return st;

@@ -5,7 +5,9 @@ rows on 64 x 64 tiles in every form) and 113 atoms (Nb = 1017, padded 1024, cont
 run stream-K (288 tiles for 256 workgroups, two segments per tile at most; the batched
 responses' launch of five directions too) and FP64 runs unsplit on 64 x 64 tiles; and 140
 atoms (Nb = 1260, padded 1280), where FP64 runs unsplit on 128 x 128 tiles (200 workgroups,
-one per CU) and the split forms on theirs, unsplit.
+one per CU) and the split forms on theirs, unsplit; and 250 atoms (Nb = 2250, padded 2304),
+where FP64 runs 128 x 128 tiles with the full-tile forward in three rounds of workgroups (the
+largest padded size the small-system rules decide) and the split forms three rounds of theirs.
 
 Checked: five responses in one call (the workspace holds two directions at a time
 with four chunks, so the call runs in three batches), each against the oracle's
@@ -34,7 +36,7 @@ TOL = {krylov.KK_FP64: 1e-10, krylov.KK_MIXED_F16: 1e-6, krylov.KK_MIXED_BF16: 1
 PRECISIONS = [krylov.KK_FP64, krylov.KK_MIXED_F16, krylov.KK_MIXED_BF16]
 
 
-@pytest.fixture(scope="module", params=[56, 113, 140, 170], ids=["fe56", "fe113", "fe140", "fe170"])
+@pytest.fixture(scope="module", params=[56, 113, 140, 170, 250], ids=["fe56", "fe113", "fe140", "fe170", "fe250"])
 def system(request):
     n = request.param
     sysd = make_system(n_atoms=n, seed=20_000 + n)
@@ -86,10 +88,9 @@ def test_ksplit_breakdown_fp64():
 @pytest.mark.parametrize("precision", PRECISIONS, ids=["fp64", "f16x3", "bf16"])
 def test_ksplit_dense_preconditioner(system, precision):
     """A dense K0 (the fused step then leaves the preconditioning to its own launch after
-    each response) at the two K-split sizes, and for FP64 also the adaptive-rank call (a
-    solve after each direction; at tolerance 0.1 it stops at rank 6 and 8 here, and the
-    split forms' rounding could move a stopping rank across the tolerance), against the
-    oracle."""
+    each response) at every size of the module, and for FP64 also the adaptive-rank call (a
+    solve after each direction, checked against the oracle's stopping rank; the split forms'
+    rounding could move a stopping rank across the tolerance), against the oracle."""
     sysd, ep = system
     n2 = 2 * sysd["n_atoms"]
     K0 = -np.eye(n2) + 0.05 * np.random.default_rng(13).standard_normal((n2, n2))

@@ -3,8 +3,8 @@ the C ABI, against krylov_kernel_apply on the same handles: two calls in a
 row (a 128-atom bcc cell, then a smaller 37-atom open cluster, so the second
 call reuses the fixed scratch array holding the first call's data), in FP64
 and in the split-precision forms, plus the FP64 results against the oracle, the
-split forms' stream-K products in the scratch array, and the refusal of a handle
-whose workspace does not fit."""
+split forms' stream-K products in the scratch array, FP64 handles on the large tile
+class of small systems, and the refusal of a handle whose workspace does not fit."""
 
 import numpy as np
 import pytest
@@ -80,6 +80,28 @@ def test_noalloc_stream_k_products(precision):
             err = rel(got.cpu().numpy(), ref.cpu().numpy())
             print(f"  vs krylov_kernel_apply: {err:.2e}; rank {info.rank_used}", flush=True)
             assert info.rank_used == 6 and err < 1e-15
+        finally:
+            h.close()
+
+
+def test_noalloc_fp64_large_tile_class():
+    """FP64 handles on the 128 x 128 tiles below a padded size of 2304 (250 atoms: full-tile
+    forward in three rounds of workgroups, 85 MB of the scratch array; then 140 atoms, one
+    round) through the allocation-free entry point, each against krylov_kernel_apply on the
+    same handle, bit for bit."""
+    cases = [make_system(n_atoms=250, seed=20_250), make_system(n_atoms=140, seed=20_140)]
+    for call, sysd in enumerate(cases):
+        ep = expansion_point(sysd)
+        print(f"no-alloc FP64 call {call}: {sysd['n_atoms']} atoms", flush=True)
+        h = handle_from_expansion(sysd, ep, krylov.KK_FP64)
+        try:
+            d = t(sysd["delta"])
+            ref, _ = h.krylov_kernel_apply(d, 6)
+            got, info = h.krylov_kernel_apply_noalloc(d, 6, out=torch.full_like(d, float("nan")))
+            torch.cuda.synchronize()
+            err = rel(got.cpu().numpy(), ref.cpu().numpy())
+            print(f"  vs krylov_kernel_apply: {err:.2e}; rank {info.rank_used}", flush=True)
+            assert info.rank_used == 6 and err == 0.0
         finally:
             h.close()
 

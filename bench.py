@@ -75,11 +75,15 @@ def parse():
 
 
 def gemm_source_digest(precision: str = "fp64") -> str:
-    """First 16 hex of the sha256 of the header holding the transform kernels."""
+    """First 16 hex of the sha256 of the headers holding the forward step's kernels (FP64:
+    kk_gemm.hpp; split forms: kk_gemm_mixed.hpp, then kk_fused.hpp with the large handles'
+    symmetrizing pass)."""
     import hashlib
-    name = "kk_gemm.hpp" if precision == "fp64" else "kk_gemm_mixed.hpp"
-    src = os.path.join(ROOT, "paper_2303_03529_amd", "csrc", name)
-    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    names = ["kk_gemm.hpp"] if precision == "fp64" else ["kk_gemm_mixed.hpp", "kk_fused.hpp"]
+    h = hashlib.sha256()
+    for name in names:
+        h.update(open(os.path.join(ROOT, "paper_2303_03529_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def cpu_baseline(sysd, m):

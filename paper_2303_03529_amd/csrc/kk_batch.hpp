@@ -115,86 +115,6 @@ __device__ __forceinline__ int pair_item(const int* __restrict__ pair_off, int n
 constexpr int BATCH_SYM_B_MIXED = SYM_B_LARGE, BATCH_SYM_T_MIXED = SYM_T_LARGE;
 constexpr int BATCH_SYM_B_F64 = SYM64_B_LARGE, BATCH_SYM_T_F64 = SYM64_T_LARGE;
 
-// Block pair (I <= J) from the upper-triangle index, row-major (as fermi_symmetrize_dev).
-__device__ __forceinline__ int2 b_upper_pair(int pair, int nblk) {
-  int I = 0, rem = pair;
-  while (rem >= nblk - I) {
-    rem -= nblk - I;
-    ++I;
-  }
-  return make_int2(I, I + rem);
-}
-
-// The split batch's symmetrizing pass for one 64 x 64 block pair (I <= J) of an item, as
-// fermi_symmetrize_dev<64, 512> computes it, with eight consecutive elements per thread:
-// thread (r, q) takes columns 8q..8q+7 of row r of both blocks (32-byte loads of A, 16-byte
-// stores of each Y piece), and every global load of the block is issued before the first is
-// used.
-typedef float bsym_f4 __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ void b_symmetrize_v8_dev(const MixedItem& it, const int n, const double beta,
-                                                    const int pair) {
-  constexpr int B = 64;
-  const int2 ij = b_upper_pair(pair, n / B);
-  const int I = ij.x, J = ij.y;
-  __shared__ double At[B][B + 1];
-  __shared__ _Float16 Tp[2][B][B + 8];
-  const int r = threadIdx.x >> 3, c8 = (threadIdx.x & 7) * 8;
-  const int m = I * B + r, cb = J * B + c8;
-  const size_t oo = (size_t)m * n + cb, om = (size_t)(J * B + r) * n + I * B + c8;
-  const bsym_f4 own0 = *reinterpret_cast<const bsym_f4*>(it.x32 + oo);
-  const bsym_f4 own1 = *reinterpret_cast<const bsym_f4*>(it.x32 + oo + 4);
-  const bsym_f4 mir0 = *reinterpret_cast<const bsym_f4*>(it.x32 + om);
-  const bsym_f4 mir1 = *reinterpret_cast<const bsym_f4*>(it.x32 + om + 4);
-  const double em = it.eps[m], fm = it.f[m], fcm = it.fc[m], wm = it.w[m];
-  d2 en[4], fn[4], fcn[4];
-#pragma unroll
-  for (int h = 0; h < 4; ++h) {
-    en[h] = reinterpret_cast<const d2*>(it.eps + cb)[h];
-    fn[h] = reinterpret_cast<const d2*>(it.f + cb)[h];
-    fcn[h] = reinterpret_cast<const d2*>(it.fc + cb)[h];
-  }
-  const double inv = it.sc[0], sy = it.sc[1];
-#pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    At[r][c8 + e] = (double)mir0[e];
-    At[r][c8 + 4 + e] = (double)mir1[e];
-  }
-  __syncthreads();
-  h8 pv[2];
-#pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const int c = c8 + e;
-    const double a = (double)(e < 4 ? own0[e & 3] : own1[e & 3]);
-    const double x = 0.5 * inv * (a + At[c][r]);
-    double y;
-    if (m == cb + e) {
-      it.xdiag[m] = x;
-      y = -wm * x * sy;
-    } else {
-      y = fermi_divided_difference(em, fm, fcm, en[e >> 1][e & 1], fn[e >> 1][e & 1], fcn[e >> 1][e & 1], beta) *
-          x * sy;
-    }
-    _Float16 pc[2];
-    split_pieces<false, 2>(y, pc);
-#pragma unroll
-    for (int p = 0; p < 2; ++p) {
-      pv[p][e] = pc[p];
-      Tp[p][c][r] = pc[p];
-    }
-  }
-  *reinterpret_cast<h8*>(it.yh + oo) = pv[0];
-  *reinterpret_cast<h8*>(it.yl + oo) = pv[1];
-  if (I == J) return;  // a diagonal block is symmetric by construction (the same in every thread)
-  __syncthreads();
-#pragma unroll
-  for (int p = 0; p < 2; ++p) {
-    h8 t;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) t[e] = Tp[p][r][c8 + e];
-    *reinterpret_cast<h8*>((p == 0 ? it.yh : it.yl) + om) = t;
-  }
-}
-
 // (Against fermi_symmetrize_dev<64, 512>, one element per thread and row: the same bits, and
 // the 64-cluster split batch 19.59 -> 19.76 batch updates/s, one process.)
 __global__ __launch_bounds__(BATCH_SYM_T_MIXED) void b_symmetrize(const BatchItemMixed* __restrict__ items,
@@ -203,7 +123,7 @@ __global__ __launch_bounds__(BATCH_SYM_T_MIXED) void b_symmetrize(const BatchIte
   const int z = pair_item(pair_off, nitems, blockIdx.x);
   const BatchItemMixed& it = items[z];
   if (*it.stop) return;
-  b_symmetrize_v8_dev(it.g, it.n, it.beta, blockIdx.x - pair_off[z]);
+  fermi_symmetrize_v8_dev<false, 2>(it.g, it.n, it.beta, blockIdx.x - pair_off[z]);
 }
 
 __global__ __launch_bounds__(BATCH_SYM_T_F64) void b_symmetrize_f64(const BatchItemF64* __restrict__ items,

@@ -582,4 +582,84 @@ __global__ __launch_bounds__(T) void fermi_symmetrize_chunks(const MixedArgs arg
   }
 }
 
+// Symmetrizing pass of the split forms for one 64 x 64 block pair (I <= J) of an item, as
+// fermi_symmetrize_dev<64, 512, BF16, NP> computes it (the same bits), with eight
+// consecutive elements per thread: thread (r, q) of 512 takes columns 8q..8q+7 of row r of
+// both blocks (32-byte loads of A, 16-byte stores of each Y piece), and every global load of
+// the block is issued before the first is used. Used by large split handles and by the split
+// batches (b_symmetrize).
+template <bool BF16, int NP>
+__device__ __forceinline__ void fermi_symmetrize_v8_dev(const MixedItem& it, const int n, const double beta,
+                                                        const int pair) {
+  static_assert(NP == 2 || NP == 3, "two or three pieces");
+  constexpr int B = 64;
+  const int2 ij = upper_pair(pair, n / B);
+  const int I = ij.x, J = ij.y;
+  __shared__ double At[B][B + 1];
+  __shared__ _Float16 Tp[NP][B][B + 8];
+  const int r = threadIdx.x >> 3, c8 = (threadIdx.x & 7) * 8;
+  const int m = I * B + r, cb = J * B + c8;
+  const size_t oo = (size_t)m * n + cb, om = (size_t)(J * B + r) * n + I * B + c8;
+  const f4v own0 = *reinterpret_cast<const f4v*>(it.x32 + oo);
+  const f4v own1 = *reinterpret_cast<const f4v*>(it.x32 + oo + 4);
+  const f4v mir0 = *reinterpret_cast<const f4v*>(it.x32 + om);
+  const f4v mir1 = *reinterpret_cast<const f4v*>(it.x32 + om + 4);
+  const double em = it.eps[m], fm = it.f[m], fcm = it.fc[m], wm = it.w[m];
+  d2 en[4], fn[4], fcn[4];
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    en[h] = reinterpret_cast<const d2*>(it.eps + cb)[h];
+    fn[h] = reinterpret_cast<const d2*>(it.f + cb)[h];
+    fcn[h] = reinterpret_cast<const d2*>(it.fc + cb)[h];
+  }
+  const double inv = it.sc[0], sy = it.sc[1];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    At[r][c8 + e] = (double)mir0[e];
+    At[r][c8 + 4 + e] = (double)mir1[e];
+  }
+  __syncthreads();
+  h8 pv[NP];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int c = c8 + e;
+    const double a = (double)(e < 4 ? own0[e & 3] : own1[e & 3]);
+    const double x = 0.5 * inv * (a + At[c][r]);
+    double y;
+    if (m == cb + e) {
+      it.xdiag[m] = x;
+      y = -wm * x * sy;
+    } else {
+      y = fermi_divided_difference(em, fm, fcm, en[e >> 1][e & 1], fn[e >> 1][e & 1], fcn[e >> 1][e & 1], beta) *
+          x * sy;
+    }
+    _Float16 pc[NP];
+    split_pieces<BF16, NP>(y, pc);
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      pv[p][e] = pc[p];
+      Tp[p][c][r] = pc[p];
+    }
+  }
+  *reinterpret_cast<h8*>(it.yh + oo) = pv[0];
+  *reinterpret_cast<h8*>(it.yl + oo) = pv[1];
+  if constexpr (NP == 3) *reinterpret_cast<h8*>(it.yr + oo) = pv[2];
+  if (I == J) return;  // a diagonal block is symmetric by construction (the same in every thread)
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    h8 t;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) t[e] = Tp[p][r][c8 + e];
+    *reinterpret_cast<h8*>((p == 0 ? it.yh : p == 1 ? it.yl : it.yr) + om) = t;
+  }
+}
+
+// Single split handles on the large tiles: blockIdx.x = block pair, blockIdx.y = item.
+template <bool BF16, int NP>
+__global__ __launch_bounds__(512) void fermi_symmetrize_v8(const MixedArgs args) {
+  if (args.stop != nullptr && *args.stop != 0) return;
+  fermi_symmetrize_v8_dev<BF16, NP>(args.item[blockIdx.y], args.n, args.beta, blockIdx.x);
+}
+
 }  // namespace kk

@@ -757,7 +757,7 @@ kk_status response_chunk(kk_handle h, int batch, const double* v, double* q1, co
 // K-split (sym != nullptr): a's items are the kch chunks of each of sym's items, whose
 // symmetrizing pass sums their partial products.
 // Large split handles symmetrize on 64 x 64 block pairs with eight elements per thread
-// (fermi_symmetrize_v8): against one element per thread and row (fermi_symmetrize<64, 512>),
+// (fermi_symmetrize_v8): against the earlier pass with one element per thread and row,
 // the same bits and, one process, FP16 x 3 / BF16 updates/s 1024 atoms 4.348 -> 4.357 /
 // 2.392 -> 2.406, 432 atoms 77.03 -> 77.40 / 44.27 -> 44.87.
 static_assert(kk::SYM_B_LARGE == 64, "the large handles' symmetrizing pass runs 64 x 64 block pairs");

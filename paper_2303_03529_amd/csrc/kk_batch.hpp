@@ -115,7 +115,7 @@ __device__ __forceinline__ int pair_item(const int* __restrict__ pair_off, int n
 constexpr int BATCH_SYM_B_MIXED = SYM_B_LARGE, BATCH_SYM_T_MIXED = SYM_T_LARGE;
 constexpr int BATCH_SYM_B_F64 = SYM64_B_LARGE, BATCH_SYM_T_F64 = SYM64_T_LARGE;
 
-// (Against fermi_symmetrize_dev<64, 512>, one element per thread and row: the same bits, and
+// (Against the earlier pass with one element per thread and row: the same bits, and
 // the 64-cluster split batch 19.59 -> 19.76 batch updates/s, one process.)
 __global__ __launch_bounds__(BATCH_SYM_T_MIXED) void b_symmetrize(const BatchItemMixed* __restrict__ items,
                                                                   const int* __restrict__ pair_off, int nitems) {

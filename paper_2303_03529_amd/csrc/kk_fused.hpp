@@ -582,8 +582,8 @@ __global__ __launch_bounds__(T) void fermi_symmetrize_chunks(const MixedArgs arg
   }
 }
 
-// Symmetrizing pass of the split forms for one 64 x 64 block pair (I <= J) of an item, as
-// fermi_symmetrize_dev<64, 512, BF16, NP> computes it (the same bits), with eight
+// Symmetrizing pass of the split forms for one 64 x 64 block pair (I <= J) of an item (the
+// arithmetic of fermi_symmetrize_chunks, element by element), with eight
 // consecutive elements per thread: thread (r, q) of 512 takes columns 8q..8q+7 of row r of
 // both blocks (32-byte loads of A, 16-byte stores of each Y piece), and every global load of
 // the block is issued before the first is used. Used by large split handles and by the split

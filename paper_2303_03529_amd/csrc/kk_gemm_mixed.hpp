@@ -721,76 +721,20 @@ __global__ __launch_bounds__(Cfg::THREADS, Cfg::MIN_BLOCKS) void gemm_mixed_sk(c
   }
 }
 
-// Second pass of the split forward transform in its full-tile form. For one
-// B x B block pair (I <= J) of an item: X = (A + A^T) / 2 / s_prod in FP64 from
-// the FP32 product A, Y = F o X off the diagonal and Y_ii = -w_i X_ii (X_ii to
-// xdiag), split at the Y scale and written to block (I, J) and, through LDS, to
-// its mirror (J, I). pair indexes the upper triangle row-major; T threads.
-// Small handles and batches: 32 x 32 blocks of 256 threads, 4 elements per thread (64 x 64
-// with 16 each: 24 instead of 14 us at Nb = 1152). Large handles: 64 x 64 blocks of 512
-// threads, whose 256-byte row reads and 128-byte row writes use HBM better than the 128- and
-// 64-byte segments of 32 x 32 blocks.
+// Block sides of the second pass of the split forward transform in its full-tile form (for
+// one block pair (I <= J) of an item: X = (A + A^T) / 2 / s_prod in FP64 from the FP32
+// product A, Y = F o X off the diagonal and Y_ii = -w_i X_ii, split at the Y scale into
+// block (I, J) and its mirror; fermi_symmetrize_chunks and fermi_symmetrize_v8 in
+// kk_fused.hpp). Small handles: 32 x 32 blocks of 256 threads, 4 elements per thread (64 x 64
+// blocks: 24 instead of 14 us at Nb = 1152). Large handles and split batches: 64 x 64 blocks
+// of 512 threads, 8 elements per thread, whose 256-byte row reads and 128-byte row writes use
+// HBM better than the 128- and 64-byte segments of 32 x 32 blocks.
 constexpr int SYM_B = 32;
 #ifndef KK_SYM_B_LARGE
 #define KK_SYM_B_LARGE 64
 #endif
 constexpr int SYM_B_LARGE = KK_SYM_B_LARGE;
 constexpr int SYM_T_LARGE = SYM_B_LARGE >= 64 ? 512 : 256;
-template <int B = SYM_B, int T = 256, bool BF16 = false, int NP = 2>
-__device__ __forceinline__ void fermi_symmetrize_dev(const MixedItem& it, const int n, const double beta,
-                                                     const int pair) {
-  static_assert(T % B == 0 && B % (T / B) == 0, "thread mapping");
-  static_assert(NP == 2 || NP == 3, "two or three pieces");
-  const int nblk = n / B;
-  int I = 0, rem = pair;
-  while (rem >= nblk - I) {
-    rem -= nblk - I;
-    ++I;
-  }
-  const int J = I + rem;
-  __shared__ float At[B][B + 1];                   // block (J, I) of A
-  __shared__ _Float16 Tp[NP][B][B + 2];            // Y pieces of block (I, J), transposed
-  const int tx = threadIdx.x % B, ty = threadIdx.x / B;
-  constexpr int RS = T / B;
-  for (int r = ty; r < B; r += RS) At[r][tx] = it.x32[(size_t)(J * B + r) * n + I * B + tx];
-  __syncthreads();
-  const double inv = it.sc[0], sy = it.sc[1];
-  const int c = J * B + tx;
-  const double en = it.eps[c], fn = it.f[c], fcn = it.fc[c];
-  for (int r = ty; r < B; r += RS) {
-    const int m = I * B + r;
-    const double x = 0.5 * inv * ((double)it.x32[(size_t)m * n + c] + (double)At[tx][r]);
-    double y;
-    if (m == c) {
-      it.xdiag[m] = x;
-      y = -it.w[m] * x * sy;
-    } else {
-      y = fermi_divided_difference(it.eps[m], it.f[m], it.fc[m], en, fn, fcn, beta) * x * sy;
-    }
-    _Float16 pc[NP];
-    split_pieces<BF16, NP>(y, pc);
-    it.yh[(size_t)m * n + c] = pc[0];
-    it.yl[(size_t)m * n + c] = pc[1];
-    if constexpr (NP == 3) it.yr[(size_t)m * n + c] = pc[2];
-#pragma unroll
-    for (int q = 0; q < NP; ++q) Tp[q][tx][r] = pc[q];
-  }
-  if (I == J) return;  // a diagonal block is symmetric by construction
-  __syncthreads();
-  for (int r = ty; r < B; r += RS) {
-    const size_t o = (size_t)(J * B + r) * n + I * B + tx;
-    it.yh[o] = Tp[0][r][tx];
-    it.yl[o] = Tp[1][r][tx];
-    if constexpr (NP == 3) it.yr[o] = Tp[2][r][tx];
-  }
-}
-
-// Single system: blockIdx.x = block pair, blockIdx.y = item.
-template <int B, int T, bool BF16 = false, int NP = 2>
-__global__ __launch_bounds__(T) void fermi_symmetrize(const MixedArgs args) {
-  if (args.stop != nullptr && *args.stop != 0) return;
-  fermi_symmetrize_dev<B, T, BF16, NP>(args.item[blockIdx.y], args.n, args.beta, blockIdx.x);
-}
 
 using MCfg128x128 = MixedCfg<128, 128, 32, 2, 2, 2>;
 using MCfg128x128f8 = MixedCfg<128, 128, 32, 2, 2, 2, 8>;
